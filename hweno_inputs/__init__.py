@@ -1,0 +1,331 @@
+"""Seeded synthetic initial states for the L-HWENO hot path.
+
+This module is shared by the CPU oracle, the tests and the benchmark.  It holds
+no arithmetic of the numerical method itself: it only samples initial data on a
+uniform cell-centred grid (point values of the solution and of its first
+derivatives), converts primitive Euler variables to conserved ones and records
+the grid geometry.
+
+State layout (all generators): a float64 numpy array ``S[nf, ny, nx]``, x
+fastest, ``ny == 1`` in one dimension.  The fields are the m conserved
+components U, then their x-derivatives U_x, then (2D only) their
+y-derivatives U_y, so ``nf = m * (1 + dim)``.  Derivatives of discontinuous
+data are zero (pointwise derivative of piecewise-constant data); derivatives of
+smooth data are the analytic ones.
+
+Random numbers come from ``numpy.random.Generator(PCG64(seed))``.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+GAMMA_GAS = 1.4
+
+PERIODIC = 0
+OUTFLOW = 1
+
+
+@dataclass
+class Workload:
+    """One initial state plus the geometry and physics it belongs to."""
+
+    S: np.ndarray            # [nf, ny, nx] float64
+    dim: int                 # 1 or 2
+    physics: str             # "linadv" | "burgers" | "euler"
+    dx: float
+    dy: float
+    bc_x: int
+    bc_y: int
+    lo: tuple = (0.0, 0.0)
+    hi: tuple = (1.0, 1.0)
+    gamma_gas: float = GAMMA_GAS
+    adv_speed: tuple = (1.0, 1.0)
+    name: str = ""
+    info: dict = field(default_factory=dict)
+
+    @property
+    def nx(self) -> int:
+        return self.S.shape[2]
+
+    @property
+    def ny(self) -> int:
+        return self.S.shape[1]
+
+    @property
+    def m(self) -> int:
+        return self.S.shape[0] // (1 + self.dim)
+
+
+def centers(n: int, lo: float, hi: float) -> np.ndarray:
+    """Cell centres x_i = lo + (i + 1/2) dx of n uniform cells on [lo, hi]."""
+    dx = (hi - lo) / n
+    return lo + (np.arange(n, dtype=np.float64) + 0.5) * dx
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+# ---------------------------------------------------------------------------
+# primitive -> conserved (definition of the Euler state, not of the scheme)
+# ---------------------------------------------------------------------------
+
+def conserved_1d(rho, u, p, gamma=GAMMA_GAS):
+    return np.stack([rho, rho * u, p / (gamma - 1.0) + 0.5 * rho * u * u])
+
+
+def conserved_2d(rho, u, v, p, gamma=GAMMA_GAS):
+    return np.stack([rho, rho * u, rho * v,
+                     p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+# ---------------------------------------------------------------------------
+# scalar problems
+# ---------------------------------------------------------------------------
+
+def scalar_sine_1d(n: int, physics: str = "linadv", lo=0.0, hi=2.0,
+                   a: float = 1.0) -> Workload:
+    """u0 = 0.5 + sin(pi x) on [lo, hi] periodic; v0 = pi cos(pi x)."""
+    x = centers(n, lo, hi)
+    S = np.zeros((2, 1, n))
+    S[0, 0] = 0.5 + np.sin(np.pi * x)
+    S[1, 0] = np.pi * np.cos(np.pi * x)
+    return Workload(S, 1, physics, (hi - lo) / n, 1.0, PERIODIC, PERIODIC,
+                    (lo, 0.0), (hi, 1.0), adv_speed=(a, 0.0),
+                    name=f"{physics}1d_sine_{n}")
+
+
+def scalar_sine_2d(nx: int, ny: int, physics: str = "burgers", lo=0.0, hi=4.0,
+                   a=(1.0, 1.0)) -> Workload:
+    """u0 = 0.5 + sin(pi (x + y) / 2) on [lo, hi]^2 periodic, with derivatives."""
+    x = centers(nx, lo, hi)[None, :]
+    y = centers(ny, lo, hi)[:, None]
+    arg = np.pi * (x + y) / 2.0
+    S = np.zeros((3, ny, nx))
+    S[0] = 0.5 + np.sin(arg)
+    S[1] = 0.5 * np.pi * np.cos(arg)
+    S[2] = 0.5 * np.pi * np.cos(arg)
+    return Workload(S, 2, physics, (hi - lo) / nx, (hi - lo) / ny, PERIODIC,
+                    PERIODIC, (lo, lo), (hi, hi), adv_speed=tuple(a),
+                    name=f"{physics}2d_sine_{nx}x{ny}")
+
+
+def scalar_random_2d(nx: int, ny: int, seed: int, physics="linadv",
+                     a=(1.0, -0.5)) -> Workload:
+    """Rough random scalar data (values and derivatives U[-1, 1]) on [0,1]^2."""
+    g = rng(seed)
+    S = g.uniform(-1.0, 1.0, size=(3, ny, nx))
+    return Workload(S, 2, physics, 1.0 / nx, 1.0 / ny, PERIODIC, PERIODIC,
+                    adv_speed=tuple(a), name=f"{physics}2d_random_{nx}x{ny}_s{seed}")
+
+
+def scalar_random_1d(n: int, seed: int, physics="linadv", a=1.0) -> Workload:
+    g = rng(seed)
+    S = g.uniform(-1.0, 1.0, size=(2, 1, n))
+    return Workload(S, 1, physics, 1.0 / n, 1.0, PERIODIC, PERIODIC,
+                    adv_speed=(a, 0.0), name=f"{physics}1d_random_{n}_s{seed}")
+
+
+# ---------------------------------------------------------------------------
+# 1D Euler
+# ---------------------------------------------------------------------------
+
+def euler1d_smooth(n: int, lo=0.0, hi=2.0, amp=0.2) -> Workload:
+    """Density wave rho = 1 + amp sin(pi x), u = 1, p = 1 on [lo, hi] periodic."""
+    x = centers(n, lo, hi)
+    rho = 1.0 + amp * np.sin(np.pi * x)
+    rho_x = amp * np.pi * np.cos(np.pi * x)
+    u = np.ones_like(x)
+    p = np.ones_like(x)
+    U = conserved_1d(rho, u, p)
+    # u and p constant: m_x = rho_x, E_x = rho_x / 2
+    D = np.stack([rho_x, rho_x, 0.5 * rho_x])
+    S = np.concatenate([U, D])[:, None, :]
+    return Workload(S, 1, "euler", (hi - lo) / n, 1.0, PERIODIC, PERIODIC,
+                    (lo, 0.0), (hi, 1.0), name=f"euler1d_smooth_{n}")
+
+
+def euler1d_piecewise(n: int, seed: int, lo=0.0, hi=2.0) -> Workload:
+    """Piecewise-constant data with k ~ U{1..5} jumps at sorted uniform points.
+
+    Each of the k+1 pieces draws rho ~ U[0.1, 2], u ~ U[-1, 1], p ~ U[0.1, 5];
+    derivatives are zero.  Periodic, so the seam is one more jump unless the
+    end states agree.
+    """
+    g = rng(seed)
+    k = int(g.integers(1, 6))
+    cuts = np.sort(g.uniform(lo, hi, size=k))
+    rho = g.uniform(0.1, 2.0, size=k + 1)
+    u = g.uniform(-1.0, 1.0, size=k + 1)
+    p = g.uniform(0.1, 5.0, size=k + 1)
+    x = centers(n, lo, hi)
+    piece = np.searchsorted(cuts, x)
+    U = conserved_1d(rho[piece], u[piece], p[piece])
+    S = np.concatenate([U, np.zeros_like(U)])[:, None, :]
+    return Workload(S, 1, "euler", (hi - lo) / n, 1.0, PERIODIC, PERIODIC,
+                    (lo, 0.0), (hi, 1.0), name=f"euler1d_piecewise_{n}_s{seed}",
+                    info={"jumps": k})
+
+
+# ---------------------------------------------------------------------------
+# 2D Euler
+# ---------------------------------------------------------------------------
+
+def euler2d_quadrants(nx: int, ny: int, seed: int, bc=OUTFLOW) -> Workload:
+    """Four constant quadrants of [0,1]^2 split at x = 1/2, y = 1/2.
+
+    Each quadrant draws rho ~ U[0.1, 2], u, v ~ U[-1, 1], p ~ U[0.1, 2];
+    derivatives are zero; outflow boundaries by default.
+    """
+    g = rng(seed)
+    rho = g.uniform(0.1, 2.0, size=4)
+    u = g.uniform(-1.0, 1.0, size=4)
+    v = g.uniform(-1.0, 1.0, size=4)
+    p = g.uniform(0.1, 2.0, size=4)
+    x = centers(nx, 0.0, 1.0)[None, :]
+    y = centers(ny, 0.0, 1.0)[:, None]
+    q = (x >= 0.5).astype(np.int64) + 2 * (y >= 0.5).astype(np.int64)
+    U = conserved_2d(rho[q], u[q], v[q], p[q])
+    S = np.concatenate([U, np.zeros_like(U), np.zeros_like(U)])
+    return Workload(S, 2, "euler", 1.0 / nx, 1.0 / ny, bc, bc,
+                    name=f"euler2d_quadrants_{nx}x{ny}_s{seed}")
+
+
+def euler2d_wave(nx: int, ny: int, lo=0.0, hi=2.0, amp=0.2, k=1.0,
+                 phase=0.0, u0=1.0, v0=1.0, p0=1.0) -> Workload:
+    """rho = 1 + amp sin(k pi (x + y) + phase), u = u0, v = v0, p = p0, periodic.
+
+    With k = 1 on [0, 2]^2 this is the 2D density wave; with k = 2 on
+    [0, 1]^2 it is the smooth instance type of the batched workload.
+    """
+    x = centers(nx, lo, hi)[None, :]
+    y = centers(ny, lo, hi)[:, None]
+    arg = k * np.pi * (x + y) + phase
+    rho = 1.0 + amp * np.sin(arg) + 0.0 * (x + y)
+    drho = amp * k * np.pi * np.cos(arg) + 0.0 * (x + y)
+    one = np.ones_like(rho)
+    U = conserved_2d(rho, u0 * one, v0 * one, p0 * one)
+    # velocities and pressure constant: m_d = u0 rho_d, n_d = v0 rho_d,
+    # E_d = (u0^2 + v0^2)/2 rho_d, and rho_x = rho_y = drho
+    D = np.stack([drho, u0 * drho, v0 * drho, 0.5 * (u0 * u0 + v0 * v0) * drho])
+    S = np.concatenate([U, D, D])
+    return Workload(S, 2, "euler", (hi - lo) / nx, (hi - lo) / ny, PERIODIC,
+                    PERIODIC, (lo, lo), (hi, hi), name=f"euler2d_wave_{nx}x{ny}")
+
+
+def euler2d_random_smooth(nx: int, ny: int, seed: int, bc=PERIODIC) -> Workload:
+    """Smooth but non-trivial periodic 2D Euler data on [0,1]^2 (all fields vary)."""
+    g = rng(seed)
+    x = centers(nx, 0.0, 1.0)[None, :]
+    y = centers(ny, 0.0, 1.0)[:, None]
+    tp = 2.0 * np.pi
+
+    def wave(base, amp):
+        kx, ky = g.integers(1, 3, size=2)
+        ph = g.uniform(0.0, tp)
+        arg = tp * (kx * x + ky * y) + ph
+        return (base + amp * np.sin(arg),
+                amp * tp * kx * np.cos(arg), amp * tp * ky * np.cos(arg))
+
+    r, rx, ry = wave(1.0, 0.2)
+    u, ux, uy = wave(0.3, 0.3)
+    v, vx, vy = wave(-0.2, 0.3)
+    p, px, py = wave(1.0, 0.2)
+    gm1 = GAMMA_GAS - 1.0
+    U = conserved_2d(r, u, v, p)
+
+    def dcons(rd, ud, vd, pd):
+        return np.stack([rd, rd * u + r * ud, rd * v + r * vd,
+                         pd / gm1 + 0.5 * rd * (u * u + v * v) + r * (u * ud + v * vd)])
+
+    S = np.concatenate([U, dcons(rx, ux, vx, px), dcons(ry, uy, vy, py)])
+    return Workload(S, 2, "euler", 1.0 / nx, 1.0 / ny, bc, bc,
+                    name=f"euler2d_rsmooth_{nx}x{ny}_s{seed}")
+
+
+def euler2d_rough(nx: int, ny: int, seed: int, bc=OUTFLOW) -> Workload:
+    """Admissible random cell data with random derivatives (stress input)."""
+    g = rng(seed)
+    rho = g.uniform(0.2, 2.0, size=(ny, nx))
+    u = g.uniform(-1.0, 1.0, size=(ny, nx))
+    v = g.uniform(-1.0, 1.0, size=(ny, nx))
+    p = g.uniform(0.5, 2.0, size=(ny, nx))
+    U = conserved_2d(rho, u, v, p)
+    D1 = g.uniform(-1.0, 1.0, size=U.shape) * nx * 0.05
+    D2 = g.uniform(-1.0, 1.0, size=U.shape) * ny * 0.05
+    S = np.concatenate([U, D1, D2])
+    return Workload(S, 2, "euler", 1.0 / nx, 1.0 / ny, bc, bc,
+                    name=f"euler2d_rough_{nx}x{ny}_s{seed}")
+
+
+# ---------------------------------------------------------------------------
+# batched uneven 2D Euler instances
+# ---------------------------------------------------------------------------
+
+def batched_instances(n_inst: int, seed: int, side_lo=64, side_hi=512,
+                      sizes: Optional[List[tuple]] = None) -> List[Workload]:
+    """Independent 2D Euler instances on [0,1]^2 with uneven grids.
+
+    Sides nx, ny ~ U{side_lo..side_hi} independently (unless ``sizes`` is
+    given).  Instance type ~ Bernoulli(1/2): four-quadrant data (outflow) or
+    a smooth wave rho = 1 + A sin(2 pi (x + y) + phi), A ~ U[0.05, 0.2],
+    phi ~ U[0, 2 pi), u = v = p = 1 (periodic).
+    """
+    g = rng(seed)
+    out = []
+    for k in range(n_inst):
+        if sizes is None:
+            nx = int(g.integers(side_lo, side_hi + 1))
+            ny = int(g.integers(side_lo, side_hi + 1))
+        else:
+            nx, ny = sizes[k]
+        if g.uniform() < 0.5:
+            w = euler2d_quadrants(nx, ny, seed=int(g.integers(0, 2**31)))
+        else:
+            amp = float(g.uniform(0.05, 0.2))
+            ph = float(g.uniform(0.0, 2.0 * np.pi))
+            w = euler2d_wave(nx, ny, lo=0.0, hi=1.0, amp=amp, k=2.0, phase=ph)
+        w.name = f"inst{k}_" + w.name
+        out.append(w)
+    return out
+
+
+# ---------------------------------------------------------------------------
+# adjoint workload
+# ---------------------------------------------------------------------------
+
+def adjoint_pair(n: int, seed: int):
+    """Initial smooth state U0 and a seed-perturbed state whose rollout is the target.
+
+    U0: rho = 1 + 0.2 sin(2 pi (x + y)), u = v = p = 1 on [0,1]^2 periodic.
+    Perturbation of the density: 0.02 sum_k a_k sin(2 pi (kx x + ky y) + phi_k),
+    k = 1..3, a_k ~ U[0.5, 1], (kx, ky) ~ U{1..3}^2, phi_k ~ U[0, 2 pi).
+    """
+    g = rng(seed)
+    base = euler2d_wave(n, n, lo=0.0, hi=1.0, amp=0.2, k=2.0)
+    x = centers(n, 0.0, 1.0)[None, :]
+    y = centers(n, 0.0, 1.0)[:, None]
+    tp = 2.0 * np.pi
+    drho = np.zeros((n, n))
+    drho_x = np.zeros((n, n))
+    drho_y = np.zeros((n, n))
+    for _ in range(3):
+        a = g.uniform(0.5, 1.0)
+        kx, ky = g.integers(1, 4, size=2)
+        ph = g.uniform(0.0, tp)
+        arg = tp * (kx * x + ky * y) + ph
+        drho += 0.02 * a * np.sin(arg)
+        drho_x += 0.02 * a * tp * kx * np.cos(arg)
+        drho_y += 0.02 * a * tp * ky * np.cos(arg)
+    pert = base.S.copy()
+    # u = v = 1 and p = 1 stay: m = rho, n = rho, E = 1/(g-1) + rho
+    for c, s in ((0, 1.0), (1, 1.0), (2, 1.0), (3, 1.0)):
+        pert[c] += s * drho
+        pert[4 + c] += s * drho_x
+        pert[8 + c] += s * drho_y
+    target = Workload(pert, 2, "euler", base.dx, base.dy, PERIODIC, PERIODIC,
+                      base.lo, base.hi, name=f"adjoint_target_{n}_s{seed}")
+    return base, target

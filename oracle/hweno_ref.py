@@ -1,0 +1,532 @@
+"""Plain, slow FP64 CPU oracle of the L-HWENO hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import or run this module.  It shares no code with the
+HIP library and imports nothing from the product package.
+
+Source: Zhang & Zhao, "A fifth-order finite difference HWENO scheme combined
+with limiter for hyperbolic conservation laws" (arXiv 2207.05258).  Every
+function names the passage it follows.  Tensors are torch float64 on the CPU,
+so that torch autograd of this forward (with the wave speeds and the time step
+held fixed) serves as the oracle adjoint.
+
+State layout: ``S[nf, ny, nx]`` with the m conserved components U, then U_x,
+then (2D) U_y; ``ny == 1`` in one dimension.
+
+Readings of passages the paper leaves open (each listed in the design notes):
+  * beta_2 of the quadratic on {x_i, x_{i+1}} is taken from its definition
+    (eq. GHYZ); the printed explicit form has f_{i-1} where the definition
+    gives f_{i+1}.
+  * The "-" reconstruction is the mirror image of the "+" one about
+    x_{i+1/2}: indices reflected, derivative data negated, and the returned
+    derivative negated.
+  * The global Lax-Friedrichs speed is one scalar per direction, the maximum
+    of |f'(u)| (Euler: |u_d| + c) over the grid of the state the operator is
+    evaluated on, recomputed at every Runge-Kutta stage.
+  * Characteristic decomposition uses the Roe average of the two cells next
+    to the interface; right eigenvectors scaled as documented in
+    ``Euler.right_eigenvectors``; L = R^{-1} by a numerical inverse; both the
+    split fluxes and the split derivative fluxes are projected.
+  * The limiter acts component by component on the conserved variables:
+    U_x along x, U_y along y.
+  * The mixed fluxes use the step sizes of eq. (ode2H): the y-differences of
+    xi-hat are divided by dy and the x-differences of eta-hat by dx.
+  * Outflow boundaries copy the nearest interior value of every field.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import torch
+
+DTYPE = torch.float64
+
+PERIODIC = 0
+OUTFLOW = 1
+
+
+@dataclass
+class Problem:
+    """Parameters of one discretised problem (Section 3 defaults)."""
+
+    dim: int = 1
+    physics: str = "linadv"          # "linadv" | "burgers" | "euler"
+    dx: float = 1.0
+    dy: float = 1.0
+    bc_x: int = PERIODIC
+    bc_y: int = PERIODIC
+    gamma_gas: float = 1.4
+    adv_speed: Tuple[float, float] = (1.0, 1.0)
+    lin_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)   # gamma_0..2
+    lim_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)   # d_0..2
+    eps: float = 1e-6
+    cfl: float = 0.6
+    characteristic: bool = True
+    limiter_on: bool = True
+    # test-only switches: force the nonlinear weights to the linear ones
+    linear_recon: bool = False
+    linear_limiter: bool = False
+
+    @property
+    def m(self) -> int:
+        if self.physics == "euler":
+            return 3 if self.dim == 1 else 4
+        return 1
+
+    @property
+    def nf(self) -> int:
+        return self.m * (1 + self.dim)
+
+
+def problem_from_workload(w, **kw) -> Problem:
+    return Problem(dim=w.dim, physics=w.physics, dx=w.dx, dy=w.dy,
+                   bc_x=w.bc_x, bc_y=w.bc_y, gamma_gas=w.gamma_gas,
+                   adv_speed=tuple(w.adv_speed), **kw)
+
+
+# ===========================================================================
+# Section 2.1: Hermite reconstruction of the "+" flux at x_{i+1/2}
+# Data: f_{i-1}, f_i, f_{i+1} (split point fluxes) and H_l = dx * h_l.
+# ===========================================================================
+
+def hermite_values(fm, f0, fp, Hm, H0, Hp):
+    """p_0, p_1, p_2 at x_{i+1/2} (Section 2.1, the values following eq. HWEp12)."""
+    p0 = 11.0 / 60.0 * fm + 19.0 / 30.0 * f0 + 11.0 / 60.0 * fp \
+        + (Hm + 10.0 * H0 - Hp) / 20.0
+    p1 = fm / 6.0 + 5.0 / 6.0 * f0 + 2.0 / 3.0 * H0
+    p2 = 5.0 / 6.0 * f0 + fp / 6.0 + H0 / 3.0
+    return p0, p1, p2
+
+
+def quintic_coefficients(fm, f0, fp, Hm, H0, Hp):
+    """a_1..a_5 of p_0 in the scaled variable (x - x_i)/dx (Section 2.1)."""
+    a1 = 19.0 / 192.0 * Hm + 79.0 / 48.0 * H0 + 19.0 / 192.0 * Hp \
+        + 27.0 / 64.0 * (fm - fp)
+    a2 = 3.0 / 8.0 * Hm - 3.0 / 8.0 * Hp + 5.0 / 4.0 * (fm - 2.0 * f0 + fp)
+    a3 = -(11.0 / 24.0 * Hm + 17.0 / 6.0 * H0 + 11.0 / 24.0 * Hp) \
+        + 15.0 / 8.0 * (fp - fm)
+    a4 = 0.25 * Hp - 0.25 * Hm - 0.5 * (fm - 2.0 * f0 + fp)
+    a5 = 0.25 * Hm + H0 + 0.25 * Hp + 0.75 * (fm - fp)
+    return a1, a2, a3, a4, a5
+
+
+def smoothness_indicators(fm, f0, fp, Hm, H0, Hp):
+    """beta_0, beta_1, beta_2 (eq. GHYZ / GHYZP; beta_2 from its definition)."""
+    a1, a2, a3, a4, a5 = quintic_coefficients(fm, f0, fp, Hm, H0, Hp)
+    b0 = (a1 + a3 / 4.0 + a5 / 16.0) ** 2 \
+        + 13.0 / 3.0 * (a2 + 63.0 / 130.0 * a4) ** 2 \
+        + 781.0 / 20.0 * (a3 + 8825.0 / 10934.0 * a5) ** 2 \
+        + 1421461.0 / 2275.0 * a4 ** 2 \
+        + 21520059541.0 / 1377684.0 * a5 ** 2
+    b1 = H0 ** 2 + 13.0 / 3.0 * (H0 - f0 + fm) ** 2
+    b2 = H0 ** 2 + 13.0 / 3.0 * (H0 + f0 - fp) ** 2
+    return b0, b1, b2
+
+
+def nonlinear_weights(b0, b1, b2, lin, eps):
+    """omega_l from tau (eq. tau-fh) and the normalised bar-omega (Section 2.1)."""
+    tau = 0.25 * ((b0 - b1).abs() + (b0 - b2).abs()) ** 2
+    w0 = lin[0] * (1.0 + tau / (b0 + eps))
+    w1 = lin[1] * (1.0 + tau / (b1 + eps))
+    w2 = lin[2] * (1.0 + tau / (b2 + eps))
+    s = w0 + w1 + w2
+    return w0 / s, w1 / s, w2 / s
+
+
+def hweno_plus(fm, f0, fp, Hm, H0, Hp, lin, eps, linear=False):
+    """Nonlinear HWENO value f-hat^+_{i+1/2} (Section 2.1, final combination).
+
+    With ``linear=True`` the nonlinear weights are replaced by the linear
+    ones, which reduces the combination to p_0 (test switch).
+    """
+    p0, p1, p2 = hermite_values(fm, f0, fp, Hm, H0, Hp)
+    if linear:
+        w0, w1, w2 = lin
+    else:
+        b0, b1, b2 = smoothness_indicators(fm, f0, fp, Hm, H0, Hp)
+        w0, w1, w2 = nonlinear_weights(b0, b1, b2, lin, eps)
+    g0, g1, g2 = lin
+    return w0 * (p0 / g0 - g1 / g0 * p1 - g2 / g0 * p2) + w1 * p1 + w2 * p2
+
+
+def quintic_derivative(fm, f0, fp, hm, h0, hp, dx):
+    """p_0'(x_{i+1/2}) (Section 2.1): the linear derivative-equation flux h-hat^+."""
+    return (fm - 8.0 * f0 + 7.0 * fp) / (4.0 * dx) + (hm - 2.0 * h0 - 5.0 * hp) / 12.0
+
+
+def hweno_minus(f_i, f_ip1, f_ip2, H_i, H_ip1, H_ip2, lin, eps, linear=False):
+    """f-hat^-_{i+1/2}: the "+" procedure mirrored about x_{i+1/2} (Section 2.1).
+
+    Reflection maps cell i+1 to the centre, i+2 to the upwind side and i to
+    the downwind side; derivative data change sign under the reflection.
+    """
+    return hweno_plus(f_ip2, f_ip1, f_i, -H_ip2, -H_ip1, -H_i, lin, eps, linear)
+
+
+def quintic_derivative_minus(f_i, f_ip1, f_ip2, h_i, h_ip1, h_ip2, dx):
+    """h-hat^-_{i+1/2}: mirrored p_0' (derivative of the reflected polynomial negated)."""
+    return -quintic_derivative(f_ip2, f_ip1, f_i, -h_ip2, -h_ip1, -h_i, dx)
+
+
+# ===========================================================================
+# Section 2.2: HWENO limiter for the derivative at x_i
+# Inputs u_{i-1}, u_i, u_{i+1}, v_{i-1}, v_{i+1}; v_i is not used.
+# ===========================================================================
+
+def limiter_candidates(um, u0, up, vm, vp, dx):
+    """q_0'(x_i), q_1'(x_i), q_2'(x_i) (Section 2.2)."""
+    q0 = 3.0 / (4.0 * dx) * (up - um) - 0.25 * (vm + vp)
+    q1 = (u0 - um) / dx
+    q2 = (up - u0) / dx
+    return q0, q1, q2
+
+
+def limiter_smoothness(um, u0, up, vm, vp, dx):
+    """beta_0..2 of q_0, q_1, q_2 (eq. GHYZ-q and its explicit form)."""
+    a1 = -dx / 4.0 * (vm + vp) + 0.75 * (up - um)
+    a2 = dx / 4.0 * (vm - vp) + um - 2.0 * u0 + up
+    a3 = dx / 4.0 * (vm + vp) + 0.25 * (um - up)
+    a4 = dx / 4.0 * (vp - vm) - 0.5 * (um - 2.0 * u0 + up)
+    b0 = (a1 + a3 / 4.0) ** 2 + 13.0 / 3.0 * (a2 + 63.0 / 130.0 * a4) ** 2 \
+        + 781.0 / 20.0 * a3 ** 2 + 1421461.0 / 2275.0 * a4 ** 2
+    b1 = (u0 - um) ** 2
+    b2 = (u0 - up) ** 2
+    return b0, b1, b2
+
+
+def limit_derivative(um, u0, up, vm, vp, dx, d, eps, linear=False):
+    """Modified derivative v-tilde_i (Section 2.2, final combination)."""
+    q0, q1, q2 = limiter_candidates(um, u0, up, vm, vp, dx)
+    if linear:
+        l0, l1, l2 = d
+    else:
+        b0, b1, b2 = limiter_smoothness(um, u0, up, vm, vp, dx)
+        l0, l1, l2 = nonlinear_weights(b0, b1, b2, d, eps)
+    d0, d1, d2 = d
+    return l0 * (q0 / d0 - d1 / d0 * q1 - d2 / d0 * q2) + l1 * q1 + l2 * q2
+
+
+# ===========================================================================
+# Physics: fluxes, chain-rule derivative fluxes, wave speeds, eigenvectors
+# (eq. EQ1 / EQ3 definitions of h, xi, eta, theta; eqs. euler1 / euler2)
+# Component index is the LAST axis in this section.
+# ===========================================================================
+
+class Scalar:
+    """f(u) = a_x u, g(u) = a_y u (linear advection) or u^2/2 (Burgers)."""
+
+    def __init__(self, prob: Problem):
+        self.prob = prob
+
+    def flux(self, U, d):
+        if self.prob.physics == "linadv":
+            return self.prob.adv_speed[d] * U
+        return 0.5 * U * U
+
+    def jvp(self, U, D, d):
+        """f'(u) D: h = f'(u) v, xi = g'(u) v, eta = f'(u) w, theta = g'(u) w."""
+        if self.prob.physics == "linadv":
+            return self.prob.adv_speed[d] * D
+        return U * D
+
+    def speed(self, U, d):
+        if self.prob.physics == "linadv":
+            return torch.full_like(U[..., 0], abs(self.prob.adv_speed[d]))
+        return U[..., 0].abs()
+
+    def right_eigenvectors(self, UL, UR, d):
+        return torch.ones(UL.shape[:-1] + (1, 1), dtype=DTYPE)
+
+
+class Euler:
+    """Compressible Euler, E = p/(gamma-1) + rho |vel|^2 / 2 (eqs. euler1, euler2)."""
+
+    def __init__(self, prob: Problem):
+        self.g = prob.gamma_gas
+        self.dim = prob.dim
+
+    def _prim(self, U):
+        rho = U[..., 0]
+        u = U[..., 1] / rho
+        if self.dim == 1:
+            v = torch.zeros_like(u)
+            E = U[..., 2]
+        else:
+            v = U[..., 2] / rho
+            E = U[..., 3]
+        p = (self.g - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+        return rho, u, v, E, p
+
+    def flux(self, U, d):
+        rho, u, v, E, p = self._prim(U)
+        if self.dim == 1:
+            return torch.stack([rho * u, rho * u * u + p, u * (E + p)], -1)
+        if d == 0:
+            return torch.stack([rho * u, rho * u * u + p, rho * u * v, u * (E + p)], -1)
+        return torch.stack([rho * v, rho * u * v, rho * v * v + p, v * (E + p)], -1)
+
+    def jvp(self, U, D, d):
+        """dF_d/dU . D by the chain rule (D = derivative of U along some direction)."""
+        rho, u, v, E, p = self._prim(U)
+        gm1 = self.g - 1.0
+        r_s = D[..., 0]
+        m_s = D[..., 1]
+        if self.dim == 1:
+            n_s = torch.zeros_like(r_s)
+            E_s = D[..., 2]
+        else:
+            n_s = D[..., 2]
+            E_s = D[..., 3]
+        u_s = (m_s - u * r_s) / rho
+        v_s = (n_s - v * r_s) / rho
+        p_s = gm1 * (E_s - u * m_s - v * n_s + 0.5 * (u * u + v * v) * r_s)
+        m = rho * u
+        n = rho * v
+        if self.dim == 1:
+            return torch.stack([m_s, m_s * u + m * u_s + p_s,
+                                u_s * (E + p) + u * (E_s + p_s)], -1)
+        if d == 0:
+            return torch.stack([m_s, m_s * u + m * u_s + p_s, m_s * v + m * v_s,
+                                u_s * (E + p) + u * (E_s + p_s)], -1)
+        return torch.stack([n_s, n_s * u + n * u_s, n_s * v + n * v_s + p_s,
+                            v_s * (E + p) + v * (E_s + p_s)], -1)
+
+    def speed(self, U, d):
+        rho, u, v, E, p = self._prim(U)
+        c = torch.sqrt(self.g * p / rho)
+        return (u if d == 0 else v).abs() + c
+
+    def roe_average(self, UL, UR):
+        rL, uL, vL, EL, pL = self._prim(UL)
+        rR, uR, vR, ER, pR = self._prim(UR)
+        sL = torch.sqrt(rL)
+        sR = torch.sqrt(rR)
+        HL = (EL + pL) / rL
+        HR = (ER + pR) / rR
+        u = (sL * uL + sR * uR) / (sL + sR)
+        v = (sL * vL + sR * vR) / (sL + sR)
+        H = (sL * HL + sR * HR) / (sL + sR)
+        c = torch.sqrt((self.g - 1.0) * (H - 0.5 * (u * u + v * v)))
+        return u, v, H, c
+
+    def right_eigenvectors(self, UL, UR, d):
+        """Columns = right eigenvectors of dF_d/dU at the Roe average.
+
+        x: (1, u-c, v, H-uc), (1, u, v, q^2/2), (0, 0, 1, v), (1, u+c, v, H+uc);
+        y: (1, u, v-c, H-vc), (1, u, v, q^2/2), (0, 1, 0, u), (1, u, v+c, H+vc);
+        1D drops the v rows/columns.
+        """
+        u, v, H, c = self.roe_average(UL, UR)
+        one = torch.ones_like(u)
+        zero = torch.zeros_like(u)
+        q2 = 0.5 * (u * u + v * v)
+        if self.dim == 1:
+            cols = [torch.stack([one, u - c, H - u * c], -1),
+                    torch.stack([one, u, q2], -1),
+                    torch.stack([one, u + c, H + u * c], -1)]
+        elif d == 0:
+            cols = [torch.stack([one, u - c, v, H - u * c], -1),
+                    torch.stack([one, u, v, q2], -1),
+                    torch.stack([zero, zero, one, v], -1),
+                    torch.stack([one, u + c, v, H + u * c], -1)]
+        else:
+            cols = [torch.stack([one, u, v - c, H - v * c], -1),
+                    torch.stack([one, u, v, q2], -1),
+                    torch.stack([zero, one, zero, u], -1),
+                    torch.stack([one, u, v + c, H + v * c], -1)]
+        return torch.stack(cols, -1)
+
+
+def physics_of(prob: Problem):
+    return Euler(prob) if prob.physics == "euler" else Scalar(prob)
+
+
+# ===========================================================================
+# Grid helpers
+# ===========================================================================
+
+def _pad(A, axis, bc, width=2):
+    """Ghost cells along ``axis``: periodic wrap or copy of the nearest interior value."""
+    n = A.shape[axis]
+    if bc == PERIODIC:
+        idx = torch.arange(-width, n + width) % n
+    else:
+        idx = torch.clamp(torch.arange(-width, n + width), 0, n - 1)
+    return A.index_select(axis, idx)
+
+
+def _split(S, prob):
+    m = prob.m
+    U = S[:m]
+    V = S[m:2 * m]
+    W = S[2 * m:3 * m] if prob.dim == 2 else None
+    return U, V, W
+
+
+def max_speeds(S, prob) -> Tuple[float, float]:
+    """alpha_d = max over the grid of |f_d'(u)| (global LF speed, Section 2.1)."""
+    phys = physics_of(prob)
+    U = _split(S, prob)[0].movedim(0, -1)
+    ax = float(phys.speed(U, 0).max())
+    ay = float(phys.speed(U, 1).max()) if prob.dim == 2 else 0.0
+    return ax, ay
+
+
+# ===========================================================================
+# Semi-discrete operator (eqs. odeH, ode2H; Remarks 2.1 and 2.2)
+# ===========================================================================
+
+def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
+    """Interface fluxes along direction d for interfaces -1/2 .. n-1/2.
+
+    U, Dn (derivative along d), Dt (derivative across d, or None): [m, ny, nx].
+    Returns (f-hat, h-hat, mixed-hat), each with the component axis first.
+    """
+    phys = physics_of(prob)
+    axis = 2 if d == 0 else 1
+    bc = prob.bc_x if d == 0 else prob.bc_y
+    dd = prob.dx if d == 0 else prob.dy
+    n = U.shape[axis]
+    Up = _pad(U, axis, bc).movedim(0, -1)
+    Dnp = _pad(Dn, axis, bc).movedim(0, -1)
+    cax = axis - 1   # grid axis once the component axis has moved last
+
+    def at(A, k):    # stencil point i-1+k of the interfaces i+1/2, i = -1..n-1
+        return A.narrow(cax, k, n + 1)
+
+    F = phys.flux(Up, d)
+    AD = phys.jvp(Up, Dnp, d)
+
+    # global Lax-Friedrichs splitting (Section 2.1), conserved components
+    fP = [0.5 * (at(F, k) + alpha * at(Up, k)) for k in range(4)]
+    fM = [0.5 * (at(F, k) - alpha * at(Up, k)) for k in range(4)]
+    hP = [0.5 * (at(AD, k) + alpha * at(Dnp, k)) for k in range(4)]
+    hM = [0.5 * (at(AD, k) - alpha * at(Dnp, k)) for k in range(4)]
+
+    # nonlinear flux in local characteristic fields (Remarks 2.1 / 2.2)
+    if prob.characteristic and prob.m > 1:
+        R = phys.right_eigenvectors(at(Up, 1), at(Up, 2), d)
+        L = torch.linalg.inv(R)
+
+        def proj(X):
+            return (L @ X.unsqueeze(-1)).squeeze(-1)
+    else:
+        R = None
+
+        def proj(X):
+            return X
+    cfP = [proj(x) for x in fP]
+    cfM = [proj(x) for x in fM]
+    cHP = [dd * proj(x) for x in hP]
+    cHM = [dd * proj(x) for x in hM]
+    lin, eps, lr = prob.lin_w, prob.eps, prob.linear_recon
+    fhat_c = hweno_plus(cfP[0], cfP[1], cfP[2], cHP[0], cHP[1], cHP[2], lin, eps, lr) \
+        + hweno_minus(cfM[1], cfM[2], cfM[3], cHM[1], cHM[2], cHM[3], lin, eps, lr)
+    fhat = (R @ fhat_c.unsqueeze(-1)).squeeze(-1) if R is not None else fhat_c
+
+    # linear derivative-equation flux, component by component
+    hhat = quintic_derivative(fP[0], fP[1], fP[2], hP[0], hP[1], hP[2], dd) \
+        + quintic_derivative_minus(fM[1], fM[2], fM[3], hM[1], hM[2], hM[3], dd)
+
+    mixed = None
+    if Dt is not None:
+        Dtp = _pad(Dt, axis, bc).movedim(0, -1)
+        AT = phys.jvp(Up, Dtp, d)
+        # eq. (mixed): central four-point value, no splitting
+        mixed = (-at(AT, 0) + 7.0 * at(AT, 1) + 7.0 * at(AT, 2) - at(AT, 3)) / 12.0
+        mixed = mixed.movedim(-1, 0)
+    return fhat.movedim(-1, 0), hhat.movedim(-1, 0), mixed
+
+
+def _difference(Fh, axis, h):
+    n = Fh.shape[axis] - 1
+    return -(Fh.narrow(axis, 1, n) - Fh.narrow(axis, 0, n)) / h
+
+
+def rhs(S, prob: Problem, alpha: Optional[Tuple[float, float]] = None):
+    """Semi-discrete right-hand side L(S) (eqs. odeH and ode2H)."""
+    if alpha is None:
+        alpha = max_speeds(S, prob)
+    U, V, W = _split(S, prob)
+    fh, hh, eh = _direction_fluxes(U, V, W, prob, 0, alpha[0])
+    LU = _difference(fh, 2, prob.dx)
+    LV = _difference(hh, 2, prob.dx)
+    if prob.dim == 1:
+        return torch.cat([LU, LV])
+    LW = _difference(eh, 2, prob.dx)
+    gh, th, xh = _direction_fluxes(U, W, V, prob, 1, alpha[1])
+    LU = LU + _difference(gh, 1, prob.dy)
+    LW = LW + _difference(th, 1, prob.dy)
+    LV = LV + _difference(xh, 1, prob.dy)
+    return torch.cat([LU, LV, LW])
+
+
+def limited_derivatives(S, prob: Problem):
+    """Limited derivatives: U_x along x (and U_y along y) by Section 2.2."""
+    U, V, W = _split(S, prob)
+    d, eps, lin = prob.lim_w, prob.eps, prob.linear_limiter
+
+    def along(D, axis, bc, h):
+        n = U.shape[axis]
+        Up = _pad(U, axis, bc, 1)
+        Dp = _pad(D, axis, bc, 1)
+        return limit_derivative(Up.narrow(axis, 0, n), Up.narrow(axis, 1, n),
+                                Up.narrow(axis, 2, n), Dp.narrow(axis, 0, n),
+                                Dp.narrow(axis, 2, n), h, d, eps, lin)
+
+    out = [along(V, 2, prob.bc_x, prob.dx)]
+    if prob.dim == 2:
+        out.append(along(W, 1, prob.bc_y, prob.dy))
+    return torch.cat(out)
+
+
+def hat(S, prob: Problem):
+    """(U, limited derivatives), or S itself with the limiter switched off."""
+    if not prob.limiter_on:
+        return S
+    return torch.cat([S[:prob.m], limited_derivatives(S, prob)])
+
+
+def cfl_dt(alpha, prob: Problem) -> float:
+    """Time step from the CFL number: 1D cfl dx / a_x, 2D cfl / (a_x/dx + a_y/dy)."""
+    if prob.dim == 1:
+        return prob.cfl * prob.dx / alpha[0]
+    return prob.cfl / (alpha[0] / prob.dx + alpha[1] / prob.dy)
+
+
+def rk3_step(S, prob: Problem, dt: Optional[float] = None, alphas=None):
+    """One SSP-RK3 step with limited derivatives in the update only (Section 2.2).
+
+    ``alphas``: optional per-stage wave speeds (replay); otherwise each stage
+    computes them from its own state.  Returns (S^{n+1}, dt, alphas).
+    """
+    a = [None, None, None] if alphas is None else list(alphas)
+    a[0] = a[0] if a[0] is not None else max_speeds(S, prob)
+    if dt is None:
+        dt = cfl_dt(a[0], prob)
+    H0 = hat(S, prob)
+    S1 = H0 + dt * rhs(S, prob, a[0])
+    a[1] = a[1] if a[1] is not None else max_speeds(S1, prob)
+    S2 = 0.75 * H0 + 0.25 * (hat(S1, prob) + dt * rhs(S1, prob, a[1]))
+    a[2] = a[2] if a[2] is not None else max_speeds(S2, prob)
+    S3 = H0 / 3.0 + 2.0 / 3.0 * (hat(S2, prob) + dt * rhs(S2, prob, a[2]))
+    return S3, dt, a
+
+
+def run(S, prob: Problem, t_end: float, dt_rule=None, max_steps=10 ** 7):
+    """Advance to t_end; ``dt_rule(alpha) -> dt`` overrides the CFL rule; last step clipped."""
+    t = 0.0
+    steps = 0
+    while t < t_end - 1e-14 * max(1.0, t_end) and steps < max_steps:
+        a0 = max_speeds(S, prob)
+        dt = dt_rule(a0) if dt_rule is not None else cfl_dt(a0, prob)
+        dt = min(dt, t_end - t)
+        S, _, _ = rk3_step(S, prob, dt, [a0, None, None])
+        t += dt
+        steps += 1
+    return S, steps
+
+
+def as_tensor(S) -> torch.Tensor:
+    return torch.as_tensor(S, dtype=DTYPE)

@@ -1,0 +1,362 @@
+"""Pins of the oracle's semi-discrete operator, limiter use and time stepping.
+
+Checks against what the paper and the mathematics fix: chain-rule derivative
+fluxes against automatic differentiation of the flux, eigen-systems against the
+Jacobian, invariants (constant states, conservation, reflection and
+transposition symmetry, 1D/2D reduction), fifth-order truncation error on
+smooth data, and the L-HWENO error tables printed in Section 3.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import hweno_inputs as hi
+from oracle import hweno_ref as o
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _prob(w, **kw):
+    return o.problem_from_workload(w, **kw)
+
+
+def _S(w):
+    return o.as_tensor(w.S)
+
+
+# ---------------------------------------------------------------------------
+# physics
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("dim,d", [(1, 0), (2, 0), (2, 1)])
+def test_euler_jvp_is_derivative_of_flux(dim, d):
+    """A(U) D equals d/ds F(U + s D) (the definition of h, xi, eta, theta in eq. EQ3)."""
+    g = torch.Generator().manual_seed(5)
+    m = 3 if dim == 1 else 4
+    prob = o.Problem(dim=dim, physics="euler")
+    phys = o.Euler(prob)
+    rho = torch.rand(50, generator=g, dtype=torch.float64) + 0.5
+    vel = torch.rand(50, dim, generator=g, dtype=torch.float64) - 0.5
+    p = torch.rand(50, generator=g, dtype=torch.float64) + 0.5
+    E = p / 0.4 + 0.5 * rho * (vel ** 2).sum(-1)
+    U = torch.cat([rho[:, None], rho[:, None] * vel, E[:, None]], -1)
+    D = torch.randn(50, m, generator=g, dtype=torch.float64)
+    _, jv = torch.autograd.functional.jvp(lambda X: phys.flux(X, d), (U,), (D,))
+    assert torch.allclose(phys.jvp(U, D, d), jv, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("dim,d", [(1, 0), (2, 0), (2, 1)])
+def test_euler_eigensystem_and_roe_property(dim, d):
+    """R diag(lambda) R^-1 = A(U_roe) and A(U_roe)(U_R - U_L) = F_R - F_L."""
+    g = torch.Generator().manual_seed(6)
+    prob = o.Problem(dim=dim, physics="euler")
+    phys = o.Euler(prob)
+
+    def state(n):
+        rho = torch.rand(n, generator=g, dtype=torch.float64) + 0.2
+        vel = torch.rand(n, dim, generator=g, dtype=torch.float64) * 2 - 1
+        p = torch.rand(n, generator=g, dtype=torch.float64) + 0.2
+        E = p / 0.4 + 0.5 * rho * (vel ** 2).sum(-1)
+        return torch.cat([rho[:, None], rho[:, None] * vel, E[:, None]], -1)
+
+    UL, UR = state(20), state(20)
+    R = phys.right_eigenvectors(UL, UR, d)
+    u, v, H, c = phys.roe_average(UL, UR)
+    # a state with the Roe velocity and enthalpy (the Jacobian does not depend on rho)
+    q2 = u * u + v * v
+    Eb = (H + 0.4 * 0.5 * q2) / 1.4
+    one = torch.ones_like(u)
+    Ub = torch.stack([one, u, Eb], -1) if dim == 1 else torch.stack([one, u, v, Eb], -1)
+    for k in range(20):
+        A = torch.autograd.functional.jacobian(lambda X: phys.flux(X, d), Ub[k])
+        un = (u if d == 0 else v)[k]
+        lam = [un - c[k], un, un + c[k]] if dim == 1 else [un - c[k], un, un, un + c[k]]
+        rec = R[k] @ torch.diag(torch.stack(lam)) @ torch.linalg.inv(R[k])
+        assert torch.allclose(rec, A, rtol=1e-10, atol=1e-10)
+        dF = phys.flux(UR[k], d) - phys.flux(UL[k], d)
+        assert torch.allclose(A @ (UR[k] - UL[k]), dF, rtol=1e-10, atol=1e-10)
+
+
+# ---------------------------------------------------------------------------
+# invariants of the operator
+# ---------------------------------------------------------------------------
+
+def test_constant_state_has_zero_rhs_and_zero_limited_derivative():
+    w = hi.euler2d_quadrants(12, 10, 0)
+    S = _S(w)
+    S[:4] = S[:4, :1, :1]       # constant state
+    S[4:] = 0.0
+    for bc in (o.PERIODIC, o.OUTFLOW):
+        prob = _prob(w, bc_x=bc, bc_y=bc) if False else o.Problem(
+            dim=2, physics="euler", dx=w.dx, dy=w.dy, bc_x=bc, bc_y=bc)
+        assert float(o.rhs(S, prob).abs().max()) == 0.0
+        assert float(o.limited_derivatives(S, prob).abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("kind", ["scalar1d", "euler1d", "euler2d"])
+def test_periodic_conservation(kind):
+    """Periodic grids: the cell sum of L_U vanishes (flux form, eqs. odeH / ode2H)."""
+    if kind == "scalar1d":
+        w = hi.scalar_random_1d(37, 1, physics="burgers")
+    elif kind == "euler1d":
+        w = hi.euler1d_piecewise(41, 2)
+    else:
+        w = hi.euler2d_quadrants(13, 11, 3, bc=hi.PERIODIC)
+    prob = _prob(w)
+    S = _S(w)
+    L = o.rhs(S, prob)
+    for c in range(prob.m):
+        scale = float(L[c].abs().max()) + 1.0
+        assert abs(float(L[c].sum())) < 1e-12 * scale * L[c].numel()
+    # and over a few full steps the totals stay put
+    tot0 = S[:prob.m].sum(dim=(1, 2))
+    for _ in range(3):
+        S, _, _ = o.rk3_step(S, prob)
+    assert torch.allclose(S[:prob.m].sum(dim=(1, 2)), tot0, rtol=1e-12, atol=1e-11)
+
+
+def test_reflection_symmetry_scalar():
+    """x -> -x with a -> -a: the '-' reconstruction mirrors the '+' one."""
+    w = hi.scalar_random_1d(29, 4, physics="linadv", a=1.0)
+    S = _S(w)
+    Sr = torch.stack([S[0].flip(-1), -S[1].flip(-1)])
+    p1 = _prob(w)
+    p2 = _prob(w)
+    p2.adv_speed = (-1.0, 0.0)
+    L = o.rhs(S, p1)
+    Lr = o.rhs(Sr, p2)
+    assert torch.allclose(Lr[0], L[0].flip(-1), rtol=1e-12, atol=1e-10)
+    assert torch.allclose(Lr[1], -L[1].flip(-1), rtol=1e-12, atol=1e-10)
+    # Burgers with mixed-sign u: u(x) -> -u(-x) leaves u_t + (u^2/2)_x = 0 invariant
+    w = hi.scalar_random_1d(31, 5, physics="burgers")
+    S = _S(w)
+    Sr = torch.stack([-S[0].flip(-1), S[1].flip(-1)])
+    L = o.rhs(S, _prob(w))
+    Lr = o.rhs(Sr, _prob(w))
+    assert torch.allclose(Lr[0], -L[0].flip(-1), rtol=1e-12, atol=1e-10)
+    assert torch.allclose(Lr[1], L[1].flip(-1), rtol=1e-12, atol=1e-10)
+
+
+def test_reflection_symmetry_euler1d():
+    """x -> -x: rho, E even, m odd; their x-derivatives take the opposite parity."""
+    w = hi.euler1d_piecewise(33, 7)
+    S = _S(w)
+    S[3:] = torch.randn(3, 1, 33, dtype=torch.float64, generator=torch.Generator().manual_seed(1))
+    par = torch.tensor([1.0, -1.0, 1.0, -1.0, 1.0, -1.0], dtype=torch.float64)[:, None, None]
+    Sr = par * S.flip(-1)
+    prob = _prob(w)
+    L = o.rhs(S, prob)
+    Lr = o.rhs(Sr, prob)
+    assert torch.allclose(Lr, par * L.flip(-1), rtol=1e-11, atol=1e-9)
+    assert torch.allclose(o.limited_derivatives(Sr, prob),
+                          par[3:] * o.limited_derivatives(S, prob).flip(-1), rtol=1e-11, atol=1e-9)
+
+
+def _transpose_euler(S):
+    """Swap x and y: transpose grids, swap the momenta and the U_x / U_y blocks."""
+    perm = [0, 2, 1, 3]
+    U = S[0:4][perm]
+    V = S[4:8][perm]
+    W = S[8:12][perm]
+    return torch.cat([U, W, V]).transpose(1, 2).contiguous()
+
+
+@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.OUTFLOW])
+def test_transpose_symmetry_euler2d(bc):
+    w = hi.euler2d_rough(14, 9, 8, bc=bc)
+    S = _S(w)
+    prob = o.Problem(dim=2, physics="euler", dx=0.07, dy=0.05, bc_x=bc, bc_y=bc)
+    probT = o.Problem(dim=2, physics="euler", dx=0.05, dy=0.07, bc_x=bc, bc_y=bc)
+    L = o.rhs(S, prob)
+    LT = o.rhs(_transpose_euler(S), probT)
+    assert torch.allclose(LT, _transpose_euler(L), rtol=1e-11, atol=1e-8)
+    lim = o.limited_derivatives(S, prob)
+    limT = o.limited_derivatives(_transpose_euler(S), probT)
+    perm = [0, 2, 1, 3]
+    exp = torch.cat([lim[4:8][perm], lim[0:4][perm]]).transpose(1, 2)
+    assert torch.allclose(limT, exp, rtol=1e-11, atol=1e-8)
+
+
+def test_2d_reduces_to_1d_for_y_independent_data():
+    w1 = hi.euler1d_piecewise(24, 9)
+    S1 = _S(w1)
+    g = torch.Generator().manual_seed(2)
+    S1[3:] = torch.randn(3, 1, 24, dtype=torch.float64, generator=g)
+    ny = 6
+    U = torch.stack([S1[0], S1[1], torch.zeros_like(S1[0]), S1[2]]).expand(4, ny, 24)
+    V = torch.stack([S1[3], S1[4], torch.zeros_like(S1[0]), S1[5]]).expand(4, ny, 24)
+    S2 = torch.cat([U, V, torch.zeros_like(U)]).contiguous()
+    p1 = o.Problem(dim=1, physics="euler", dx=w1.dx)
+    p2 = o.Problem(dim=2, physics="euler", dx=w1.dx, dy=0.3)
+    L1 = o.rhs(S1, p1)
+    L2 = o.rhs(S2, p2)
+    idx = [0, 1, 3]
+    assert torch.allclose(L2[idx], L1[0:3].expand(3, ny, 24), rtol=1e-12, atol=1e-10)
+    assert torch.allclose(L2[[4, 5, 7]], L1[3:6].expand(3, ny, 24), rtol=1e-12, atol=1e-10)
+    assert float(L2[[2, 6]].abs().max()) < 1e-12
+    assert float(L2[8:].abs().max()) < 1e-12
+
+
+def test_characteristic_equals_componentwise_with_linear_weights():
+    """With omega forced to gamma the reconstruction is linear, so projection commutes."""
+    w = hi.euler2d_rough(10, 8, 11, bc=hi.PERIODIC)
+    S = _S(w)
+    pc = _prob(w, linear_recon=True, characteristic=True)
+    pn = _prob(w, linear_recon=True, characteristic=False)
+    assert torch.allclose(o.rhs(S, pc), o.rhs(S, pn), rtol=1e-11, atol=1e-9)
+    # and the nonlinear weights do change the answer on rough data
+    assert not torch.allclose(o.rhs(S, _prob(w)), o.rhs(S, pc), rtol=1e-6)
+
+
+def test_limiter_off_is_plain_rk3():
+    w = hi.euler1d_piecewise(30, 1)
+    prob = _prob(w, limiter_on=False)
+    S = _S(w)
+    assert torch.equal(o.hat(S, prob), S)
+
+
+# ---------------------------------------------------------------------------
+# accuracy
+# ---------------------------------------------------------------------------
+
+def _orders(errs):
+    return [math.log2(a / b) for a, b in zip(errs, errs[1:])]
+
+
+def test_rhs_truncation_order_scalar_1d():
+    """-(f-hat_{i+1/2} - f-hat_{i-1/2})/dx = -f(u)_x + O(dx^5) (eqs. semi-kth, semi-kth-1)."""
+    eU, eV = [], []
+    for n in (20, 40, 80, 160):
+        w = hi.scalar_sine_1d(n, "burgers")
+        x = torch.as_tensor(hi.centers(n, 0, 2))
+        L = o.rhs(_S(w), _prob(w))
+        u = 0.5 + torch.sin(torch.pi * x)
+        ux = torch.pi * torch.cos(torch.pi * x)
+        uxx = -torch.pi ** 2 * torch.sin(torch.pi * x)
+        eU.append(float((L[0, 0] + u * ux).abs().max()))
+        eV.append(float((L[1, 0] + ux * ux + u * uxx).abs().max()))
+    assert min(_orders(eU)[1:]) > 4.7, eU
+    assert min(_orders(eV)[1:]) > 4.5, eV
+
+
+def test_rhs_truncation_order_euler_2d():
+    """2D Euler density wave: L_U is fifth order (eq. dd-app); the derivative rows
+    carry the fourth-order central mixed terms (eq. md-app), so they are fourth order."""
+    errs, errd = [], []
+    for n in (16, 32, 64):
+        w = hi.euler2d_wave(n, n, lo=0.0, hi=2.0)
+        x = torch.as_tensor(hi.centers(n, 0, 2))[None, :]
+        y = torch.as_tensor(hi.centers(n, 0, 2))[:, None]
+        L = o.rhs(_S(w), _prob(w))
+        # u = v = 1, p = 1: U_t = -(U_x + U_y) with U = (rho, rho, rho, 1/(g-1) + rho)
+        r_x = 0.2 * torch.pi * torch.cos(torch.pi * (x + y))
+        r_xx = -0.2 * torch.pi ** 2 * torch.sin(torch.pi * (x + y))
+        ex = torch.stack([-2 * r_x, -2 * r_x, -2 * r_x, -2 * r_x,
+                          -2 * r_xx, -2 * r_xx, -2 * r_xx, -2 * r_xx,
+                          -2 * r_xx, -2 * r_xx, -2 * r_xx, -2 * r_xx])
+        errs.append(float((L - ex)[:4].abs().max()))
+        errd.append(float((L - ex)[4:].abs().max()))
+    assert min(_orders(errs)) > 4.6, errs
+    assert min(_orders(errd)) > 3.8, errd
+
+
+def _load_table(name):
+    rows = np.loadtxt(os.path.join(GOLDEN, name), comments="#")
+    return {int(r[0]): (r[1], r[2]) for r in rows}
+
+
+def _accuracy_dt(prob):
+    # Tables 1-4 are fifth order in time as well as space: dt ~ dx^(5/3) keeps
+    # the third-order Runge-Kutta error below the spatial one.
+    if prob.dim == 1:
+        return lambda a: prob.cfl * prob.dx ** (5.0 / 3.0) / a[0]
+    return lambda a: prob.cfl / (a[0] / prob.dx + a[1] / prob.dy) * prob.dx ** (2.0 / 3.0)
+
+
+def _check_against_table(table, errs, ns, lo=0.5, hi_=2.0):
+    for n, (l1, li) in zip(ns, errs):
+        p1, pi = table[n]
+        assert lo < l1 / p1 < hi_, (n, l1, p1)
+        assert lo < li / pi < hi_, (n, li, pi)
+
+
+def test_table2_euler1d_density_wave():
+    """Example 3.2, Table 2 (L-HWENO columns), N = 10, 20, 40."""
+    table = _load_table("table2_euler1d.txt")
+    ns, errs = (10, 20, 40), []
+    for n in ns:
+        w = hi.euler1d_smooth(n)
+        prob = _prob(w)
+        S, _ = o.run(_S(w), prob, 2.0, _accuracy_dt(prob))
+        x = hi.centers(n, 0.0, 2.0)
+        e = np.abs(S[0, 0].numpy() - (1 + 0.2 * np.sin(np.pi * (x - 2.0))))
+        errs.append((e.mean(), e.max()))
+    _check_against_table(table, errs, ns, 0.7, 1.3)
+    assert min(_orders([e[0] for e in errs])) > 4.8
+
+
+def _burgers_exact(x, t):
+    u = 0.5 + np.sin(np.pi * x)
+    for _ in range(60):
+        g = u - (0.5 + np.sin(np.pi * (x - u * t)))
+        u = u - g / (1 + np.pi * np.cos(np.pi * (x - u * t)) * t)
+    return u
+
+
+def test_table1_burgers1d():
+    """Example 3.1, Table 1 (L-HWENO columns), N = 10..80."""
+    table = _load_table("table1_burgers1d.txt")
+    T = 0.5 / np.pi
+    ns, errs = (10, 20, 40, 80), []
+    for n in ns:
+        w = hi.scalar_sine_1d(n, "burgers")
+        prob = _prob(w)
+        S, _ = o.run(_S(w), prob, T, _accuracy_dt(prob))
+        e = np.abs(S[0, 0].numpy() - _burgers_exact(hi.centers(n, 0.0, 2.0), T))
+        errs.append((e.mean(), e.max()))
+    _check_against_table(table, errs[1:], ns[1:], 0.4, 2.5)
+    _check_against_table(table, errs[2:], ns[2:], 0.8, 1.25)
+
+
+def test_table4_euler2d_density_wave():
+    """Example 3.9, Table 4 (L-HWENO columns), N = 10 and 20."""
+    table = _load_table("table4_euler2d.txt")
+    ns, errs = (10, 20), []
+    for n in ns:
+        w = hi.euler2d_wave(n, n)
+        prob = _prob(w)
+        S, _ = o.run(_S(w), prob, 2.0, _accuracy_dt(prob))
+        x = hi.centers(n, 0.0, 2.0)[None, :]
+        y = hi.centers(n, 0.0, 2.0)[:, None]
+        e = np.abs(S[0].numpy() - (1 + 0.2 * np.sin(np.pi * (x + y - 4.0))))
+        errs.append((e.mean(), e.max()))
+    _check_against_table(table, errs, ns, 0.7, 1.3)
+
+
+def test_linear_advection_sits_on_rk3_floor():
+    """u_t + u_x = 0, N = 200, CFL 0.6, T = 2: the time error of SSP-RK3 dominates.
+
+    For the mode sin(pi x) the exact operator multiplies by -i pi; one RK3
+    step multiplies by G(z) = 1 + z + z^2/2 + z^3/6 with z = -i pi dt, so the
+    error after n steps is |G(z)^n - exp(-i pi T)| (the spatial error is ~1e-11).
+    """
+    n = 200
+    w = hi.scalar_sine_1d(n, "linadv")
+    prob = _prob(w)
+    S, steps = o.run(_S(w), prob, 2.0)
+    x = hi.centers(n, 0.0, 2.0)
+    err = np.abs(S[0, 0].numpy() - (0.5 + np.sin(np.pi * (x - 2.0)))).max()
+    dt = prob.cfl * prob.dx
+    full = int(np.floor(2.0 / dt + 1e-9))
+    last = 2.0 - full * dt            # the final step is clipped to reach T
+    assert steps == full + (1 if last > 1e-12 else 0)
+
+    def G(h):
+        z = -1j * np.pi * h
+        return 1 + z + z * z / 2 + z ** 3 / 6
+    amp = G(dt) ** full * (G(last) if last > 1e-12 else 1.0)
+    floor = abs(amp - np.exp(-1j * np.pi * 2.0))
+    assert 0.9 < err / floor < 1.1, (err, floor)
