@@ -1,0 +1,181 @@
+/*
+ * hweno.h -- C ABI of the MI355X (gfx950) L-HWENO hot path.
+ *
+ * Method: Zhang & Zhao, "A fifth-order finite difference HWENO scheme combined
+ * with limiter for hyperbolic conservation laws" (arXiv 2207.05258), Section 2.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Memory.  Every array argument is DEVICE memory owned by the caller
+ * (e.g. torch tensors); the library allocates no device memory and keeps no
+ * device state.  Pointers are borrowed until the enqueued work has completed.
+ *
+ * State layout.  One contiguous buffer of nf fields, each ny * nx values of the
+ * problem's dtype, x fastest ("SoA [nf][ny][nx]", ny == 1 when dim == 1):
+ * the m conserved components U, then their x-derivatives U_x, then (2D) their
+ * y-derivatives U_y, nf = m * (1 + dim), with m = 1 for the scalar
+ * equations, 3 for 1D Euler and 4 for 2D Euler (rho, rho u, [rho v,] E).
+ * Values are point values at cell centres x_i = x_lo + (i + 1/2) dx.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default stream).
+ * Every call only enqueues work on it, never synchronises, and never copies
+ * between host and device, so the calls may be captured in a hipGraph.
+ *
+ * Errors.  Argument errors are detected on the host before any HIP call and
+ * returned as a status code; hweno_last_error() then gives a thread-local
+ * message.  Launch failures return HWENO_ERR_LAUNCH.  Numerical failure
+ * (non-finite values, rho <= 0, p <= 0) is not an error code: it is recorded
+ * in the device status word of the step control block (see below).  Nothing
+ * aborts and nothing throws across this ABI.  A grid with nx == 0 or ny == 0 is
+ * a valid, empty problem: calls return HWENO_OK and enqueue nothing.
+ */
+#ifndef HWENO_H
+#define HWENO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  HWENO_OK = 0,
+  HWENO_ERR_INVALID_ARG = 1,
+  HWENO_ERR_UNSUPPORTED = 2,
+  HWENO_ERR_WORKSPACE = 3,
+  HWENO_ERR_LAUNCH = 4
+} hweno_status;
+
+typedef enum { HWENO_F32 = 0, HWENO_F64 = 1 } hweno_dtype;
+typedef enum { HWENO_LINADV = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_physics;
+typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1 } hweno_bc;
+
+/* Problem description (host memory, read during the call only).
+ *  dim            1 or 2.
+ *  nx, ny         cells per direction (ny must be 1 when dim == 1); >= 0.
+ *  physics        hweno_physics: u_t + f(u)_x [+ g(u)_y] = 0 with
+ *                 f = a_x u, g = a_y u (LINADV), f = g = u^2/2 (BURGERS), or
+ *                 the Euler equations with E = p/(gamma-1) + rho|vel|^2/2.
+ *  dtype          hweno_dtype of every array (FP32 or FP64).
+ *  bc_x, bc_y     hweno_bc: periodic wrap, or outflow = copy of the nearest
+ *                 interior value of every field into the two ghost cells.
+ *  characteristic Euler only: 1 = nonlinear flux reconstruction in local
+ *                 characteristic fields (Remarks 2.1/2.2; Roe average),
+ *                 0 = component by component.  Ignored for scalars.
+ *  limiter_on     1 = HWENO limiter on the derivatives in the time update
+ *                 (Section 2.2), 0 = no limiter (ablation of Table 5).
+ *  dx, dy         cell sizes (> 0; dy ignored in 1D).
+ *  gamma_gas      ratio of specific heats (> 1; Euler only).
+ *  adv_speed      (a_x, a_y) for LINADV.
+ *  lin_w          gamma_0..2 of the reconstruction; lim_w: d_0..2 of the
+ *                 limiter.  Each must be > 0 and sum to 1 within 1e-12.
+ *  eps            epsilon of the nonlinear weights (> 0; paper: 1e-6).
+ *  cfl            CFL number for the device-side time step (> 0; paper: 0.6).
+ */
+typedef struct {
+  int32_t dim, nx, ny;
+  int32_t physics, dtype, bc_x, bc_y;
+  int32_t characteristic, limiter_on;
+  int32_t reserved;
+  double dx, dy;
+  double gamma_gas;
+  double adv_speed[2];
+  double lin_w[3], lim_w[3];
+  double eps, cfl;
+} hweno_problem;
+
+/* Step control block: HWENO_CTRL_LEN doubles of device memory at the start of
+ * the workspace (and the layout of one tape record).
+ *   [0..1] alpha_x, alpha_y of stage 1 (global Lax-Friedrichs speeds of U^n)
+ *   [2..3] alpha of stage 2, [4..5] alpha of stage 3
+ *   [6]    dt of the last step (0 when the step was skipped)
+ *   [7]    simulated time t (accumulates over steps; caller sets the start)
+ *   [8]    status word (uint64 bit pattern): bit 0 non-finite value produced,
+ *          bit 1 rho <= 0, bit 2 p <= 0, bit 3 step skipped (non-finite or
+ *          non-positive dt).  Bits accumulate until the caller clears them.
+ *   [9]    number of steps taken
+ * Wave speeds are stored as IEEE doubles and reduced with an integer atomic
+ * max on their bit pattern (exact, order independent; NaN propagates). */
+#define HWENO_CTRL_LEN 16
+#define HWENO_ST_NONFINITE 1u
+#define HWENO_ST_RHO 2u
+#define HWENO_ST_PRESSURE 4u
+#define HWENO_ST_SKIPPED 8u
+
+/* Host-side validation of a problem (no HIP call).  Returns HWENO_OK or
+ * HWENO_ERR_INVALID_ARG with hweno_last_error() set. */
+hweno_status hweno_validate(const hweno_problem* prob);
+
+/* Bytes of device workspace hweno_rk3_step needs for `prob`
+ * (control block, two stage states and the limited base derivatives).
+ * Returns 0 for an invalid problem. */
+size_t hweno_workspace_bytes(const hweno_problem* prob);
+
+/* Global Lax-Friedrichs speeds alpha_d = max over the grid of |f_d'(u)|
+ * (Section 2.1; Euler: |u_d| + c).  alpha: device double[2], overwritten
+ * (alpha[1] = 0 in 1D). */
+hweno_status hweno_alpha(const hweno_problem* prob, const void* state,
+                         double* alpha, void* stream);
+
+/* Semi-discrete right-hand side (eqs. odeH and ode2H):
+ *   rhs = (L_U, L_Ux[, L_Uy]) in the state layout, with the flux f-hat from
+ *   the nonlinear HWENO reconstruction (Section 2.1), h-hat / theta-hat from
+ *   p_0' and the mixed eta-hat / xi-hat from the four-point formula (eq. mixed).
+ * alpha: device double[2]; if compute_alpha != 0 it is first overwritten with
+ *   the speeds of `state` (as hweno_alpha), else it is read as given.
+ * state, rhs: device, nf * ny * nx values; must not overlap. */
+hweno_status hweno_rhs(const hweno_problem* prob, const void* state, void* rhs,
+                       double* alpha, int32_t compute_alpha, void* stream);
+
+/* HWENO limiter (Section 2.2) applied component by component:
+ *   dlim = (U_x limited along x [, U_y limited along y]), m * dim fields in
+ *   the state layout.  The centre derivative is not an input of the limiter. */
+hweno_status hweno_limit(const hweno_problem* prob, const void* state,
+                         void* dlim, void* stream);
+
+/* One SSP-RK3 step (Section 2.2, eqs. for u^(1), u^(2), u^(n+1)), in place:
+ *   S1 = S^ + dt L(S0); S2 = 3/4 S^ + 1/4 (S1^ + dt L(S1));
+ *   S^{n+1} = 1/3 S^ + 2/3 (S2^ + dt L(S2)), with S^ = (U, limited
+ *   derivatives) used in the update only and L always evaluated on the
+ *   unlimited state.  Each stage recomputes the wave speeds of its own input.
+ * state: device, in/out.
+ * ws: device workspace of at least hweno_workspace_bytes(prob) bytes, 256-byte
+ *   aligned; its first HWENO_CTRL_LEN doubles are the step control block.
+ *   Zero the control block before the first step of a run (t and the status
+ *   word accumulate there across calls).
+ * dt_fixed: > 0 uses this time step; otherwise dt = cfl dx / alpha_x (1D) or
+ *   cfl / (alpha_x/dx + alpha_y/dy) (2D) from the stage-1 speeds, on device.
+ * t_end: > 0 clips dt to t_end - t (a step at t >= t_end is skipped).
+ * tape: device double[HWENO_CTRL_LEN] or NULL; receives the control block
+ *   after the step (speeds of all three stages, dt, t, status).
+ * replay: device double[HWENO_CTRL_LEN] or NULL; when given, the stage speeds
+ *   [0..5] and dt [6] are taken from it instead of being computed (used to
+ *   recompute a taped forward pass exactly). */
+hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws,
+                            size_t ws_bytes, double dt_fixed, double t_end,
+                            double* tape, const double* replay, void* stream);
+
+/* Vector-Jacobian product of one stage with frozen wave speeds (discrete
+ * adjoint of eqs. odeH / ode2H and of the limiter of Section 2.2):
+ *   lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim
+ * alpha: device double[2], the speeds the forward stage used (replayed);
+ * the absolute values in tau are differentiated with sign(0) = 0.
+ * lam_rhs: nf fields; lam_lim: m * dim fields or NULL; lam_state: nf fields,
+ * accumulated into. */
+hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
+                               const double* alpha, const void* lam_rhs,
+                               const void* lam_lim, void* lam_state,
+                               void* stream);
+
+/* Human-readable name of a status code (static string). */
+const char* hweno_status_string(int32_t status);
+
+/* Thread-local detail of the last non-OK return on this thread ("" if none). */
+const char* hweno_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HWENO_H */

@@ -1,0 +1,8 @@
+"""MI355X (gfx950) L-HWENO hot path: HIP kernels behind a C ABI, thin binding.
+
+Zhang & Zhao, "A fifth-order finite difference HWENO scheme combined with
+limiter for hyperbolic conservation laws" (arXiv 2207.05258).
+"""
+from .hweno import (CTRL_LEN, OUTFLOW, PERIODIC, HwenoError, Problem, Stepper,  # noqa: F401
+                    alpha, lib, limit, problem_for, rhs, rk3_step_, validate,
+                    workspace_bytes)

@@ -1,0 +1,760 @@
+// HIP kernels for gfx950 and the C ABI of include/hweno.h.
+//
+// One workgroup advances one tile of cells through one Runge-Kutta stage
+// (or evaluates the right-hand side on it):
+//   1. the tile plus a two-cell halo of every field is staged in LDS with
+//      coalesced row loads (boundary conditions are index maps on these
+//      loads; there is no ghost-fill pass);
+//   2. one thread per x-interface computes all interface fluxes
+//      (characteristic HWENO f-hat, linear h-hat, mixed eta-hat) into an LDS
+//      flux buffer; each thread then differences the two interfaces of its
+//      own cell;
+//   3. the same for the y-interfaces (same code, momenta swapped on load);
+//   4. each thread limits the derivatives of its cell, applies the SSP-RK3
+//      combination, stores its cell, and contributes its wave speeds to a
+//      workgroup max that is folded into the next stage's global speed with
+//      one 64-bit atomic max on the IEEE bit pattern.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/hweno.h"
+#include "hweno_math.h"
+
+namespace hweno {
+
+// ---------------------------------------------------------------------------
+// launch arguments
+// ---------------------------------------------------------------------------
+template <typename T>
+struct StageArgs {
+  const T* in;        // stage input S_k (state layout)
+  T* out;             // S_{k+1}, or the right-hand side (K == 0)
+  const T* st0;       // S^n (stages 2 and 3 read U^n, and all of S^n without limiter)
+  T* base;            // limited derivatives of S^n (written by stage 1, read by 2, 3)
+  double* ctrl;       // step control block (stages only)
+  unsigned long long* status;  // status word, or NULL
+  const double* alpha;  // speeds for K == 0
+  int nx, ny, bc_x, bc_y;
+  long long fs;       // field stride nx * ny
+  double dx, dy;
+  double dt_fixed, t_end, cfl;
+  int replay;
+};
+
+__device__ __forceinline__ int map_index(int i, int n, int bc) {
+  if (bc == HWENO_BC_PERIODIC) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ unsigned long long dbits(double x) {
+  return (unsigned long long)__double_as_longlong(x);
+}
+
+// workgroup reduction of two non-negative speeds (as bit patterns, so NaN
+// wins) and of status flags; thread 0 folds them into global memory.
+template <int NT>
+__device__ __forceinline__ void block_fold(double sx, double sy, uint32_t flags,
+                                           double* slot, unsigned long long* status,
+                                           bool do_speeds) {
+  __shared__ unsigned long long red[NT / 64][2];
+  __shared__ uint32_t redf[NT / 64];
+  unsigned long long bx = dbits(sx), by = dbits(sy);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long ox = __shfl_xor(bx, off);
+    unsigned long long oy = __shfl_xor(by, off);
+    uint32_t of = __shfl_xor(flags, off);
+    bx = ox > bx ? ox : bx;
+    by = oy > by ? oy : by;
+    flags |= of;
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[wv][0] = bx;
+    red[wv][1] = by;
+    redf[wv] = flags;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int q = 1; q < NT / 64; ++q) {
+      bx = red[q][0] > bx ? red[q][0] : bx;
+      by = red[q][1] > by ? red[q][1] : by;
+      flags |= redf[q];
+    }
+    if (do_speeds) {
+      atomicMax((unsigned long long*)slot, bx);
+      atomicMax((unsigned long long*)slot + 1, by);
+    }
+    if (flags && status) atomicOr(status, (unsigned long long)flags);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// stage / right-hand-side kernel
+// K = 0: right-hand side only; K = 1, 2, 3: SSP-RK3 stage K.
+// ---------------------------------------------------------------------------
+template <typename T, int PHYS, int DIM, int K, int TX, int TY>
+__global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
+  constexpr int M = Comps<PHYS, DIM>::M;
+  constexpr int NF = Comps<PHYS, DIM>::NF;
+  constexpr int NT = TX * TY;
+  constexpr int HY = (DIM == 2) ? 2 : 0;
+  constexpr int W = TX + 4;           // LDS row length (2-cell x halo each side)
+  constexpr int HR = TY + 2 * HY;     // LDS rows
+  constexpr int FW = TX + 1;          // flux buffer row length
+  constexpr int FR = TY + 1;          // flux buffer rows
+  constexpr int NQ = (DIM == 2) ? 3 : 2;  // flux kinds stored per interface
+  __shared__ T sm[NF * HR * W];
+  __shared__ T fb[NQ * M * FR * FW];
+
+  const int tid = threadIdx.x;
+  double* ctrl = a.ctrl;
+  unsigned long long* status = a.status;
+
+  // ---- time step and wave speeds of this stage ----
+  double dt = 0.0, alx, aly;
+  if constexpr (K == 0) {
+    alx = a.alpha[0];
+    aly = a.alpha[1];
+  } else {
+    alx = ctrl[2 * (K - 1)];
+    aly = ctrl[2 * (K - 1) + 1];
+    if constexpr (K == 1) {
+      if (a.replay) {
+        dt = ctrl[6];
+      } else {
+        if (a.dt_fixed > 0.0) {
+          dt = a.dt_fixed;
+        } else if (DIM == 1) {
+          dt = a.cfl * a.dx / alx;
+        } else {
+          dt = a.cfl / (alx / a.dx + aly / a.dy);
+        }
+        if (a.t_end > 0.0) dt = fmin(dt, a.t_end - ctrl[7]);
+        if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
+        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+          ctrl[6] = dt;
+          if (dt == 0.0) atomicOr(status, (unsigned long long)HWENO_ST_SKIPPED);
+        }
+      }
+    } else {
+      dt = ctrl[6];
+    }
+    if (!(dt > 0.0)) return;  // uniform over the grid: the step is skipped
+  }
+
+  const int i0 = blockIdx.x * TX;
+  const int j0 = blockIdx.y * TY;
+  const int nx = a.nx, ny = a.ny;
+  const long long fs = a.fs;
+
+  // ---- stage the tile and its halo in LDS ----
+  for (int q = tid; q < W * HR; q += NT) {
+    const int lr = q / W, lc = q - lr * W;
+    const int gi = map_index(i0 - 2 + lc, nx, a.bc_x);
+    const int gj = (DIM == 2) ? map_index(j0 - HY + lr, ny, a.bc_y) : 0;
+    const long long g = (long long)gj * nx + gi;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sm[(f * HR + lr) * W + lc] = a.in[f * fs + g];
+  }
+  __syncthreads();
+
+  const T idx = T(1.0 / a.dx);
+  const T hx = T(a.dx);
+  const int tx = tid % TX, ty = tid / TX;
+  T LU[M], LV[M], LW[M];
+
+  // ---- x-interfaces: between local cells ix-1 and ix, ix = 0..TX ----
+  for (int q = tid; q < FW * TY; q += NT) {
+    const int r = q / FW, ix = q - r * FW;
+    const T* row = sm + (r + HY) * W + ix;
+    auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        U[c] = row[(c * HR) * W + s];
+        Dn[c] = row[((M + c) * HR) * W + s];
+        if constexpr (DIM == 2) Dt[c] = row[((2 * M + c) * HR) * W + s];
+      }
+    };
+    T fh[M], hh[M], xh[M];
+    interface_fluxes<T, PHYS, M, DIM == 2>(ld, T(alx), hx, idx, k.ax, k, fh, hh, xh);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      fb[(c * FR + r) * FW + ix] = fh[c];
+      fb[((M + c) * FR + r) * FW + ix] = hh[c];
+      if constexpr (DIM == 2) fb[((2 * M + c) * FR + r) * FW + ix] = xh[c];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const int b0 = (c * FR + ty) * FW + tx;
+    LU[c] = -(fb[b0 + 1] - fb[b0]) * idx;
+    const int b1 = ((M + c) * FR + ty) * FW + tx;
+    LV[c] = -(fb[b1 + 1] - fb[b1]) * idx;
+    if constexpr (DIM == 2) {
+      const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
+      LW[c] = -(fb[b2 + 1] - fb[b2]) * idx;
+    }
+  }
+
+  if constexpr (DIM == 2) {
+    const T idy = T(1.0 / a.dy);
+    const T hy = T(a.dy);
+    __syncthreads();
+    // ---- y-interfaces: between local rows iy-1 and iy, iy = 0..TY ----
+    for (int q = tid; q < TX * FR; q += NT) {
+      const int iy = q / TX, cc = q - iy * TX;
+      const T* col = sm + iy * W + cc + 2;
+      auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          // normal frame: swap the two momenta; Dn = U_y, Dt = U_x
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          U[c] = col[(cs * HR + s) * W];
+          Dn[c] = col[((2 * M + cs) * HR + s) * W];
+          Dt[c] = col[((M + cs) * HR + s) * W];
+        }
+      };
+      T fh[M], hh[M], xh[M];
+      interface_fluxes<T, PHYS, M, true>(ld, T(aly), hy, idy, k.ay, k, fh, hh, xh);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        fb[(cs * FR + iy) * FW + cc] = fh[c];
+        fb[((M + cs) * FR + iy) * FW + cc] = hh[c];   // theta-hat -> L_W
+        fb[((2 * M + cs) * FR + iy) * FW + cc] = xh[c];  // xi-hat -> L_V
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const int b0 = (c * FR + ty) * FW + tx;
+      LU[c] -= (fb[b0 + FW] - fb[b0]) * idy;
+      const int b1 = ((M + c) * FR + ty) * FW + tx;
+      LW[c] -= (fb[b1 + FW] - fb[b1]) * idy;
+      const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
+      LV[c] -= (fb[b2 + FW] - fb[b2]) * idy;
+    }
+  }
+
+  // ---- own cell: limiter, Runge-Kutta combination, store ----
+  const int gi = i0 + tx, gj = j0 + ty;
+  const bool inside = gi < nx && gj < ny;
+  const long long g = (long long)gj * nx + gi;
+  const T* own = sm + (ty + HY) * W + tx + 2;
+
+  if constexpr (K == 0) {
+    if (inside) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        a.out[c * fs + g] = LU[c];
+        a.out[(M + c) * fs + g] = LV[c];
+        if constexpr (DIM == 2) a.out[(2 * M + c) * fs + g] = LW[c];
+      }
+    }
+    return;
+  } else {
+    // S^_k = (U_k, limited derivatives of S_k)
+    T Sh[NF];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      Sh[c] = own[(c * HR) * W];
+      const T* u = own + (c * HR) * W;
+      const T* v = own + ((M + c) * HR) * W;
+      if (k.limiter_on) {
+        Sh[M + c] = limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw);
+      } else {
+        Sh[M + c] = v[0];
+      }
+      if constexpr (DIM == 2) {
+        const T* w = own + ((2 * M + c) * HR) * W;
+        if (k.limiter_on) {
+          Sh[2 * M + c] = limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
+                                 T(1.0 / a.dy), k.lw);
+        } else {
+          Sh[2 * M + c] = w[0];
+        }
+      }
+    }
+    T L[NF];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      L[c] = LU[c];
+      L[M + c] = LV[c];
+      if constexpr (DIM == 2) L[2 * M + c] = LW[c];
+    }
+    const T tdt = T(dt);
+    T out[NF];
+    if (inside) {
+      if constexpr (K == 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) out[f] = Sh[f] + tdt * L[f];
+        if (k.limiter_on) {
+#pragma unroll
+          for (int f = M; f < NF; ++f) a.base[(f - M) * fs + g] = Sh[f];
+        }
+      } else {
+        const T w0 = (K == 2) ? T(0.75) : T(1.0 / 3.0);
+        const T w1 = (K == 2) ? T(0.25) : T(2.0 / 3.0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          T s0;
+          if (f < M || !k.limiter_on) {
+            s0 = a.st0[f * fs + g];
+          } else {
+            s0 = a.base[(f - M) * fs + g];
+          }
+          out[f] = w0 * s0 + w1 * (Sh[f] + tdt * L[f]);
+        }
+      }
+#pragma unroll
+      for (int f = 0; f < NF; ++f) a.out[f * fs + g] = out[f];
+    }
+    if constexpr (K < 3) {
+      // speeds of the new stage state, for the next stage's splitting
+      T sx = T(0), sy = T(0);
+      uint32_t flags = 0;
+      if (inside) point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
+      block_fold<NT>(double(sx), double(sy), flags, ctrl + 2 * K, status, !a.replay);
+    } else {
+      T sx = T(0), sy = T(0);
+      uint32_t flags = 0;
+      if (inside) point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
+      block_fold<NT>(0.0, 0.0, flags, ctrl, status, false);
+    }
+  }
+}
+
+// global speeds of a state: alpha[0..1] = max over cells (target pre-zeroed)
+template <typename T, int PHYS, int DIM>
+__global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, long long n,
+                                               Consts<T> k, double* alpha,
+                                               unsigned long long* status) {
+  constexpr int M = Comps<PHYS, DIM>::M;
+  T mx = T(0), my = T(0);
+  uint32_t flags = 0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
+    T U[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) U[c] = S[c * n + i];
+    T sx, sy;
+    point_speeds<T, PHYS, DIM>(U, k, sx, sy, flags);
+    // bit-pattern max keeps NaN
+    mx = (dbits(double(sx)) > dbits(double(mx))) ? sx : mx;
+    my = (dbits(double(sy)) > dbits(double(my))) ? sy : my;
+  }
+  block_fold<256>(double(mx), double(my), flags, alpha, status, true);
+}
+
+__global__ void k_begin(double* ctrl, const double* replay) {
+  const int t = threadIdx.x;
+  if (replay) {
+    if (t < 7) ctrl[t] = replay[t];
+  } else if (t < 6) {
+    ctrl[t] = 0.0;
+  }
+}
+
+__global__ void k_zero(double* p, int n) {
+  if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
+}
+
+__global__ void k_finish(double* ctrl, double* tape) {
+  if (threadIdx.x == 0) {
+    if (ctrl[6] > 0.0) {
+      ctrl[7] += ctrl[6];
+      ctrl[9] += 1.0;
+    }
+    if (tape) {
+      for (int q = 0; q < 10; ++q) tape[q] = ctrl[q];
+    }
+  }
+}
+
+// limited derivatives (Section 2.2), one thread per cell, all components
+template <typename T, int PHYS, int DIM>
+__global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __restrict__ out,
+                                               int nx, int ny, int bc_x, int bc_y,
+                                               double dx, double dy, Consts<T> k) {
+  constexpr int M = Comps<PHYS, DIM>::M;
+  const long long n = (long long)nx * ny;
+  const long long i = blockIdx.x * 256ll + threadIdx.x;
+  if (i >= n) return;
+  const int gj = (int)(i / nx), gi = (int)(i - (long long)gj * nx);
+  const long long xm = (long long)gj * nx + map_index(gi - 1, nx, bc_x);
+  const long long xp = (long long)gj * nx + map_index(gi + 1, nx, bc_x);
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    const T* u = S + c * n;
+    const T* v = S + (M + c) * n;
+    out[c * n + i] = limit1(u[xm], u[i], u[xp], v[xm], v[xp], T(dx), T(1.0 / dx), k.lw);
+  }
+  if constexpr (DIM == 2) {
+    const long long ym = (long long)map_index(gj - 1, ny, bc_y) * nx + gi;
+    const long long yp = (long long)map_index(gj + 1, ny, bc_y) * nx + gi;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      const T* u = S + c * n;
+      const T* w = S + (2 * M + c) * n;
+      out[(M + c) * n + i] = limit1(u[ym], u[i], u[yp], w[ym], w[yp], T(dy), T(1.0 / dy), k.lw);
+    }
+  }
+}
+
+}  // namespace hweno
+
+// ===========================================================================
+// host side
+// ===========================================================================
+using namespace hweno;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+hweno_status fail(hweno_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+hweno_status ok() {
+  g_last_error.clear();
+  return HWENO_OK;
+}
+
+int n_comp(const hweno_problem* p) {
+  if (p->physics == HWENO_EULER) return p->dim == 1 ? 3 : 4;
+  return 1;
+}
+
+int n_fields(const hweno_problem* p) { return n_comp(p) * (1 + p->dim); }
+
+size_t elem_size(const hweno_problem* p) { return p->dtype == HWENO_F64 ? 8 : 4; }
+
+bool weights_ok(const double* w) {
+  if (!(w[0] > 0.0 && w[1] > 0.0 && w[2] > 0.0)) return false;
+  if (!std::isfinite(w[0] + w[1] + w[2])) return false;
+  return std::fabs(w[0] + w[1] + w[2] - 1.0) <= 1e-12;
+}
+
+hweno_status validate(const hweno_problem* p) {
+  if (!p) return fail(HWENO_ERR_INVALID_ARG, "problem pointer is NULL");
+  if (p->dim != 1 && p->dim != 2) return fail(HWENO_ERR_INVALID_ARG, "dim must be 1 or 2 (got %d)", p->dim);
+  if (p->nx < 0 || p->ny < 0) return fail(HWENO_ERR_INVALID_ARG, "nx, ny must be >= 0");
+  if (p->dim == 1 && p->ny != 1 && p->ny != 0)
+    return fail(HWENO_ERR_INVALID_ARG, "ny must be 1 for dim == 1 (got %d)", p->ny);
+  if (p->physics < HWENO_LINADV || p->physics > HWENO_EULER)
+    return fail(HWENO_ERR_INVALID_ARG, "unknown physics %d", p->physics);
+  if (p->dtype != HWENO_F32 && p->dtype != HWENO_F64)
+    return fail(HWENO_ERR_INVALID_ARG, "unknown dtype %d", p->dtype);
+  if ((p->bc_x != HWENO_BC_PERIODIC && p->bc_x != HWENO_BC_OUTFLOW) ||
+      (p->dim == 2 && p->bc_y != HWENO_BC_PERIODIC && p->bc_y != HWENO_BC_OUTFLOW))
+    return fail(HWENO_ERR_INVALID_ARG, "unknown boundary condition");
+  if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(HWENO_ERR_INVALID_ARG, "dx must be > 0");
+  if (p->dim == 2 && (!(p->dy > 0.0) || !std::isfinite(p->dy)))
+    return fail(HWENO_ERR_INVALID_ARG, "dy must be > 0");
+  if (!weights_ok(p->lin_w))
+    return fail(HWENO_ERR_INVALID_ARG, "linear weights gamma must be > 0 and sum to 1 (got %.17g %.17g %.17g)",
+                p->lin_w[0], p->lin_w[1], p->lin_w[2]);
+  if (!weights_ok(p->lim_w))
+    return fail(HWENO_ERR_INVALID_ARG, "limiter weights d must be > 0 and sum to 1 (got %.17g %.17g %.17g)",
+                p->lim_w[0], p->lim_w[1], p->lim_w[2]);
+  if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return fail(HWENO_ERR_INVALID_ARG, "eps must be > 0");
+  if (!(p->cfl > 0.0) || !std::isfinite(p->cfl)) return fail(HWENO_ERR_INVALID_ARG, "cfl must be > 0");
+  if (p->physics == HWENO_EULER && (!(p->gamma_gas > 1.0) || !std::isfinite(p->gamma_gas)))
+    return fail(HWENO_ERR_INVALID_ARG, "gamma_gas must be > 1");
+  if (p->physics == HWENO_LINADV &&
+      (!std::isfinite(p->adv_speed[0]) || !std::isfinite(p->adv_speed[1])))
+    return fail(HWENO_ERR_INVALID_ARG, "advection speeds must be finite");
+  const double cells = (double)p->nx * (double)(p->dim == 2 ? p->ny : 1);
+  if (cells * n_fields(p) > 9.0e18 / 8.0) return fail(HWENO_ERR_INVALID_ARG, "grid too large");
+  if (p->nx > (1 << 28) || p->ny > (1 << 28)) return fail(HWENO_ERR_INVALID_ARG, "grid side too large");
+  return ok();
+}
+
+bool empty(const hweno_problem* p) { return p->nx == 0 || (p->dim == 2 && p->ny == 0); }
+
+long long cells_of(const hweno_problem* p) {
+  return (long long)p->nx * (p->dim == 2 ? p->ny : 1);
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct WsLayout {
+  size_t ctrl, s1, s2, base, total;
+};
+
+WsLayout ws_layout(const hweno_problem* p) {
+  WsLayout L;
+  const size_t fb = (size_t)cells_of(p) * elem_size(p);
+  L.ctrl = 0;
+  L.s1 = align256(HWENO_CTRL_LEN * sizeof(double));
+  L.s2 = L.s1 + align256(fb * n_fields(p));
+  L.base = L.s2 + align256(fb * n_fields(p));
+  L.total = L.base + align256(fb * n_comp(p) * p->dim);
+  return L;
+}
+
+template <typename T>
+Consts<T> make_consts(const hweno_problem* p) {
+  Consts<T> k;
+  k.rw = {T(p->lin_w[0]), T(p->lin_w[1]), T(p->lin_w[2]), T(p->eps)};
+  k.lw = {T(p->lim_w[0]), T(p->lim_w[1]), T(p->lim_w[2]), T(p->eps)};
+  k.gm1 = T(p->gamma_gas - 1.0);
+  k.gam = T(p->gamma_gas);
+  k.ax = T(p->adv_speed[0]);
+  k.ay = T(p->adv_speed[1]);
+  k.characteristic = p->characteristic ? 1 : 0;
+  k.limiter_on = p->limiter_on ? 1 : 0;
+  return k;
+}
+
+hweno_status launch_check(const char* what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(HWENO_ERR_LAUNCH, "%s: %s", what, hipGetErrorString(e));
+  return HWENO_OK;
+}
+
+template <int DIM>
+struct Tile {
+  static constexpr int TX = (DIM == 2) ? 32 : 256;
+  static constexpr int TY = (DIM == 2) ? 8 : 1;
+};
+
+// dispatch helper: calls F::template run<T, PHYS, DIM>(args...)
+template <typename F, typename... Args>
+hweno_status dispatch(const hweno_problem* p, Args&&... args) {
+#define HWENO_CASE(TT, PH, D)                                                  \
+  if (p->dtype == (sizeof(TT) == 8 ? HWENO_F64 : HWENO_F32) && p->physics == PH && \
+      p->dim == D)                                                             \
+    return F::template run<TT, PH, D>(p, args...);
+  HWENO_CASE(double, HWENO_LINADV, 1)
+  HWENO_CASE(double, HWENO_BURGERS, 1)
+  HWENO_CASE(double, HWENO_EULER, 1)
+  HWENO_CASE(double, HWENO_LINADV, 2)
+  HWENO_CASE(double, HWENO_BURGERS, 2)
+  HWENO_CASE(double, HWENO_EULER, 2)
+  HWENO_CASE(float, HWENO_LINADV, 1)
+  HWENO_CASE(float, HWENO_BURGERS, 1)
+  HWENO_CASE(float, HWENO_EULER, 1)
+  HWENO_CASE(float, HWENO_LINADV, 2)
+  HWENO_CASE(float, HWENO_BURGERS, 2)
+  HWENO_CASE(float, HWENO_EULER, 2)
+#undef HWENO_CASE
+  return fail(HWENO_ERR_UNSUPPORTED, "unsupported combination");
+}
+
+template <typename T, int PHYS, int DIM>
+StageArgs<T> base_args(const hweno_problem* p) {
+  StageArgs<T> a;
+  std::memset(&a, 0, sizeof a);
+  a.nx = p->nx;
+  a.ny = DIM == 2 ? p->ny : 1;
+  a.bc_x = p->bc_x;
+  a.bc_y = p->bc_y;
+  a.fs = cells_of(p);
+  a.dx = p->dx;
+  a.dy = DIM == 2 ? p->dy : 1.0;
+  a.cfl = p->cfl;
+  return a;
+}
+
+dim3 stage_grid(int dim, int nx, int ny) {
+  if (dim == 2) return dim3((nx + Tile<2>::TX - 1) / Tile<2>::TX, (ny + Tile<2>::TY - 1) / Tile<2>::TY);
+  return dim3((nx + Tile<1>::TX - 1) / Tile<1>::TX, 1);
+}
+
+unsigned alpha_blocks(long long n) {
+  long long b = (n + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+struct RunAlpha {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* state, double* alpha,
+                          unsigned long long* status, hipStream_t s) {
+    const long long n = cells_of(p);
+    k_zero<<<1, 64, 0, s>>>(alpha, 2);
+    k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>((const T*)state, n,
+                                                          make_consts<T>(p), alpha, status);
+    return launch_check("alpha");
+  }
+};
+
+struct RunRhs {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* state, void* rhs,
+                          double* alpha, int compute, hipStream_t s) {
+    if (compute) {
+      hweno_status st = RunAlpha::run<T, PHYS, DIM>(p, state, alpha, nullptr, s);
+      if (st) return st;
+    }
+    StageArgs<T> a = base_args<T, PHYS, DIM>(p);
+    a.in = (const T*)state;
+    a.out = (T*)rhs;
+    a.alpha = alpha;
+    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY;
+    k_stage<T, PHYS, DIM, 0, TX, TY><<<stage_grid(DIM, a.nx, a.ny), TX * TY, 0, s>>>(
+        a, make_consts<T>(p));
+    return launch_check("rhs");
+  }
+};
+
+struct RunLimit {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* state, void* out, hipStream_t s) {
+    const long long n = cells_of(p);
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    k_limit<T, PHYS, DIM><<<blocks, 256, 0, s>>>((const T*)state, (T*)out, p->nx,
+                                                 DIM == 2 ? p->ny : 1, p->bc_x, p->bc_y,
+                                                 p->dx, DIM == 2 ? p->dy : 1.0,
+                                                 make_consts<T>(p));
+    return launch_check("limit");
+  }
+};
+
+struct RunStep {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, void* state, void* ws, double dt_fixed,
+                          double t_end, double* tape, const double* replay, hipStream_t s) {
+    const WsLayout L = ws_layout(p);
+    char* w = (char*)ws;
+    double* ctrl = (double*)(w + L.ctrl);
+    const long long n = cells_of(p);
+    const Consts<T> k = make_consts<T>(p);
+    k_begin<<<1, 64, 0, s>>>(ctrl, replay);
+    if (!replay) {
+      k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>(
+          (const T*)state, n, k, ctrl, (unsigned long long*)(ctrl + 8));
+    }
+    StageArgs<T> a = base_args<T, PHYS, DIM>(p);
+    a.ctrl = ctrl;
+    a.status = (unsigned long long*)(ctrl + 8);
+    a.st0 = (const T*)state;
+    a.base = (T*)(w + L.base);
+    a.dt_fixed = dt_fixed;
+    a.t_end = t_end;
+    a.replay = replay ? 1 : 0;
+    T* s1 = (T*)(w + L.s1);
+    T* s2 = (T*)(w + L.s2);
+    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY;
+    const dim3 grid = stage_grid(DIM, a.nx, a.ny);
+    a.in = (const T*)state;
+    a.out = s1;
+    k_stage<T, PHYS, DIM, 1, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    a.in = s1;
+    a.out = s2;
+    k_stage<T, PHYS, DIM, 2, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    a.in = s2;
+    a.out = (T*)state;
+    k_stage<T, PHYS, DIM, 3, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    k_finish<<<1, 64, 0, s>>>(ctrl, tape);
+    return launch_check("rk3_step");
+  }
+};
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+hweno_status hweno_validate(const hweno_problem* prob) { return validate(prob); }
+
+size_t hweno_workspace_bytes(const hweno_problem* prob) {
+  if (validate(prob) != HWENO_OK) return 0;
+  return ws_layout(prob).total;
+}
+
+hweno_status hweno_alpha(const hweno_problem* prob, const void* state, double* alpha,
+                         void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state || !alpha) return fail(HWENO_ERR_INVALID_ARG, "state and alpha must be non-NULL");
+  st = dispatch<RunAlpha>(prob, state, alpha, (unsigned long long*)nullptr, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_rhs(const hweno_problem* prob, const void* state, void* rhs,
+                       double* alpha, int32_t compute_alpha, void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state || !rhs || !alpha) return fail(HWENO_ERR_INVALID_ARG, "state, rhs and alpha must be non-NULL");
+  if (state == rhs) return fail(HWENO_ERR_INVALID_ARG, "state and rhs must not alias");
+  st = dispatch<RunRhs>(prob, state, rhs, alpha, (int)compute_alpha, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_limit(const hweno_problem* prob, const void* state, void* dlim,
+                         void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state || !dlim) return fail(HWENO_ERR_INVALID_ARG, "state and dlim must be non-NULL");
+  st = dispatch<RunLimit>(prob, state, dlim, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws, size_t ws_bytes,
+                            double dt_fixed, double t_end, double* tape, const double* replay,
+                            void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state || !ws) return fail(HWENO_ERR_INVALID_ARG, "state and ws must be non-NULL");
+  const size_t need = ws_layout(prob).total;
+  if (ws_bytes < need)
+    return fail(HWENO_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (((uintptr_t)ws & 255u) != 0) return fail(HWENO_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
+    return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
+  st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end, tape, replay, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, const double* alpha,
+                               const void* lam_rhs, const void* lam_lim, void* lam_state,
+                               void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  (void)state; (void)alpha; (void)lam_rhs; (void)lam_lim; (void)lam_state; (void)stream;
+  return fail(HWENO_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+const char* hweno_status_string(int32_t s) {
+  switch (s) {
+    case HWENO_OK: return "HWENO_OK";
+    case HWENO_ERR_INVALID_ARG: return "HWENO_ERR_INVALID_ARG";
+    case HWENO_ERR_UNSUPPORTED: return "HWENO_ERR_UNSUPPORTED";
+    case HWENO_ERR_WORKSPACE: return "HWENO_ERR_WORKSPACE";
+    case HWENO_ERR_LAUNCH: return "HWENO_ERR_LAUNCH";
+    default: return "HWENO_ERR_UNKNOWN";
+  }
+}
+
+const char* hweno_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// Device math of the L-HWENO hot path for gfx950 (header-only, templated on
+// the real type).  Zhang & Zhao, arXiv 2207.05258, Section 2.
+//
+// Everything here is per-lane scalar code: the stencil work is a VALU problem
+// (every interface has its own 4x4 eigenbasis, so there is no shared-operand
+// contraction for MFMA).  The formulas are rearranged for few divisions:
+//   * the convex combination of Sections 2.1/2.2 is evaluated with a single
+//     division in FP64 (numerator and denominator scaled by the product of
+//     the three (beta_l + eps)) and with hardware reciprocals in FP32;
+//   * the Euler characteristic projection L = R^{-1} and back projection R
+//     use the closed-form eigenvectors and their shared sub-expressions;
+//   * the linear derivative flux h-hat = p0'^+ + p0'^- is pre-combined over
+//     the four stencil points (one set of coefficients on F, U, A U_n, U_n).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hweno {
+
+enum { PH_LINADV = 0, PH_BURGERS = 1, PH_EULER = 2 };
+
+template <int PHYS, int DIM>
+struct Comps {
+  static constexpr int M = (PHYS == PH_EULER) ? (DIM == 1 ? 3 : 4) : 1;
+  static constexpr int NF = M * (1 + DIM);
+};
+
+template <typename T>
+struct Weights {
+  T g0, g1, g2;  // linear weights, positive, summing to one
+  T eps;         // epsilon of the nonlinear weights
+};
+
+template <typename T>
+struct Consts {
+  Weights<T> rw;  // reconstruction weights gamma_l (Section 2.1)
+  Weights<T> lw;  // limiter weights d_l (Section 2.2)
+  T gm1;          // gamma_gas - 1
+  T gam;          // gamma_gas
+  T ax, ay;       // advection speeds (linear advection)
+  int characteristic;
+  int limiter_on;
+};
+
+template <typename T>
+__device__ __forceinline__ T fast_rcp(T x);
+template <>
+__device__ __forceinline__ float fast_rcp<float>(float x) {
+  return __builtin_amdgcn_rcpf(x);
+}
+template <>
+__device__ __forceinline__ double fast_rcp<double>(double x) {
+  return 1.0 / x;
+}
+
+// ---------------------------------------------------------------------------
+// Convex combination shared by the reconstruction (Section 2.1) and the
+// limiter (Section 2.2):
+//   tau = (|b0-b1| + |b0-b2|)^2 / 4,  wbar_l = g_l (1 + tau/(b_l + eps)),
+//   result = w0 (P0/g0 - g1/g0 P1 - g2/g0 P2) + w1 P1 + w2 P2, w = wbar/sum.
+// With e_l = 1 + tau/(b_l+eps) this is
+//   (e0 P0 + g1 P1 (e1-e0) + g2 P2 (e2-e0)) / (g0 e0 + g1 e1 + g2 e2).
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T combine(T P0, T P1, T P2, T b0, T b1, T b2,
+                                     const Weights<T>& w) {
+  T tau = fabs(b0 - b1) + fabs(b0 - b2);
+  tau = T(0.25) * tau * tau;
+  const T c0 = b0 + w.eps, c1 = b1 + w.eps, c2 = b2 + w.eps;
+  if constexpr (sizeof(T) == 8) {
+    // multiply numerator and denominator by c0 c1 c2: one division
+    const T E0 = (c0 + tau) * (c1 * c2);
+    const T E1 = (c1 + tau) * (c0 * c2);
+    const T E2 = (c2 + tau) * (c0 * c1);
+    const T num = E0 * P0 + tau * (w.g1 * P1 * c2 * (c0 - c1) +
+                                   w.g2 * P2 * c1 * (c0 - c2));
+    const T den = w.g0 * E0 + w.g1 * E1 + w.g2 * E2;
+    return num / den;
+  } else {
+    const T e0 = T(1) + tau * fast_rcp(c0);
+    const T e1 = T(1) + tau * fast_rcp(c1);
+    const T e2 = T(1) + tau * fast_rcp(c2);
+    const T num = e0 * P0 + w.g1 * P1 * (e1 - e0) + w.g2 * P2 * (e2 - e0);
+    const T den = w.g0 * e0 + w.g1 * e1 + w.g2 * e2;
+    return num * fast_rcp(den);
+  }
+}
+
+// Nonlinear HWENO value at x_{i+1/2} from the upwind ("+") data
+// f_{i-1}, f_i, f_{i+1} and H_l = dx h_l (Section 2.1): candidate values of
+// the quintic p0 and quadratics p1, p2, their smoothness indicators (beta2
+// from its integral definition, eq. GHYZ) and the combination above.
+template <typename T>
+__device__ __forceinline__ T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
+                                     const Weights<T>& w) {
+  const T s = fm + fp, dl = fm - fp, lap = s - T(2) * f0;
+  const T Hs = Hm + Hp, Hd = Hm - Hp;
+  const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
+  const T p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
+  const T p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
+  // monomial coefficients of p0 in (x - x_i)/dx
+  const T a1 = T(19.0 / 192.0) * Hs + T(79.0 / 48.0) * H0 + T(27.0 / 64.0) * dl;
+  const T a2 = T(0.375) * Hd + T(1.25) * lap;
+  const T a3 = -(T(11.0 / 24.0) * Hs + T(17.0 / 6.0) * H0) - T(1.875) * dl;
+  const T a4 = T(-0.25) * Hd - T(0.5) * lap;
+  const T a5 = T(0.25) * Hs + H0 + T(0.75) * dl;
+  const T t0 = a1 + T(0.25) * a3 + T(0.0625) * a5;
+  const T t1 = a2 + T(63.0 / 130.0) * a4;
+  const T t2 = a3 + T(8825.0 / 10934.0) * a5;
+  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * t2 * t2 +
+               T(1421461.0 / 2275.0) * a4 * a4 +
+               T(21520059541.0 / 1377684.0) * a5 * a5;
+  const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp, h2 = H0 * H0;
+  const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
+  const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
+  return combine(p0, p1, p2, b0, b1, b2, w);
+}
+
+// HWENO limiter value v~_i (Section 2.2) from u_{i-1}, u_i, u_{i+1},
+// v_{i-1}, v_{i+1}: quartic q0 and linear q1, q2, their derivatives at x_i
+// and smoothness indicators.  h = dx, ih = 1/dx.
+template <typename T>
+__device__ __forceinline__ T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
+                                    const Weights<T>& w) {
+  const T Vs = h * (vm + vp), Vd = h * (vm - vp);
+  const T lap = um - T(2) * u0 + up;
+  const T a1 = T(0.75) * (up - um) - T(0.25) * Vs;  // = dx q0'(x_i)
+  const T a2 = T(0.25) * Vd + lap;
+  const T a3 = T(0.25) * Vs + T(0.25) * (um - up);
+  const T a4 = T(-0.25) * Vd - T(0.5) * lap;
+  const T t0 = a1 + T(0.25) * a3;
+  const T t1 = a2 + T(63.0 / 130.0) * a4;
+  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * a3 * a3 +
+               T(1421461.0 / 2275.0) * a4 * a4;
+  const T d1 = u0 - um, d2 = up - u0;
+  return combine(a1 * ih, d1 * ih, d2 * ih, b0, d1 * d1, d2 * d2, w);
+}
+
+// ---------------------------------------------------------------------------
+// Physics in a normal-direction frame.  For 2D Euler the components are
+// ordered (rho, m_n, m_t, E): normal momentum first, so one code path serves
+// both directions (y swaps the two momenta on load and store).
+// ---------------------------------------------------------------------------
+
+// flux F_n(U) and the chain-rule products A_n(U) Dn and A_n(U) Dt
+// (h, xi, eta, theta of eq. EQ3), for one stencil point.
+template <typename T, int PHYS, int M, bool MIXED>
+__device__ __forceinline__ void point_fluxes(const T* U, const T* Dn, const T* Dt,
+                                             const Consts<T>& k, T an, T* F,
+                                             T* A, T* B) {
+  if constexpr (PHYS == PH_EULER) {
+    const T ir = T(1) / U[0];
+    const T un = U[1] * ir;
+    const T ut = (M == 4) ? U[2] * ir : T(0);
+    const T E = U[M - 1];
+    const T q2 = un * un + ut * ut;
+    const T p = k.gm1 * (E - T(0.5) * U[0] * q2);
+    const T Ep = E + p;
+    F[0] = U[1];
+    F[1] = U[1] * un + p;
+    if constexpr (M == 4) F[2] = U[1] * ut;
+    F[M - 1] = un * Ep;
+    auto jvp = [&](const T* D, T* out) {
+      const T r = D[0], a = D[1], b = (M == 4) ? D[2] : T(0), e = D[M - 1];
+      const T us = (a - un * r) * ir;
+      const T ts = (b - ut * r) * ir;
+      const T ps = k.gm1 * (e - un * a - ut * b + T(0.5) * q2 * r);
+      out[0] = a;
+      out[1] = a * un + U[1] * us + ps;
+      if constexpr (M == 4) out[2] = a * ut + U[1] * ts;
+      out[M - 1] = us * Ep + un * (e + ps);
+    };
+    jvp(Dn, A);
+    if constexpr (MIXED) jvp(Dt, B);
+  } else if constexpr (PHYS == PH_BURGERS) {
+    F[0] = T(0.5) * U[0] * U[0];
+    A[0] = U[0] * Dn[0];
+    if constexpr (MIXED) B[0] = U[0] * Dt[0];
+  } else {
+    F[0] = an * U[0];
+    A[0] = an * Dn[0];
+    if constexpr (MIXED) B[0] = an * Dt[0];
+  }
+}
+
+// Roe-averaged eigen-system of the normal flux Jacobian: right eigenvectors
+// (1, un-c, ut, H-un c), (1, un, ut, q^2/2), (0, 0, 1, ut), (1, un+c, ut, H+un c)
+// (1D drops ut), left eigenvectors = their inverse in closed form.
+template <typename T, int M>
+struct Eigen {
+  T un, ut, H, c, ic, b1, b2, hq2;
+
+  __device__ __forceinline__ void roe(const T* UL, const T* UR, T gm1) {
+    const T irL = T(1) / UL[0], irR = T(1) / UR[0];
+    const T sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+    const T uL = UL[1] * irL, uR = UR[1] * irR;
+    const T tL = (M == 4) ? UL[2] * irL : T(0), tR = (M == 4) ? UR[2] * irR : T(0);
+    const T pL = gm1 * (UL[M - 1] - T(0.5) * UL[0] * (uL * uL + tL * tL));
+    const T pR = gm1 * (UR[M - 1] - T(0.5) * UR[0] * (uR * uR + tR * tR));
+    const T HL = (UL[M - 1] + pL) * irL, HR = (UR[M - 1] + pR) * irR;
+    const T iw = T(1) / (sL + sR);
+    const T wL = sL * iw, wR = sR * iw;
+    un = wL * uL + wR * uR;
+    ut = wL * tL + wR * tR;
+    H = wL * HL + wR * HR;
+    const T q2 = un * un + ut * ut;
+    hq2 = T(0.5) * q2;
+    c = sqrt(gm1 * (H - hq2));
+    ic = T(1) / c;
+    b1 = gm1 * ic * ic;
+    b2 = b1 * hq2;
+  }
+
+  // w = L x
+  __device__ __forceinline__ void project(const T* x, T* w) const {
+    if constexpr (M == 4) {
+      const T phi = b2 * x[0] - b1 * (un * x[1] + ut * x[2] - x[3]);
+      const T psi = (un * x[0] - x[1]) * ic;
+      w[0] = T(0.5) * (phi + psi);
+      w[1] = x[0] - phi;
+      w[2] = x[2] - ut * x[0];
+      w[3] = T(0.5) * (phi - psi);
+    } else {
+      const T phi = b2 * x[0] - b1 * (un * x[1] - x[2]);
+      const T psi = (un * x[0] - x[1]) * ic;
+      w[0] = T(0.5) * (phi + psi);
+      w[1] = x[0] - phi;
+      w[2] = T(0.5) * (phi - psi);
+    }
+  }
+
+  // y = R w
+  __device__ __forceinline__ void back(const T* w, T* y) const {
+    if constexpr (M == 4) {
+      const T s = w[0] + w[1] + w[3], dif = w[3] - w[0];
+      y[0] = s;
+      y[1] = un * s + c * dif;
+      y[2] = ut * s + w[2];
+      y[3] = H * (w[0] + w[3]) + un * c * dif + hq2 * w[1] + ut * w[2];
+    } else {
+      const T s = w[0] + w[1] + w[2], dif = w[2] - w[0];
+      y[0] = s;
+      y[1] = un * s + c * dif;
+      y[2] = H * (w[0] + w[2]) + un * c * dif + hq2 * w[1];
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// All fluxes of one interface x_{i+1/2} along the normal direction.
+// Stencil points s = 0..3 are x_{i-1}, x_i, x_{i+1}, x_{i+2};
+// ld(s, U, Dn, Dt) loads the state of point s in the normal frame.
+// Outputs (normal frame): fh = f-hat (nonlinear, Section 2.1 with Remarks
+// 2.1/2.2), hh = h-hat (linear p0'^+ + p0'^-, component-wise), xh = the
+// mixed flux of eq. (mixed) (only when MIXED).
+//   alpha: global LF speed of this direction; h: cell size; ih = 1/h.
+// ---------------------------------------------------------------------------
+template <typename T, int PHYS, int M, bool MIXED, typename Loader>
+__device__ __forceinline__ void interface_fluxes(const Loader& ld, T alpha, T h,
+                                                 T ih, T an, const Consts<T>& k,
+                                                 T* fh, T* hh, T* xh) {
+  constexpr bool CHARW = (PHYS == PH_EULER);
+  Eigen<T, M> eg;
+  const bool proj = CHARW && k.characteristic;
+  if constexpr (CHARW) {
+    if (proj) {
+      T UL[M], UR[M], dn[M], dt[M];
+      ld(1, UL, dn, dt);
+      ld(2, UR, dn, dt);
+      eg.roe(UL, UR, k.gm1);
+    }
+  }
+  // split point data in characteristic fields: "+" side uses s = 0..2,
+  // "-" side uses s = 1..3 (stored at s-1)
+  T fP[3][M], HP[3][M], fM[3][M], HM[3][M];
+  // linear derivative flux h-hat = p0'^+(f^+, h^+) + mirrored p0'^-(f^-, h^-),
+  // expanded with f^+- = (F +- alpha U)/2, h^+- = (A Dn +- alpha Dn)/2:
+  //   [F0 - 15F1 + 15F2 - F3 + alpha (U0 - U1 - U2 + U3)] / (8 dx)
+  // + [A0 - 7A1 - 7A2 + A3 + alpha (D0 + 3D1 - 3D2 - D3)] / 24
+  constexpr T cF[4] = {T(1), T(-15), T(15), T(-1)};
+  constexpr T cU[4] = {T(1), T(-1), T(-1), T(1)};
+  constexpr T cA[4] = {T(1), T(-7), T(-7), T(1)};
+  constexpr T cD[4] = {T(1), T(3), T(-3), T(-1)};
+  constexpr T cX[4] = {T(-1), T(7), T(7), T(-1)};
+  T sF[M], sA[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    sF[c] = T(0);
+    sA[c] = T(0);
+    if constexpr (MIXED) xh[c] = T(0);
+  }
+  const T hh2 = T(0.5) * h;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
+    ld(s, U, Dn, Dt);
+    point_fluxes<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, F, A, B);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      sF[c] += cF[s] * F[c] + alpha * cU[s] * U[c];
+      sA[c] += cA[s] * A[c] + alpha * cD[s] * Dn[c];
+      if constexpr (MIXED) xh[c] += cX[s] * B[c];
+    }
+    if (s <= 2) {
+      T x[M], y[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        x[c] = T(0.5) * (F[c] + alpha * U[c]);
+        y[c] = hh2 * (A[c] + alpha * Dn[c]);
+      }
+      if (proj) {
+        eg.project(x, fP[s]);
+        eg.project(y, HP[s]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          fP[s][c] = x[c];
+          HP[s][c] = y[c];
+        }
+      }
+    }
+    if (s >= 1) {
+      T x[M], y[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        x[c] = T(0.5) * (F[c] - alpha * U[c]);
+        y[c] = hh2 * (A[c] - alpha * Dn[c]);
+      }
+      if (proj) {
+        eg.project(x, fM[s - 1]);
+        eg.project(y, HM[s - 1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          fM[s - 1][c] = x[c];
+          HM[s - 1][c] = y[c];
+        }
+      }
+    }
+  }
+  T fc[M];
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    // "+" at x_{i+1/2} from i-1, i, i+1; "-" mirrored: i+2, i+1, i with
+    // derivative data negated (reflection about the interface)
+    fc[c] = hw_plus(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw) +
+            hw_plus(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw);
+  }
+  if (proj) {
+    eg.back(fc, fh);
+  } else {
+#pragma unroll
+    for (int c = 0; c < M; ++c) fh[c] = fc[c];
+  }
+  const T i8 = T(0.125) * ih;
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    hh[c] = sF[c] * i8 + sA[c] * T(1.0 / 24.0);
+    if constexpr (MIXED) xh[c] *= T(1.0 / 12.0);
+  }
+}
+
+// wave speeds |u_n| + c (Euler), |u| (Burgers), |a| (linear advection) of
+// one point in each direction, plus admissibility flags.
+template <typename T, int PHYS, int DIM>
+__device__ __forceinline__ void point_speeds(const T* U, const Consts<T>& k,
+                                             T& sx, T& sy, uint32_t& flags) {
+  if constexpr (PHYS == PH_EULER) {
+    constexpr int M = Comps<PHYS, DIM>::M;
+    const T r = U[0];
+    const T ir = T(1) / r;
+    const T u = U[1] * ir;
+    const T v = (DIM == 2) ? U[2] * ir : T(0);
+    const T p = k.gm1 * (U[M - 1] - T(0.5) * r * (u * u + v * v));
+    const T c = sqrt(k.gam * p * ir);
+    sx = fabs(u) + c;
+    sy = (DIM == 2) ? fabs(v) + c : T(0);
+    bool fin = true;
+#pragma unroll
+    for (int q = 0; q < M; ++q) fin = fin && isfinite(U[q]);
+    if (!fin) flags |= 1u;
+    if (!(r > T(0))) flags |= 2u;
+    if (!(p > T(0))) flags |= 4u;
+  } else if constexpr (PHYS == PH_BURGERS) {
+    sx = fabs(U[0]);
+    sy = (DIM == 2) ? sx : T(0);
+    if (!isfinite(U[0])) flags |= 1u;
+  } else {
+    sx = fabs(k.ax);
+    sy = (DIM == 2) ? fabs(k.ay) : T(0);
+    if (!isfinite(U[0])) flags |= 1u;
+  }
+}
+
+}  // namespace hweno

@@ -1,0 +1,256 @@
+"""Thin Python binding of the C ABI in include/hweno.h.
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Arrays are torch tensors on the GPU; the current torch stream is
+passed to every call.  There is no CPU fallback: if the library is missing
+the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhweno.so")
+
+HWENO_OK = 0
+CTRL_LEN = 16
+ST_NONFINITE, ST_RHO, ST_PRESSURE, ST_SKIPPED = 1, 2, 4, 8
+
+PHYSICS = {"linadv": 0, "burgers": 1, "euler": 2}
+DTYPES = {torch.float32: 0, torch.float64: 1}
+PERIODIC, OUTFLOW = 0, 1
+
+
+class HwenoError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {_status_name(code)}: {detail}")
+        self.code = code
+
+
+class _CProblem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("physics", ctypes.c_int32), ("dtype", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("characteristic", ctypes.c_int32), ("limiter_on", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("gamma_gas", ctypes.c_double), ("adv_speed", ctypes.c_double * 2),
+        ("lin_w", ctypes.c_double * 3), ("lim_w", ctypes.c_double * 3),
+        ("eps", ctypes.c_double), ("cfl", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libhweno.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_2207_05258_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(_CProblem)
+        vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
+        sig = {
+            "hweno_validate": ([P], ctypes.c_int),
+            "hweno_workspace_bytes": ([P], ctypes.c_size_t),
+            "hweno_alpha": ([P, vp, vp, vp], ctypes.c_int),
+            "hweno_rhs": ([P, vp, vp, vp, ctypes.c_int32, vp], ctypes.c_int),
+            "hweno_limit": ([P, vp, vp, vp], ctypes.c_int),
+            "hweno_rk3_step": ([P, vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
+                                vp, vp, vp], ctypes.c_int),
+            "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+            "hweno_status_string": ([ctypes.c_int32], ctypes.c_char_p),
+            "hweno_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _status_name(code: int) -> str:
+    return lib().hweno_status_string(code).decode()
+
+
+def _check(code: int, where: str):
+    if code != HWENO_OK:
+        raise HwenoError(code, where, lib().hweno_last_error().decode())
+
+
+@dataclass
+class Problem:
+    """Parameters of a discretised problem (mirrors hweno_problem)."""
+
+    dim: int
+    nx: int
+    ny: int = 1
+    physics: str = "euler"
+    dtype: torch.dtype = torch.float64
+    dx: float = 1.0
+    dy: float = 1.0
+    bc_x: int = PERIODIC
+    bc_y: int = PERIODIC
+    characteristic: bool = True
+    limiter_on: bool = True
+    gamma_gas: float = 1.4
+    adv_speed: Tuple[float, float] = (1.0, 1.0)
+    lin_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)
+    lim_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)
+    eps: float = 1e-6
+    cfl: float = 0.6
+
+    @property
+    def m(self) -> int:
+        if self.physics == "euler":
+            return 3 if self.dim == 1 else 4
+        return 1
+
+    @property
+    def nf(self) -> int:
+        return self.m * (1 + self.dim)
+
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nf, self.ny if self.dim == 2 else 1, self.nx)
+
+    def c(self) -> _CProblem:
+        p = _CProblem()
+        p.dim, p.nx, p.ny = self.dim, self.nx, (self.ny if self.dim == 2 else 1)
+        p.physics = PHYSICS[self.physics]
+        p.dtype = DTYPES[self.dtype]
+        p.bc_x, p.bc_y = int(self.bc_x), int(self.bc_y)
+        p.characteristic = int(bool(self.characteristic))
+        p.limiter_on = int(bool(self.limiter_on))
+        p.dx, p.dy = float(self.dx), float(self.dy)
+        p.gamma_gas = float(self.gamma_gas)
+        p.adv_speed[:] = [float(x) for x in self.adv_speed]
+        p.lin_w[:] = [float(x) for x in self.lin_w]
+        p.lim_w[:] = [float(x) for x in self.lim_w]
+        p.eps, p.cfl = float(self.eps), float(self.cfl)
+        return p
+
+
+def problem_for(S: torch.Tensor, dim: int, physics: str, dx: float, dy: float = 1.0,
+                **kw) -> Problem:
+    nf, ny, nx = S.shape
+    return Problem(dim=dim, nx=nx, ny=ny, physics=physics, dtype=S.dtype, dx=dx, dy=dy, **kw)
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _require(t: torch.Tensor, prob: Problem, nfields: int, what: str):
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a GPU tensor")
+    if t.dtype != prob.dtype:
+        raise ValueError(f"{what} dtype {t.dtype} does not match the problem's {prob.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    ny = prob.ny if prob.dim == 2 else 1
+    if t.numel() != nfields * ny * prob.nx:
+        raise ValueError(f"{what} has {t.numel()} values, expected {nfields}x{ny}x{prob.nx}")
+
+
+def validate(prob: Problem):
+    _check(lib().hweno_validate(ctypes.byref(prob.c())), "hweno_validate")
+
+
+def workspace_bytes(prob: Problem) -> int:
+    return int(lib().hweno_workspace_bytes(ctypes.byref(prob.c())))
+
+
+def alpha(S: torch.Tensor, prob: Problem, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Global Lax-Friedrichs speeds (alpha_x, alpha_y) as a float64 device tensor."""
+    _require(S, prob, prob.nf, "state")
+    a = out if out is not None else torch.zeros(2, dtype=torch.float64, device=S.device)
+    _check(lib().hweno_alpha(ctypes.byref(prob.c()), _ptr(S), _ptr(a), _stream()), "hweno_alpha")
+    return a
+
+
+def rhs(S: torch.Tensor, prob: Problem, alpha_: Optional[torch.Tensor] = None,
+        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Semi-discrete right-hand side L(S); speeds computed from S unless given."""
+    _require(S, prob, prob.nf, "state")
+    L = out if out is not None else torch.empty_like(S)
+    if alpha_ is None:
+        a = torch.zeros(2, dtype=torch.float64, device=S.device)
+        compute = 1
+    else:
+        a = alpha_.to(device=S.device, dtype=torch.float64).contiguous()
+        compute = 0
+    _check(lib().hweno_rhs(ctypes.byref(prob.c()), _ptr(S), _ptr(L), _ptr(a), compute, _stream()),
+           "hweno_rhs")
+    return L
+
+
+def limit(S: torch.Tensor, prob: Problem, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Limited derivatives (U_x along x [, U_y along y]): m * dim fields."""
+    _require(S, prob, prob.nf, "state")
+    ny = prob.ny if prob.dim == 2 else 1
+    D = out if out is not None else torch.empty((prob.m * prob.dim, ny, prob.nx),
+                                                dtype=S.dtype, device=S.device)
+    _check(lib().hweno_limit(ctypes.byref(prob.c()), _ptr(S), _ptr(D), _stream()), "hweno_limit")
+    return D
+
+
+class Stepper:
+    """Owns the device workspace of hweno_rk3_step for one problem.
+
+    ``ctrl`` (float64[16] on the device) is the step control block: stage
+    speeds, last dt, simulated time t, status word, step count.
+    """
+
+    def __init__(self, prob: Problem, device="cuda", t0: float = 0.0):
+        validate(prob)
+        self.prob = prob
+        self._c = prob.c()
+        self.nbytes = max(workspace_bytes(prob), 256)
+        self.ws = torch.zeros(self.nbytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws = self.ws[off:off + self.nbytes]
+        self.ctrl = self.ws[:CTRL_LEN * 8].view(torch.float64)
+        self.ctrl[7] = t0
+
+    def step(self, S: torch.Tensor, dt: Optional[float] = None, t_end: Optional[float] = None,
+             tape: Optional[torch.Tensor] = None, replay: Optional[torch.Tensor] = None):
+        """One SSP-RK3 step of S in place (device-side dt unless ``dt`` is given)."""
+        _require(S, self.prob, self.prob.nf, "state")
+        for t, name in ((tape, "tape"), (replay, "replay")):
+            if t is not None and (t.dtype != torch.float64 or t.numel() < CTRL_LEN or not t.is_cuda):
+                raise ValueError(f"{name} must be a float64 GPU tensor of >= {CTRL_LEN} values")
+        _check(lib().hweno_rk3_step(ctypes.byref(self._c), _ptr(S), _ptr(self.ws), self.nbytes,
+                                    float(dt or 0.0), float(t_end or 0.0), _ptr(tape),
+                                    _ptr(replay), _stream()), "hweno_rk3_step")
+        return S
+
+    @property
+    def t(self) -> float:
+        return float(self.ctrl[7])
+
+    @property
+    def status(self) -> int:
+        return int(self.ctrl[8:9].view(torch.int64).item())
+
+    @property
+    def last_dt(self) -> float:
+        return float(self.ctrl[6])
+
+
+def rk3_step_(S: torch.Tensor, prob: Problem, dt: Optional[float] = None) -> torch.Tensor:
+    """One in-place step with a throw-away workspace (convenience)."""
+    return Stepper(prob, device=S.device).step(S, dt=dt)

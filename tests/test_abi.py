@@ -1,0 +1,140 @@
+"""Host-side checks of the C ABI: it loads without a GPU, exports every symbol
+declared in include/hweno.h, and rejects bad arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "hweno.h")
+
+h = pytest.importorskip("paper_2207_05258_amd")
+
+
+def _lib_or_skip():
+    if not os.path.exists(h.hweno.LIB_PATH):
+        pytest.skip("libhweno.so not built")
+    return h.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(hweno_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("hweno_rhs", "hweno_limit", "hweno_rk3_step", "hweno_rhs_adjoint",
+                     "hweno_workspace_bytes", "hweno_status_string", "hweno_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib_or_skip()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def _prob(**kw):
+    base = dict(dim=2, nx=64, ny=48, physics="euler", dx=1 / 64, dy=1 / 48)
+    base.update(kw)
+    return h.Problem(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(dim=3),
+    dict(nx=-1),
+    dict(dx=0.0),
+    dict(dy=-1.0),
+    dict(lin_w=(0.5, 0.5, 0.1)),
+    dict(lin_w=(1.0, 0.0, 0.0)),
+    dict(lim_w=(0.98, 0.02, -0.0)),
+    dict(lim_w=(0.9, 0.05, 0.05000001)),
+    dict(eps=0.0),
+    dict(cfl=-0.6),
+    dict(gamma_gas=1.0),
+    dict(bc_x=7),
+])
+def test_invalid_problems_are_rejected(bad):
+    _lib_or_skip()
+    with pytest.raises(h.HwenoError) as e:
+        h.validate(_prob(**bad))
+    assert e.value.code == 1
+    assert h.workspace_bytes(_prob(**bad)) == 0
+
+
+def test_1d_requires_ny_one():
+    L = _lib_or_skip()
+    c = _prob(dim=1).c()
+    c.ny = 5
+    assert L.hweno_validate(ctypes.byref(c)) == 1
+    c.ny = 1
+    assert L.hweno_validate(ctypes.byref(c)) == 0
+
+
+def test_weights_sum_tolerance():
+    _lib_or_skip()
+    h.validate(_prob(lin_w=(1 / 3, 1 / 3, 1 / 3), lim_w=(0.01, 0.495, 0.495)))
+    h.validate(_prob(lin_w=(0.99, 0.005, 0.005)))
+
+
+def test_workspace_bytes_layout():
+    _lib_or_skip()
+    p = _prob(nx=100, ny=30, dtype=torch.float64)
+    n = 100 * 30
+    need = h.workspace_bytes(p)
+    # control block + two stage states (12 fields) + limited base derivatives (8 fields)
+    assert need >= 128 + (2 * 12 + 8) * n * 8
+    assert need < 128 + (2 * 12 + 8) * n * 8 + 4 * 256 + 256
+    p32 = _prob(nx=100, ny=30, dtype=torch.float32)
+    assert h.workspace_bytes(p32) < need
+
+
+def test_null_pointers_and_small_workspace_are_rejected_on_host():
+    L = _lib_or_skip()
+    c = _prob().c()
+    P = ctypes.byref(c)
+    assert L.hweno_rhs(P, None, None, None, 1, None) == 1
+    assert L.hweno_limit(P, None, None, None) == 1
+    assert L.hweno_rk3_step(P, None, None, 0, 0.0, 0.0, None, None, None) == 1
+    assert "non-NULL" in L.hweno_last_error().decode()
+    # a fake (never dereferenced) pointer with a too-small workspace size
+    assert L.hweno_rk3_step(P, ctypes.c_void_p(256), ctypes.c_void_p(256), 10, 0.0, 0.0,
+                            None, None, None) == 3
+    assert L.hweno_rk3_step(P, ctypes.c_void_p(256), ctypes.c_void_p(256), 1 << 40,
+                            float("inf"), 0.0, None, None, None) == 1
+
+
+def test_empty_grid_is_a_noop_without_device_calls():
+    L = _lib_or_skip()
+    for kw in (dict(nx=0), dict(ny=0), dict(dim=1, nx=0, ny=1)):
+        c = _prob(**kw).c()
+        P = ctypes.byref(c)
+        assert L.hweno_rhs(P, None, None, None, 1, None) == 0
+        assert L.hweno_limit(P, None, None, None) == 0
+        assert L.hweno_rk3_step(P, None, None, 0, 0.0, 0.0, None, None, None) == 0
+        assert L.hweno_last_error().decode() == ""
+
+
+def test_status_strings():
+    L = _lib_or_skip()
+    assert L.hweno_status_string(0).decode() == "HWENO_OK"
+    assert L.hweno_status_string(3).decode() == "HWENO_ERR_WORKSPACE"
+    assert L.hweno_status_string(99).decode() == "HWENO_ERR_UNKNOWN"
+
+
+def test_product_package_does_not_import_the_oracle():
+    import sys
+    import subprocess
+    code = ("import sys; import paper_2207_05258_amd; "
+            "assert not any(m == 'oracle' or m.startswith('oracle.') for m in sys.modules), "
+            "'oracle imported'")
+    subprocess.run([sys.executable, "-c", code], check=True, cwd=ROOT)
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "paper_2207_05258_amd")):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f

@@ -1,0 +1,338 @@
+"""GPU parity of the HIP path against the CPU oracle, through the C ABI.
+
+Every case feeds the same seeded input to both sides (FP32 cases give the
+oracle the FP32-rounded values) and compares element by element in the norms
+of tests/parity.py: FP64 within 1e-12, FP32 within 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import hweno_inputs as hi
+from oracle import hweno_ref as o
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+h = pytest.importorskip("paper_2207_05258_amd")
+
+DTYPES = [torch.float64, torch.float32]
+
+
+def announce(*what):
+    print("\n[case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+# --------------------------------------------------------------------------
+# workloads: sizes span several tiles (32x8 in 2D, 256 in 1D) and ragged tails
+# --------------------------------------------------------------------------
+CASES = {
+    "linadv1d_sine_200": lambda: hi.scalar_sine_1d(200, "linadv"),
+    "linadv1d_neg_random_301": lambda: hi.scalar_random_1d(301, 3, "linadv", a=-0.7),
+    "burgers1d_random_517": lambda: hi.scalar_random_1d(517, 1, "burgers"),
+    "euler1d_smooth_400": lambda: hi.euler1d_smooth(400),
+    "euler1d_piecewise_4000": lambda: hi.euler1d_piecewise(4000, 0),
+    "euler1d_piecewise_777_s5": lambda: hi.euler1d_piecewise(777, 5),
+    "euler2d_quadrants_70x45": lambda: hi.euler2d_quadrants(70, 45, 0),
+    "euler2d_quadrants_periodic_65x33": lambda: hi.euler2d_quadrants(65, 33, 4, bc=hi.PERIODIC),
+    "euler2d_rsmooth_64x40": lambda: hi.euler2d_random_smooth(64, 40, 2),
+    "euler2d_rough_50x37": lambda: hi.euler2d_rough(50, 37, 3),
+    "euler2d_wave_48x48": lambda: hi.euler2d_wave(48, 48),
+    "burgers2d_sine_40x33": lambda: hi.scalar_sine_2d(40, 33, "burgers"),
+    "linadv2d_random_33x17": lambda: hi.scalar_random_2d(33, 17, 6, "linadv", a=(1.0, -0.5)),
+}
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_alpha(case, dtype):
+    w = CASES[case]()
+    announce("alpha", case, dtype)
+    Sg = P.to_gpu(w, dtype)
+    prob = P.gpu_problem(w, dtype)
+    a = h.alpha(Sg, prob).cpu()
+    ax, ay = o.max_speeds(P.exact_input(Sg), P.oracle_problem(w))
+    rel = 1e-14 if dtype == torch.float64 else 1e-6
+    assert abs(float(a[0]) - ax) <= rel * ax
+    assert abs(float(a[1]) - ay) <= rel * max(ay, 1e-300)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rhs(case, dtype):
+    w = CASES[case]()
+    announce("rhs", case, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, dtype)
+    op = P.oracle_problem(w)
+    alpha = o.max_speeds(S, op)
+    L = h.rhs(Sg, prob, torch.tensor(alpha, dtype=torch.float64))
+    Lref = o.rhs(S, op, alpha)
+    P.assert_within(P.rhs_errors(L, Lref, S, w), P.TOL[dtype], f"rhs {case}")
+    # with speeds computed on the device
+    L2 = h.rhs(Sg, prob)
+    P.assert_within(P.rhs_errors(L2, Lref, S, w), P.TOL[dtype], f"rhs(alpha on device) {case}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", ["euler1d_piecewise_777_s5", "euler2d_rough_50x37",
+                                  "euler2d_quadrants_70x45"])
+def test_rhs_componentwise(case, dtype):
+    w = CASES[case]()
+    announce("rhs componentwise", case, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, dtype, characteristic=False)
+    op = P.oracle_problem(w, characteristic=False)
+    alpha = o.max_speeds(S, op)
+    L = h.rhs(Sg, prob, torch.tensor(alpha, dtype=torch.float64))
+    P.assert_within(P.rhs_errors(L, o.rhs(S, op, alpha), S, w), P.TOL[dtype], case)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_limit(case, dtype):
+    w = CASES[case]()
+    announce("limit", case, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    D = h.limit(Sg, P.gpu_problem(w, dtype))
+    Dref = o.limited_derivatives(S, P.oracle_problem(w))
+    P.assert_within(P.limit_errors(D, Dref, S, w), P.TOL[dtype], f"limit {case}")
+
+
+@pytest.mark.parametrize("weights", [((1 / 3, 1 / 3, 1 / 3), (0.01, 0.495, 0.495)),
+                                     ((0.01, 0.495, 0.495), (0.99, 0.005, 0.005))])
+def test_rhs_and_limit_other_linear_weights(weights):
+    lin, lim = weights
+    w = hi.euler2d_rough(40, 24, 9)
+    announce("weights", lin, lim)
+    Sg = P.to_gpu(w, torch.float64)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, torch.float64, lin_w=lin, lim_w=lim)
+    op = P.oracle_problem(w, lin_w=lin, lim_w=lim)
+    alpha = o.max_speeds(S, op)
+    L = h.rhs(Sg, prob, torch.tensor(alpha, dtype=torch.float64))
+    P.assert_within(P.rhs_errors(L, o.rhs(S, op, alpha), S, w), 1e-12, "rhs weights")
+    D = h.limit(Sg, prob)
+    P.assert_within(P.limit_errors(D, o.limited_derivatives(S, op), S, w), 1e-12, "limit weights")
+
+
+def _step_case(w, dtype, dt=None, **kw):
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, dtype, **kw)
+    op = P.oracle_problem(w, **kw)
+    st = h.Stepper(prob)
+    st.step(Sg, dt=dt)
+    ctrl = st.ctrl.cpu()
+    ref, dt_ref, alphas = o.rk3_step(S, op, dt)
+    return Sg, ref, ctrl, dt_ref, alphas
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_rk3_step(case, dtype):
+    w = CASES[case]()
+    announce("rk3_step", case, dtype)
+    out, ref, ctrl, dt_ref, alphas = _step_case(w, dtype)
+    rel = 1e-13 if dtype == torch.float64 else 1e-6
+    assert abs(float(ctrl[6]) - dt_ref) <= rel * dt_ref, (float(ctrl[6]), dt_ref)
+    for k in range(3):
+        for d in range(w.dim):
+            a = alphas[k][d]
+            assert abs(float(ctrl[2 * k + d]) - a) <= max(rel, P.TOL[dtype]) * a
+    assert float(ctrl[7]) == pytest.approx(float(ctrl[6]), rel=1e-15)
+    assert int(ctrl[8:9].view(torch.int64)) == 0
+    assert float(ctrl[9]) == 1.0
+    P.assert_within(P.step_errors(out, ref, w), P.TOL[dtype], f"step {case}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", ["euler2d_quadrants_70x45", "euler1d_piecewise_777_s5",
+                                  "burgers2d_sine_40x33"])
+def test_rk3_step_without_limiter(case, dtype):
+    w = CASES[case]()
+    announce("rk3_step limiter off", case, dtype)
+    out, ref, *_ = _step_case(w, dtype, limiter_on=False)
+    P.assert_within(P.step_errors(out, ref, w), P.TOL[dtype], f"step nolim {case}")
+
+
+def test_rk3_step_fixed_dt_and_clipping():
+    w = hi.euler2d_random_smooth(40, 30, 7)
+    announce("fixed dt + t_end")
+    Sg = P.to_gpu(w, torch.float64)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, torch.float64)
+    st = h.Stepper(prob)
+    st.step(Sg, dt=1e-3)
+    ref, _, _ = o.rk3_step(S, P.oracle_problem(w), 1e-3)
+    P.assert_within(P.step_errors(Sg, ref, w), 1e-12, "fixed dt")
+    # clip to t_end: t = 1e-3 now; t_end = 1.25e-3 gives a 2.5e-4 step
+    st.step(Sg, t_end=1.25e-3)
+    assert float(st.ctrl[6]) == pytest.approx(2.5e-4, rel=1e-12)
+    ref, _, _ = o.rk3_step(ref, P.oracle_problem(w), 2.5e-4)
+    P.assert_within(P.step_errors(Sg, ref, w), 1e-12, "clipped dt")
+    # at t >= t_end the step is skipped and flagged
+    before = Sg.clone()
+    st.step(Sg, t_end=1.25e-3)
+    assert torch.equal(before, Sg)
+    assert st.status & h.hweno.ST_SKIPPED
+    assert float(st.ctrl[9]) == 2.0
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_several_steps_euler2d(dtype):
+    w = hi.euler2d_quadrants(64, 48, 1)
+    announce("5 steps", dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    st = h.Stepper(P.gpu_problem(w, dtype))
+    op = P.oracle_problem(w)
+    for _ in range(5):
+        st.step(Sg)
+        S, _, _ = o.rk3_step(S, op)
+    errs = P.step_errors(Sg, S, w)
+    # drift over several steps is reported, gated a little above the per-step bar
+    P.assert_within(errs, 10 * P.TOL[dtype], "5 steps")
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 5])
+@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.OUTFLOW])
+def test_tiny_grids(n, bc):
+    announce("tiny", n, bc)
+    w1 = hi.euler1d_piecewise(n, 2)
+    w1.bc_x = bc
+    w2 = hi.euler2d_rough(n, n + 1, 5, bc=bc)
+    for w in (w1, w2):
+        out, ref, *_ = _step_case(w, torch.float64)
+        P.assert_within(P.step_errors(out, ref, w), 1e-12, f"tiny {w.name}")
+
+
+def test_constant_state_is_stationary_bitwise():
+    w = hi.euler2d_quadrants(67, 35, 0)
+    announce("constant")
+    S = w.S.copy()
+    S[:4] = S[:4, :1, :1]
+    S[4:] = 0.0
+    w.S = S
+    for dtype in DTYPES:
+        Sg = P.to_gpu(w, dtype)
+        prob = P.gpu_problem(w, dtype)
+        assert float(h.rhs(Sg, prob).abs().max()) == 0.0
+        assert float(h.limit(Sg, prob).abs().max()) == 0.0
+        before = Sg.clone()
+        h.Stepper(prob).step(Sg)
+        # L == 0 exactly; the Runge-Kutta combinations 3/4 x + 1/4 x and
+        # 1/3 x + 2/3 x reproduce x only up to rounding
+        eps = torch.finfo(dtype).eps
+        assert float((before - Sg).abs().max()) <= 4 * eps * float(before.abs().max())
+        assert float(Sg[4:].abs().max()) == 0.0
+
+
+def test_periodic_conservation_and_determinism():
+    w = hi.euler2d_quadrants(96, 80, 2, bc=hi.PERIODIC)
+    announce("conservation")
+    Sg = P.to_gpu(w, torch.float64)
+    S2 = Sg.clone()
+    tot0 = Sg[:4].sum(dim=(1, 2))
+    st1, st2 = h.Stepper(P.gpu_problem(w, torch.float64)), h.Stepper(P.gpu_problem(w, torch.float64))
+    for _ in range(10):
+        st1.step(Sg)
+        st2.step(S2)
+    assert torch.equal(Sg, S2)
+    assert torch.allclose(Sg[:4].sum(dim=(1, 2)), tot0, rtol=1e-13, atol=1e-10)
+
+
+def test_tape_and_replay_reproduce_the_step():
+    w = hi.euler2d_rough(45, 38, 12)
+    announce("tape/replay")
+    Sg = P.to_gpu(w, torch.float64)
+    S0 = Sg.clone()
+    prob = P.gpu_problem(w, torch.float64)
+    tape = torch.zeros(h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    h.Stepper(prob).step(Sg, tape=tape)
+    S1 = S0.clone()
+    h.Stepper(prob).step(S1, replay=tape)
+    assert torch.equal(Sg, S1)
+    # replayed speeds are used as given
+    fake = tape.clone()
+    fake[0:6] *= 1.5
+    S2 = S0.clone()
+    h.Stepper(prob).step(S2, replay=fake)
+    ref, _, _ = o.rk3_step(P.exact_input(S0), P.oracle_problem(w), float(tape[6]),
+                           [tuple(fake[0:2].tolist()), tuple(fake[2:4].tolist()),
+                            tuple(fake[4:6].tolist())])
+    P.assert_within(P.step_errors(S2, ref, w), 1e-12, "replay")
+
+
+def test_status_word_flags_inadmissible_states():
+    w = hi.euler2d_quadrants(40, 40, 3)
+    announce("status")
+    Sg = P.to_gpu(w, torch.float64)
+    # negative pressure in one cell: E below the kinetic energy
+    Sg[3, 10, 11] = 0.5 * Sg[1, 10, 11] ** 2 / Sg[0, 10, 11] - 0.1
+    st = h.Stepper(P.gpu_problem(w, torch.float64))
+    st.step(Sg)
+    assert st.status & h.hweno.ST_PRESSURE
+    # NaN input: speeds become NaN, the step is skipped and flagged
+    Sg = P.to_gpu(w, torch.float64)
+    Sg[0, 5, 5] = float("nan")
+    st = h.Stepper(P.gpu_problem(w, torch.float64))
+    st.step(Sg)
+    assert st.status & (h.hweno.ST_NONFINITE | h.hweno.ST_SKIPPED)
+    assert np.isnan(float(st.ctrl[0]))
+
+
+# --------------------------------------------------------------------------
+# full-size grids, launched exactly as the benchmark launches them:
+# sampled windows against the oracle with the device's speeds and dt
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("n,dtype", [(1024, torch.float64), (1024, torch.float32),
+                                     (4096, torch.float64), (4096, torch.float32)],
+                         ids=["1024-f64", "1024-f32", "4096-f64", "4096-f32"])
+def test_full_size_quadrants_sampled(n, dtype):
+    w = hi.euler2d_quadrants(n, n, 0)
+    announce("full size", n, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S0 = Sg.clone()
+    prob = P.gpu_problem(w, dtype)
+    st = h.Stepper(prob)
+    st.step(Sg)
+    ctrl = st.ctrl.cpu()
+    alphas = [(float(ctrl[0]), float(ctrl[1])), (float(ctrl[2]), float(ctrl[3])),
+              (float(ctrl[4]), float(ctrl[5]))]
+    dt = float(ctrl[6])
+    ax, ay = o.max_speeds(P.exact_input(S0[:4]), o.Problem(dim=2, physics="euler"))
+    assert abs(alphas[0][0] - ax) <= 1e-6 * ax and abs(alphas[0][1] - ay) <= 1e-6 * ay
+    half, m, k = n // 2, 8, 24
+    rng = np.random.default_rng(0)
+    spots = [(half - k // 2, half - k // 2), (0, 0), (n - k, n - k), (0, half - k // 2),
+             (half - k // 2, n - k)] + [tuple(int(v) for v in rng.integers(m, n - k - m, 2))
+                                        for _ in range(3)]
+    for (j, i) in spots:
+        j0, j1 = max(j - m, 0), min(j + k + m, n)
+        i0, i1 = max(i - m, 0), min(i + k + m, n)
+        Sw = P.exact_input(P.window(S0, j0, j1, i0, i1))
+        ref = P.oracle_window_step(Sw, w, alphas, dt)
+        got = P.window(Sg, j0, j1, i0, i1).cpu()
+        sj, si = j - j0, i - i0
+        errs = P.step_errors(got[:, sj:sj + k, si:si + k], ref[:, sj:sj + k, si:si + k], w)
+        P.assert_within(errs, P.TOL[dtype], f"window {(j, i)} of {n}^2")
+    # determinism at full size
+    S1 = S0.clone()
+    h.Stepper(prob).step(S1)
+    assert torch.equal(S1, Sg)
