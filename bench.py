@@ -1,0 +1,215 @@
+#!/usr/bin/env python
+"""Benchmark of the L-HWENO hot path on one MI355X: 2D Euler cell-stage updates/s.
+
+Workload: 2D Euler (gamma 1.4) on [0,1]^2 at 4096 x 4096, seed-0 four-quadrant
+piecewise-constant data (rho ~ U[0.1,2], u,v ~ U[-1,1], p ~ U[0.1,2]),
+outflow boundaries, CFL 0.6, characteristic HWENO with the limiter, 12 fields
+(U, U_x, U_y).  One "step" is one SSP-RK3 step (three fused stage kernels plus
+the wave-speed reduction) with the time step computed on the device.
+
+Prints ONE JSON line.  value = cells * 3 stages * steps / wall time of the
+timed region (inputs resident in HBM).  The roofline object is for the
+dominant kernel (the fused stage kernel), timed with HIP events around each of
+its launches on the stream it runs on.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Algorithmic floating-point work of one 2D Euler cell-stage of the fused
+# stage kernel, characteristic-wise with the limiter (operation count of the
+# formulation: +, -, *, /, sqrt, |.| each 1, fused multiply-add 2):
+# two interfaces (x, y) of ~1740 each, flux differences 72, limiter 8 x ~64,
+# Runge-Kutta combination ~48, wave speeds ~15.
+FLOP_PER_CELL_STAGE = 4130.0
+
+# MI355X published peaks (dense vector FP64 / FP32, HBM3E)
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
+PEAK_HBM_GBS = 8000.0
+
+# Compulsory HBM bytes per cell-stage of the fused kernel (fields of 8 / 4 B):
+# stage 1 reads S^n (12) and writes S1 (12) + limited base derivatives (8);
+# stages 2, 3 read S_k (12), U^n (4), base (8) and write 12  -> 104 / 3 fields.
+FIELDS_PER_CELL_STAGE = 104.0 / 3.0
+
+# HBM traffic of one stage-kernel launch from rocprofv3 --pmc FETCH_SIZE /
+# WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the SHA-256 of the
+# kernel sources it was measured on (stale entries are reported as null).
+MEASURED_TRAFFIC = {
+    # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md
+    ("0e5a8766b90ecd97", "f64", 4096): 6.2651e9,
+}
+
+
+def kernel_sha() -> str:
+    hsh = hashlib.sha256()
+    for f in ("paper_2207_05258_amd/csrc/hweno_kernels.hip", "paper_2207_05258_amd/csrc/hweno_math.h"):
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()[:16]
+
+
+def cpu_baseline(n: int = 1024):
+    """The CPU oracle, as it stands, on one SSP-RK3 step of an n x n grid."""
+    import torch
+
+    import hweno_inputs as hi
+    from oracle import hweno_ref as o
+    w = hi.euler2d_quadrants(n, n, 0)
+    prob = o.problem_from_workload(w)
+    S = o.as_tensor(w.S)
+    t0 = time.perf_counter()
+    o.rk3_step(S, prob)
+    dt = time.perf_counter() - t0
+    return {"value": n * n * 3 / dt, "unit": "cell-stage updates/s",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"one SSP-RK3 step (3 cell-stages per cell) of the four-quadrant 2D Euler "
+                      f"workload at {n}x{n} in float64 (torch CPU), {dt:.1f} s"}
+
+
+def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
+    import torch
+
+    import hweno_inputs as hi
+    import paper_2207_05258_amd as h
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    w = hi.euler2d_quadrants(n, n, 0)
+    S = torch.as_tensor(w.S).to(dtype).cuda().contiguous()
+    del w
+    prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=dtype, dx=1.0 / n, dy=1.0 / n,
+                     bc_x=h.OUTFLOW, bc_y=h.OUTFLOW)
+    st = h.Stepper(prob)
+    for _ in range(warmup):
+        st.step(S)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    h.timing_begin()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        st.step(S)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, stage_ms = h.timing_end()
+    ev_ms = e0.elapsed_time(e1)
+    status = st.status
+    ok = status == 0 and bool(torch.isfinite(S).all())
+    cells = n * n
+    rate = cells * 3 * steps / wall
+    per_launch_s = stage_ms / 1e3 / max(launches, 1)
+    flops = FLOP_PER_CELL_STAGE * cells
+    achieved = flops / per_launch_s / 1e12
+    byt = FIELDS_PER_CELL_STAGE * cells * (8 if dtype_name == "f64" else 4)
+    return {
+        "rate": rate, "wall_s": wall, "event_ms": ev_ms, "ms_per_step": wall * 1e3 / steps,
+        "stage_launches": launches, "stage_ms_avg": per_launch_s * 1e3,
+        "achieved_tflops": achieved, "algorithmic_hbm_gbs": byt / per_launch_s / 1e9,
+        "t": st.t, "status": status, "finite_ok": ok,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variant", action="store_true",
+                    help="skip the secondary run in the other precision")
+    ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one plain device copy of 1 GiB (for scaling HBM byte counters) and exit")
+    args = ap.parse_args()
+
+    if args.copy_calibration:
+        import torch
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8}))
+        return
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the design note describes how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU available", file=sys.stderr)
+        sys.exit(2)
+    import paper_2207_05258_amd as h
+    h.lib()
+
+    main_run = run_gpu(args.n, args.dtype, args.steps, args.warmup)
+    print(f"# {args.dtype} {args.n}^2: {main_run['rate']:.4e} cell-stage/s, stage kernel "
+          f"{main_run['stage_ms_avg']:.3f} ms, {main_run['achieved_tflops']:.2f} TFLOP/s",
+          file=sys.stderr, flush=True)
+    variant = None
+    if not args.no_variant:
+        other = "f32" if args.dtype == "f64" else "f64"
+        v = run_gpu(args.n, other, max(args.steps // 2, 1), 1)
+        variant = {"dtype": other, "value": v["rate"], "ms_per_step": v["ms_per_step"],
+                   "stage_ms_avg": v["stage_ms_avg"],
+                   "roofline_frac": v["achieved_tflops"] / PEAK_TFLOPS[other],
+                   "status": v["status"]}
+
+    sha = kernel_sha()
+    traffic = MEASURED_TRAFFIC.get((sha, args.dtype, args.n))
+    roofline = {
+        "bound": "alu",
+        "achieved": round(main_run["achieved_tflops"], 3),
+        "peak": PEAK_TFLOPS[args.dtype],
+        "unit": "TFLOP/s",
+        "frac": round(main_run["achieved_tflops"] / PEAK_TFLOPS[args.dtype], 4),
+        "traffic": traffic,
+        "kernel": "k_stage (fused SSP-RK3 stage)",
+        "flop_per_cell_stage": FLOP_PER_CELL_STAGE,
+        "algorithmic_hbm_GBps": round(main_run["algorithmic_hbm_gbs"], 1),
+        "hbm_frac": round(main_run["algorithmic_hbm_gbs"] / PEAK_HBM_GBS, 4),
+        "stage_launch_ms": round(main_run["stage_ms_avg"], 4),
+    }
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n)
+    out = {
+        "metric": "2D Euler HWENO cell-stage updates/s",
+        "value": main_run["rate"],
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.dtype,
+        "data": "synthetic",
+        "config": {"workload": f"2D Euler four-quadrant Riemann data, {args.n}x{args.n}, outflow, "
+                               f"CFL 0.6, characteristic HWENO + limiter, SSP-RK3, seed 0",
+                   "nx": args.n, "ny": args.n, "fields": 12, "parallelism": "single GPU"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variant": variant,
+        "status_word": main_run["status"],
+        "kernel_sha": sha,
+    }
+    print(json.dumps(out), flush=True)
+    if not main_run["finite_ok"]:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

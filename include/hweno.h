@@ -168,6 +168,17 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
                                const void* lam_lim, void* lam_state,
                                void* stream);
 
+/* Diagnostics: kernel timing of the Runge-Kutta stage kernels.
+ * hweno_timing_begin(1) makes subsequent hweno_rk3_step calls (on this
+ * thread) record a hipEvent pair around every stage-kernel launch on the
+ * call's stream; hweno_timing_end() synchronises on the recorded events, adds
+ * up the elapsed times and returns the number of timed launches and their
+ * total duration in milliseconds (either pointer may be NULL), then stops
+ * timing and releases the events.  hweno_timing_begin(0) stops without
+ * reporting.  Timing adds two event records per stage launch. */
+hweno_status hweno_timing_begin(int32_t enable);
+hweno_status hweno_timing_end(int64_t* launches, double* total_ms);
+
 /* Human-readable name of a status code (static string). */
 const char* hweno_status_string(int32_t status);
 

@@ -21,6 +21,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "../../include/hweno.h"
 #include "hweno_math.h"
@@ -421,6 +423,48 @@ namespace {
 
 thread_local std::string g_last_error;
 
+// stage-kernel timing (diagnostics, per host thread)
+struct Timing {
+  bool on = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+  size_t used = 0;
+};
+thread_local Timing g_timing;
+
+hipEvent_t* timing_pair(hipStream_t s, bool start) {
+  (void)s;
+  if (!g_timing.on) return nullptr;
+  if (start) {
+    if (g_timing.used == g_timing.ev.size()) {
+      hipEvent_t a, b;
+      if (hipEventCreate(&a) != hipSuccess) return nullptr;
+      if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return nullptr; }
+      g_timing.ev.emplace_back(a, b);
+    }
+    return &g_timing.ev[g_timing.used].first;
+  }
+  return &g_timing.ev[g_timing.used++].second;
+}
+
+void timing_release() {
+  for (auto& e : g_timing.ev) {
+    (void)hipEventDestroy(e.first);
+    (void)hipEventDestroy(e.second);
+  }
+  g_timing.ev.clear();
+  g_timing.used = 0;
+  g_timing.on = false;
+}
+
+// launches one stage kernel, bracketed by timing events when enabled
+template <typename Launch>
+void timed(hipStream_t s, Launch&& launch) {
+  hipEvent_t* a = timing_pair(s, true);
+  if (a) (void)hipEventRecord(*a, s);
+  launch();
+  if (a) (void)hipEventRecord(*timing_pair(s, false), s);
+}
+
 hweno_status fail(hweno_status st, const char* fmt, ...) {
   char buf[512];
   va_list ap;
@@ -657,13 +701,13 @@ struct RunStep {
     const dim3 grid = stage_grid(DIM, a.nx, a.ny);
     a.in = (const T*)state;
     a.out = s1;
-    k_stage<T, PHYS, DIM, 1, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    timed(s, [&] { k_stage<T, PHYS, DIM, 1, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
     a.in = s1;
     a.out = s2;
-    k_stage<T, PHYS, DIM, 2, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    timed(s, [&] { k_stage<T, PHYS, DIM, 2, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
     a.in = s2;
     a.out = (T*)state;
-    k_stage<T, PHYS, DIM, 3, TX, TY><<<grid, TX * TY, 0, s>>>(a, k);
+    timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
     k_finish<<<1, 64, 0, s>>>(ctrl, tape);
     return launch_check("rk3_step");
   }
@@ -742,6 +786,32 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, con
   if (st) return st;
   (void)state; (void)alpha; (void)lam_rhs; (void)lam_lim; (void)lam_state; (void)stream;
   return fail(HWENO_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+hweno_status hweno_timing_begin(int32_t enable) {
+  timing_release();
+  g_timing.on = enable != 0;
+  return ok();
+}
+
+hweno_status hweno_timing_end(int64_t* launches, double* total_ms) {
+  double tot = 0.0;
+  for (size_t q = 0; q < g_timing.used; ++q) {
+    if (hipEventSynchronize(g_timing.ev[q].second) != hipSuccess) {
+      timing_release();
+      return fail(HWENO_ERR_LAUNCH, "event synchronisation failed");
+    }
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, g_timing.ev[q].first, g_timing.ev[q].second) != hipSuccess) {
+      timing_release();
+      return fail(HWENO_ERR_LAUNCH, "event timing failed");
+    }
+    tot += ms;
+  }
+  if (launches) *launches = (int64_t)g_timing.used;
+  if (total_ms) *total_ms = tot;
+  timing_release();
+  return ok();
 }
 
 const char* hweno_status_string(int32_t s) {

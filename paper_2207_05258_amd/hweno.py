@@ -68,6 +68,8 @@ def lib() -> ctypes.CDLL:
             "hweno_rk3_step": ([P, vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
                                 vp, vp, vp], ctypes.c_int),
             "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+            "hweno_timing_begin": ([ctypes.c_int32], ctypes.c_int),
+            "hweno_timing_end": ([ctypes.POINTER(ctypes.c_int64), dp], ctypes.c_int),
             "hweno_status_string": ([ctypes.c_int32], ctypes.c_char_p),
             "hweno_last_error": ([], ctypes.c_char_p),
         }
@@ -249,6 +251,19 @@ class Stepper:
     @property
     def last_dt(self) -> float:
         return float(self.ctrl[6])
+
+
+def timing_begin(enable: bool = True):
+    """Start timing every Runge-Kutta stage-kernel launch (HIP events on its stream)."""
+    _check(lib().hweno_timing_begin(1 if enable else 0), "hweno_timing_begin")
+
+
+def timing_end() -> Tuple[int, float]:
+    """Stop timing; returns (number of stage launches, their total milliseconds)."""
+    n = ctypes.c_int64(0)
+    ms = ctypes.c_double(0.0)
+    _check(lib().hweno_timing_end(ctypes.byref(n), ctypes.byref(ms)), "hweno_timing_end")
+    return int(n.value), float(ms.value)
 
 
 def rk3_step_(S: torch.Tensor, prob: Problem, dt: Optional[float] = None) -> torch.Tensor:
