@@ -100,61 +100,71 @@ __device__ __forceinline__ void block_fold(double sx, double sy, uint32_t flags,
 }
 
 // ---------------------------------------------------------------------------
-// stage / right-hand-side kernel
-// K = 0: right-hand side only; K = 1, 2, 3: SSP-RK3 stage K.
+// Tile order.  Workgroups are dispatched round-robin over the 8 XCDs (each
+// with its own L2); renumbering so that each XCD receives a contiguous band
+// of tiles keeps the halo rows shared by neighbouring tiles in one L2.
 // ---------------------------------------------------------------------------
-template <typename T, int PHYS, int DIM, int K, int TX, int TY>
-__global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
+__device__ __forceinline__ int xcd_band(int b, int nb) {
+  constexpr int NXCD = 8;
+  const int per = nb / NXCD;
+  if (b >= per * NXCD) return b;
+  return (b % NXCD) * per + (b / NXCD);
+}
+
+// time step of stage K and the speeds it splits with (uniform per grid)
+template <int DIM, int K>
+__device__ __forceinline__ bool stage_dt(const StageArgs<double>* unused, double* ctrl,
+                                         double dt_fixed, double t_end, double cfl, double dx,
+                                         double dy, int replay, bool leader,
+                                         unsigned long long* status, double& dt) {
+  (void)unused;
+  if constexpr (K == 1) {
+    if (replay) {
+      dt = ctrl[6];
+    } else {
+      const double alx = ctrl[0], aly = ctrl[1];
+      if (dt_fixed > 0.0) {
+        dt = dt_fixed;
+      } else if (DIM == 1) {
+        dt = cfl * dx / alx;
+      } else {
+        dt = cfl / (alx / dx + aly / dy);
+      }
+      if (t_end > 0.0) dt = fmin(dt, t_end - ctrl[7]);
+      if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
+      if (leader) {
+        ctrl[6] = dt;
+        if (dt == 0.0) atomicOr(status, (unsigned long long)HWENO_ST_SKIPPED);
+      }
+    }
+  } else {
+    dt = ctrl[6];
+  }
+  return dt > 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// One tile of one stage (K = 1, 2, 3) or of the right-hand side (K = 0).
+// NT threads; TX x TY cells (TX*TY <= NT); sm, fb: LDS staging buffers.
+// Returns this thread's contribution to the next stage's speeds.
+// ---------------------------------------------------------------------------
+template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
+__device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T>& k,
+                                           int tile_x, int tile_y, double dt, double alx,
+                                           double aly, T* __restrict__ sm, T* __restrict__ fb,
+                                           T& sx, T& sy, uint32_t& flags) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
-  constexpr int NT = TX * TY;
   constexpr int HY = (DIM == 2) ? 2 : 0;
   constexpr int W = TX + 4;           // LDS row length (2-cell x halo each side)
   constexpr int HR = TY + 2 * HY;     // LDS rows
   constexpr int FW = TX + 1;          // flux buffer row length
   constexpr int FR = TY + 1;          // flux buffer rows
-  constexpr int NQ = (DIM == 2) ? 3 : 2;  // flux kinds stored per interface
-  __shared__ T sm[NF * HR * W];
-  __shared__ T fb[NQ * M * FR * FW];
+  static_assert(TX * TY <= NT, "one cell per thread");
 
   const int tid = threadIdx.x;
-  double* ctrl = a.ctrl;
-  unsigned long long* status = a.status;
-
-  // ---- time step and wave speeds of this stage ----
-  double dt = 0.0, alx, aly;
-  if constexpr (K == 0) {
-    alx = a.alpha[0];
-    aly = a.alpha[1];
-  } else {
-    alx = ctrl[2 * (K - 1)];
-    aly = ctrl[2 * (K - 1) + 1];
-    if constexpr (K == 1) {
-      if (a.replay) {
-        dt = ctrl[6];
-      } else {
-        if (a.dt_fixed > 0.0) {
-          dt = a.dt_fixed;
-        } else if (DIM == 1) {
-          dt = a.cfl * a.dx / alx;
-        } else {
-          dt = a.cfl / (alx / a.dx + aly / a.dy);
-        }
-        if (a.t_end > 0.0) dt = fmin(dt, a.t_end - ctrl[7]);
-        if (!(dt > 0.0) || !isfinite(dt)) dt = 0.0;
-        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
-          ctrl[6] = dt;
-          if (dt == 0.0) atomicOr(status, (unsigned long long)HWENO_ST_SKIPPED);
-        }
-      }
-    } else {
-      dt = ctrl[6];
-    }
-    if (!(dt > 0.0)) return;  // uniform over the grid: the step is skipped
-  }
-
-  const int i0 = blockIdx.x * TX;
-  const int j0 = blockIdx.y * TY;
+  const int i0 = tile_x * TX;
+  const int j0 = tile_y * TY;
   const int nx = a.nx, ny = a.ny;
   const long long fs = a.fs;
 
@@ -171,6 +181,7 @@ __global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
 
   const T idx = T(1.0 / a.dx);
   const T hx = T(a.dx);
+  const bool owner = tid < TX * TY;
   const int tx = tid % TX, ty = tid / TX;
   T LU[M], LV[M], LW[M];
 
@@ -196,15 +207,17 @@ __global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
     }
   }
   __syncthreads();
+  if (owner) {
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
-    const int b0 = (c * FR + ty) * FW + tx;
-    LU[c] = -(fb[b0 + 1] - fb[b0]) * idx;
-    const int b1 = ((M + c) * FR + ty) * FW + tx;
-    LV[c] = -(fb[b1 + 1] - fb[b1]) * idx;
-    if constexpr (DIM == 2) {
-      const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
-      LW[c] = -(fb[b2 + 1] - fb[b2]) * idx;
+    for (int c = 0; c < M; ++c) {
+      const int b0 = (c * FR + ty) * FW + tx;
+      LU[c] = -(fb[b0 + 1] - fb[b0]) * idx;
+      const int b1 = ((M + c) * FR + ty) * FW + tx;
+      LV[c] = -(fb[b1 + 1] - fb[b1]) * idx;
+      if constexpr (DIM == 2) {
+        const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
+        LW[c] = -(fb[b2 + 1] - fb[b2]) * idx;
+      }
     }
   }
 
@@ -232,59 +245,52 @@ __global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
       for (int c = 0; c < M; ++c) {
         const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
         fb[(cs * FR + iy) * FW + cc] = fh[c];
-        fb[((M + cs) * FR + iy) * FW + cc] = hh[c];   // theta-hat -> L_W
+        fb[((M + cs) * FR + iy) * FW + cc] = hh[c];      // theta-hat -> L_W
         fb[((2 * M + cs) * FR + iy) * FW + cc] = xh[c];  // xi-hat -> L_V
       }
     }
     __syncthreads();
+    if (owner) {
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      const int b0 = (c * FR + ty) * FW + tx;
-      LU[c] -= (fb[b0 + FW] - fb[b0]) * idy;
-      const int b1 = ((M + c) * FR + ty) * FW + tx;
-      LW[c] -= (fb[b1 + FW] - fb[b1]) * idy;
-      const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
-      LV[c] -= (fb[b2 + FW] - fb[b2]) * idy;
+      for (int c = 0; c < M; ++c) {
+        const int b0 = (c * FR + ty) * FW + tx;
+        LU[c] -= (fb[b0 + FW] - fb[b0]) * idy;
+        const int b1 = ((M + c) * FR + ty) * FW + tx;
+        LW[c] -= (fb[b1 + FW] - fb[b1]) * idy;
+        const int b2 = ((2 * M + c) * FR + ty) * FW + tx;
+        LV[c] -= (fb[b2 + FW] - fb[b2]) * idy;
+      }
     }
   }
 
   // ---- own cell: limiter, Runge-Kutta combination, store ----
   const int gi = i0 + tx, gj = j0 + ty;
-  const bool inside = gi < nx && gj < ny;
+  const bool inside = owner && gi < nx && gj < ny;
   const long long g = (long long)gj * nx + gi;
   const T* own = sm + (ty + HY) * W + tx + 2;
+  if (!inside) return;
 
   if constexpr (K == 0) {
-    if (inside) {
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        a.out[c * fs + g] = LU[c];
-        a.out[(M + c) * fs + g] = LV[c];
-        if constexpr (DIM == 2) a.out[(2 * M + c) * fs + g] = LW[c];
-      }
+    for (int c = 0; c < M; ++c) {
+      a.out[c * fs + g] = LU[c];
+      a.out[(M + c) * fs + g] = LV[c];
+      if constexpr (DIM == 2) a.out[(2 * M + c) * fs + g] = LW[c];
     }
-    return;
   } else {
     // S^_k = (U_k, limited derivatives of S_k)
     T Sh[NF];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      Sh[c] = own[(c * HR) * W];
       const T* u = own + (c * HR) * W;
       const T* v = own + ((M + c) * HR) * W;
-      if (k.limiter_on) {
-        Sh[M + c] = limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw);
-      } else {
-        Sh[M + c] = v[0];
-      }
+      Sh[c] = u[0];
+      Sh[M + c] = k.limiter_on ? limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw) : v[0];
       if constexpr (DIM == 2) {
         const T* w = own + ((2 * M + c) * HR) * W;
-        if (k.limiter_on) {
-          Sh[2 * M + c] = limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
-                                 T(1.0 / a.dy), k.lw);
-        } else {
-          Sh[2 * M + c] = w[0];
-        }
+        Sh[2 * M + c] = k.limiter_on ? limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
+                                              T(1.0 / a.dy), k.lw)
+                                     : w[0];
       }
     }
     T L[NF];
@@ -296,43 +302,65 @@ __global__ __launch_bounds__(TX* TY) void k_stage(StageArgs<T> a, Consts<T> k) {
     }
     const T tdt = T(dt);
     T out[NF];
-    if (inside) {
-      if constexpr (K == 1) {
+    if constexpr (K == 1) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) out[f] = Sh[f] + tdt * L[f];
-        if (k.limiter_on) {
+      for (int f = 0; f < NF; ++f) out[f] = Sh[f] + tdt * L[f];
+      if (k.limiter_on) {
 #pragma unroll
-          for (int f = M; f < NF; ++f) a.base[(f - M) * fs + g] = Sh[f];
-        }
-      } else {
-        const T w0 = (K == 2) ? T(0.75) : T(1.0 / 3.0);
-        const T w1 = (K == 2) ? T(0.25) : T(2.0 / 3.0);
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-          T s0;
-          if (f < M || !k.limiter_on) {
-            s0 = a.st0[f * fs + g];
-          } else {
-            s0 = a.base[(f - M) * fs + g];
-          }
-          out[f] = w0 * s0 + w1 * (Sh[f] + tdt * L[f]);
-        }
+        for (int f = M; f < NF; ++f) a.base[(f - M) * fs + g] = Sh[f];
       }
-#pragma unroll
-      for (int f = 0; f < NF; ++f) a.out[f * fs + g] = out[f];
-    }
-    if constexpr (K < 3) {
-      // speeds of the new stage state, for the next stage's splitting
-      T sx = T(0), sy = T(0);
-      uint32_t flags = 0;
-      if (inside) point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
-      block_fold<NT>(double(sx), double(sy), flags, ctrl + 2 * K, status, !a.replay);
     } else {
-      T sx = T(0), sy = T(0);
-      uint32_t flags = 0;
-      if (inside) point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
-      block_fold<NT>(0.0, 0.0, flags, ctrl, status, false);
+      const T w0 = (K == 2) ? T(0.75) : T(1.0 / 3.0);
+      const T w1 = (K == 2) ? T(0.25) : T(2.0 / 3.0);
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        const T s0 = (f < M || !k.limiter_on) ? a.st0[f * fs + g] : a.base[(f - M) * fs + g];
+        out[f] = w0 * s0 + w1 * (Sh[f] + tdt * L[f]);
+      }
     }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) a.out[f * fs + g] = out[f];
+    point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
+  }
+  (void)alx;
+  (void)aly;
+}
+
+// ---------------------------------------------------------------------------
+// stage / right-hand-side kernel over one grid
+// K = 0: right-hand side only; K = 1, 2, 3: SSP-RK3 stage K.
+// ---------------------------------------------------------------------------
+template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a, Consts<T> k) {
+  constexpr int M = Comps<PHYS, DIM>::M;
+  constexpr int NF = Comps<PHYS, DIM>::NF;
+  constexpr int HY = (DIM == 2) ? 2 : 0;
+  constexpr int NQ = (DIM == 2) ? 3 : 2;
+  __shared__ T sm[NF * (TY + 2 * HY) * (TX + 4)];
+  __shared__ T fb[NQ * M * (TY + 1) * (TX + 1)];
+
+  double dt = 0.0, alx, aly;
+  if constexpr (K == 0) {
+    alx = a.alpha[0];
+    aly = a.alpha[1];
+  } else {
+    alx = a.ctrl[2 * (K - 1)];
+    aly = a.ctrl[2 * (K - 1) + 1];
+    if (!stage_dt<DIM, K>(nullptr, a.ctrl, a.dt_fixed, a.t_end, a.cfl, a.dx, a.dy, a.replay,
+                          blockIdx.x == 0 && threadIdx.x == 0, a.status, dt))
+      return;  // uniform over the grid: the step is skipped
+  }
+  const int ntx = (a.nx + TX - 1) / TX;
+  const int t = xcd_band(blockIdx.x, gridDim.x);
+  const int tile_y = t / ntx, tile_x = t - tile_y * ntx;
+  T sx = T(0), sy = T(0);
+  uint32_t flags = 0;
+  stage_tile<T, PHYS, DIM, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
+                                          flags);
+  if constexpr (K > 0) {
+    // speeds of the new stage state feed the next stage's splitting
+    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status,
+                   K < 3 && !a.replay);
   }
 }
 
@@ -573,10 +601,13 @@ hweno_status launch_check(const char* what) {
   return HWENO_OK;
 }
 
+// 2D tile: 16 x 15 cells on 256 threads gives 255 x-interfaces and 256
+// y-interfaces, i.e. one balanced pass per direction.
 template <int DIM>
 struct Tile {
-  static constexpr int TX = (DIM == 2) ? 32 : 256;
-  static constexpr int TY = (DIM == 2) ? 8 : 1;
+  static constexpr int TX = (DIM == 2) ? 16 : 256;
+  static constexpr int TY = (DIM == 2) ? 15 : 1;
+  static constexpr int NT = 256;
 };
 
 // dispatch helper: calls F::template run<T, PHYS, DIM>(args...)
@@ -618,8 +649,9 @@ StageArgs<T> base_args(const hweno_problem* p) {
 }
 
 dim3 stage_grid(int dim, int nx, int ny) {
-  if (dim == 2) return dim3((nx + Tile<2>::TX - 1) / Tile<2>::TX, (ny + Tile<2>::TY - 1) / Tile<2>::TY);
-  return dim3((nx + Tile<1>::TX - 1) / Tile<1>::TX, 1);
+  if (dim == 2)
+    return dim3(((nx + Tile<2>::TX - 1) / Tile<2>::TX) * ((ny + Tile<2>::TY - 1) / Tile<2>::TY));
+  return dim3((nx + Tile<1>::TX - 1) / Tile<1>::TX);
 }
 
 unsigned alpha_blocks(long long n) {
@@ -653,8 +685,8 @@ struct RunRhs {
     a.in = (const T*)state;
     a.out = (T*)rhs;
     a.alpha = alpha;
-    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY;
-    k_stage<T, PHYS, DIM, 0, TX, TY><<<stage_grid(DIM, a.nx, a.ny), TX * TY, 0, s>>>(
+    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
+    k_stage<T, PHYS, DIM, 0, TX, TY, NT><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
         a, make_consts<T>(p));
     return launch_check("rhs");
   }
@@ -697,17 +729,17 @@ struct RunStep {
     a.replay = replay ? 1 : 0;
     T* s1 = (T*)(w + L.s1);
     T* s2 = (T*)(w + L.s2);
-    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY;
+    constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
     const dim3 grid = stage_grid(DIM, a.nx, a.ny);
     a.in = (const T*)state;
     a.out = s1;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 1, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
+    timed(s, [&] { k_stage<T, PHYS, DIM, 1, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
     a.in = s1;
     a.out = s2;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 2, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
+    timed(s, [&] { k_stage<T, PHYS, DIM, 2, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
     a.in = s2;
     a.out = (T*)state;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY><<<grid, TX * TY, 0, s>>>(a, k); });
+    timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
     k_finish<<<1, 64, 0, s>>>(ctrl, tape);
     return launch_check("rk3_step");
   }

@@ -291,8 +291,8 @@ __device__ __forceinline__ void interface_fluxes(const Loader& ld, T alpha, T h,
     if constexpr (MIXED) xh[c] = T(0);
   }
   const T hh2 = T(0.5) * h;
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
+  // one stencil point: physics, linear-flux accumulation, split and projected data
+  auto point = [&](const int s) {
     T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
     ld(s, U, Dn, Dt);
     point_fluxes<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, F, A, B);
@@ -338,15 +338,21 @@ __device__ __forceinline__ void interface_fluxes(const Loader& ld, T alpha, T h,
         }
       }
     }
-  }
+  };
+  // "+" side first (points 0..2), so its data die before point 3 is loaded
+  point(0);
+  point(1);
+  point(2);
   T fc[M];
 #pragma unroll
-  for (int c = 0; c < M; ++c) {
-    // "+" at x_{i+1/2} from i-1, i, i+1; "-" mirrored: i+2, i+1, i with
-    // derivative data negated (reflection about the interface)
-    fc[c] = hw_plus(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw) +
-            hw_plus(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw);
-  }
+  for (int c = 0; c < M; ++c)
+    fc[c] = hw_plus(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw);
+  point(3);
+  // "-" mirrored: i+2, i+1, i with derivative data negated (reflection about
+  // the interface)
+#pragma unroll
+  for (int c = 0; c < M; ++c)
+    fc[c] += hw_plus(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw);
   if (proj) {
     eg.back(fc, fh);
   } else {
