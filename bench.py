@@ -118,6 +118,38 @@ def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
     }
 
 
+def run_batched(steps: int, warmup: int, n_inst: int = 256, seed: int = 0):
+    """256 uneven 2D Euler instances (sides ~ U{64..512}), FP32, autotuned tile
+    variant and grid, one hipGraph per step replayed ``steps`` times."""
+    import torch
+
+    import hweno_inputs as hi
+    import paper_2207_05258_amd as h
+    ws = hi.batched_instances(n_inst, seed)
+    states = [torch.as_tensor(w.S).to(torch.float32).cuda().contiguous() for w in ws]
+    grids = [dict(dx=w.dx, dy=w.dy, bc_x=w.bc_x, bc_y=w.bc_y) for w in ws]
+    del ws
+    common = h.Problem(dim=2, nx=1, ny=1, physics="euler", dtype=torch.float32)
+    b = h.BatchedStepper(states, grids, common)
+    best, _ = h.autotune_batched(b)
+    for _ in range(warmup):
+        b.step()
+    b.capture(steps=1)
+    torch.cuda.synchronize()
+    h.timing_begin()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        b.replay()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    launches, stage_ms = h.timing_end()
+    bad = sum(1 for st in b.statuses() if st)
+    return {"value": b.cells * 3 * steps / wall, "unit": "cell-stage updates/s", "dtype": "f32",
+            "instances": n_inst, "cells": b.cells, "variant": best[0], "blocks": best[1],
+            "steps": steps, "ms_per_step": wall * 1e3 / steps, "failed_instances": bad,
+            "graph": "one hipGraph per step (speeds, 3 persistent stages, time update)"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -129,6 +161,7 @@ def main():
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the secondary run in the other precision")
     ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
@@ -168,6 +201,15 @@ def main():
                    "roofline_frac": v["achieved_tflops"] / PEAK_TFLOPS[other],
                    "status": v["status"]}
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(args.steps, max(args.warmup, 1))
+        single_f32 = (variant["value"] if variant and variant["dtype"] == "f32"
+                      else (main_run["rate"] if args.dtype == "f32" else None))
+        batched["ratio_vs_single_grid_f32"] = (batched["value"] / single_f32) if single_f32 else None
+        print(f"# batched: {batched['value']:.4e} cell-stage/s "
+              f"(ratio {batched['ratio_vs_single_grid_f32']})", file=sys.stderr, flush=True)
+
     sha = kernel_sha()
     traffic = MEASURED_TRAFFIC.get((sha, args.dtype, args.n))
     roofline = {
@@ -203,6 +245,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "variant": variant,
+        "batched": batched,
         "status_word": main_run["status"],
         "kernel_sha": sha,
     }

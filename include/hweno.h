@@ -168,6 +168,50 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
                                const void* lam_lim, void* lam_state,
                                void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Batched 2D Euler: many independent grids advanced by one persistent launch
+ * per Runge-Kutta stage (the same stage computation as hweno_rk3_step, per
+ * instance: own speeds, own dt, own boundary conditions).
+ *
+ * Descriptor of one instance.  Fields marked (caller) are set by the caller
+ * before hweno_batch_prepare; fields marked (prepare) are filled by it.  The
+ * kernels read an array of these from DEVICE memory (the caller copies the
+ * host array there after filling state/ws pointers).
+ * --------------------------------------------------------------------------- */
+#define HWENO_BATCH_VARIANTS 2   /* tile shapes: 0 = 16 x 15 cells, 1 = 32 x 7 cells */
+typedef struct {
+  void* state;             /* (caller) device state of this instance, [12][ny][nx]  */
+  void* ws;                /* (caller) device workspace, >= ws_bytes, 256-B aligned */
+  int32_t nx, ny;          /* (caller) grid, each >= 1                              */
+  int32_t bc_x, bc_y;      /* (caller) hweno_bc                                     */
+  double dx, dy;           /* (caller) cell sizes                                   */
+  double dt_fixed, t_end;  /* (caller) as in hweno_rk3_step                         */
+  int64_t ws_bytes;        /* (prepare) workspace bytes this instance needs          */
+  int64_t off_s1, off_s2, off_base;            /* (prepare) workspace layout        */
+  int32_t tile_begin[HWENO_BATCH_VARIANTS];    /* (prepare) first global tile index */
+  int32_t n_tiles[HWENO_BATCH_VARIANTS];       /* (prepare) tiles of this instance  */
+} hweno_instance;
+
+/* Host only: validates every instance against `common` (dim must be 2,
+ * physics Euler; nx, ny, bc, dx, dy, dt_fixed, t_end taken from the instance),
+ * fills the (prepare) fields and writes the total tile count of each variant
+ * to total_tiles[HWENO_BATCH_VARIANTS].  The control block at the start of
+ * every workspace follows the hweno_rk3_step rules (zero it before the first
+ * step). */
+hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* inst,
+                                 int32_t n_inst, int32_t* total_tiles);
+
+/* One SSP-RK3 step of every instance: wave speeds, three persistent stage
+ * launches striding over the flattened tile list (instance found by binary
+ * search on tile_begin), and the per-instance time update.  Enqueues six
+ * kernels and nothing else, so it can be captured in a hipGraph.
+ * inst_dev: device copy of the prepared descriptors; total_tiles: the
+ * prepared count for `variant`; blocks: persistent grid size (0 = one
+ * workgroup per tile up to 8 per compute unit). */
+hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_instance* inst_dev,
+                                    int32_t n_inst, int32_t total_tiles, int32_t variant,
+                                    int32_t blocks, void* stream);
+
 /* Diagnostics: kernel timing of the Runge-Kutta stage kernels.
  * hweno_timing_begin(1) makes subsequent hweno_rk3_step calls (on this
  * thread) record a hipEvent pair around every stage-kernel launch on the

@@ -19,6 +19,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -361,6 +362,132 @@ __global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a, Consts<T> k) {
     // speeds of the new stage state feed the next stage's splitting
     block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status,
                    K < 3 && !a.replay);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2D Euler: persistent kernels striding over the flattened tile list
+// of many independent instances.
+// ---------------------------------------------------------------------------
+template <int V>
+struct BatchTile;
+template <>
+struct BatchTile<0> {  // 255 x- and 256 y-interfaces: one pass each
+  static constexpr int TX = 16, TY = 15, NT = 256;
+};
+template <>
+struct BatchTile<1> {  // 231 x- and 256 y-interfaces: one pass each, wider rows
+  static constexpr int TX = 32, TY = 7, NT = 256;
+};
+
+__device__ __forceinline__ int find_instance(const hweno_instance* __restrict__ inst, int n,
+                                             int t, int V) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (inst[mid].tile_begin[V] <= t) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <typename T, int K>
+__device__ __forceinline__ StageArgs<T> instance_args(const hweno_instance& I, double cfl) {
+  StageArgs<T> a;
+  char* ws = (char*)I.ws;
+  a.ctrl = (double*)ws;
+  a.status = (unsigned long long*)(a.ctrl + 8);
+  a.alpha = nullptr;
+  a.nx = I.nx;
+  a.ny = I.ny;
+  a.bc_x = I.bc_x;
+  a.bc_y = I.bc_y;
+  a.fs = (long long)I.nx * I.ny;
+  a.dx = I.dx;
+  a.dy = I.dy;
+  a.dt_fixed = I.dt_fixed;
+  a.t_end = I.t_end;
+  a.cfl = cfl;
+  a.replay = 0;
+  a.st0 = (const T*)I.state;
+  a.base = (T*)(ws + I.off_base);
+  T* s1 = (T*)(ws + I.off_s1);
+  T* s2 = (T*)(ws + I.off_s2);
+  a.in = (K <= 1) ? (const T*)I.state : (K == 2 ? s1 : s2);
+  a.out = (K <= 1) ? s1 : (K == 2 ? s2 : (T*)I.state);
+  return a;
+}
+
+template <typename T, int V, int K>
+__global__ __launch_bounds__(256) void k_stage_batched(const hweno_instance* __restrict__ inst,
+                                                       int n_inst, int total, double cfl,
+                                                       Consts<T> k) {
+  constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY, NT = BatchTile<V>::NT;
+  __shared__ T sm[12 * (TY + 4) * (TX + 4)];
+  __shared__ T fb[12 * (TY + 1) * (TX + 1)];
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const hweno_instance& I = inst[find_instance(inst, n_inst, t, V)];
+    StageArgs<T> a = instance_args<T, K>(I, cfl);
+    double dt;
+    if (!stage_dt<2, K>(nullptr, a.ctrl, a.dt_fixed, a.t_end, cfl, a.dx, a.dy, 0,
+                        t == I.tile_begin[V] && threadIdx.x == 0, a.status, dt))
+      continue;  // uniform over the workgroup: this instance's step is skipped
+    const double alx = a.ctrl[2 * (K - 1)], aly = a.ctrl[2 * (K - 1) + 1];
+    const int lt = t - I.tile_begin[V];
+    const int ntx = (I.nx + TX - 1) / TX;
+    const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
+    T sx = T(0), sy = T(0);
+    uint32_t flags = 0;
+    stage_tile<T, PH_EULER, 2, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx,
+                                              sy, flags);
+    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status, K < 3);
+  }
+}
+
+// speeds of every instance's state (slots pre-zeroed by k_begin_batched)
+template <typename T, int V>
+__global__ __launch_bounds__(256) void k_alpha_batched(const hweno_instance* __restrict__ inst,
+                                                       int n_inst, int total, Consts<T> k) {
+  constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY;
+  for (int t = blockIdx.x; t < total; t += gridDim.x) {
+    const hweno_instance& I = inst[find_instance(inst, n_inst, t, V)];
+    const int lt = t - I.tile_begin[V];
+    const int ntx = (I.nx + TX - 1) / TX;
+    const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
+    const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
+    const int gi = tile_x * TX + tx, gj = tile_y * TY + ty;
+    T sx = T(0), sy = T(0);
+    uint32_t flags = 0;
+    if (threadIdx.x < TX * TY && gi < I.nx && gj < I.ny) {
+      const long long n = (long long)I.nx * I.ny;
+      const long long g = (long long)gj * I.nx + gi;
+      const T* S = (const T*)I.state;
+      T U[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) U[c] = S[c * n + g];
+      point_speeds<T, PH_EULER, 2>(U, k, sx, sy, flags);
+    }
+    double* ctrl = (double*)I.ws;
+    block_fold<256>(double(sx), double(sy), flags, ctrl, (unsigned long long*)(ctrl + 8), true);
+  }
+}
+
+__global__ void k_begin_batched(const hweno_instance* __restrict__ inst, int n_inst) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n_inst) {
+    double* ctrl = (double*)inst[q].ws;
+#pragma unroll
+    for (int j = 0; j < 6; ++j) ctrl[j] = 0.0;
+  }
+}
+
+__global__ void k_finish_batched(const hweno_instance* __restrict__ inst, int n_inst) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < n_inst) {
+    double* ctrl = (double*)inst[q].ws;
+    if (ctrl[6] > 0.0) {
+      ctrl[7] += ctrl[6];
+      ctrl[9] += 1.0;
+    }
   }
 }
 
@@ -745,6 +872,49 @@ struct RunStep {
   }
 };
 
+int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        cus <= 0)
+      cus = 256;
+  }
+  return cus;
+}
+
+template <int V>
+int tiles_of(int nx, int ny) {
+  return ((nx + BatchTile<V>::TX - 1) / BatchTile<V>::TX) *
+         ((ny + BatchTile<V>::TY - 1) / BatchTile<V>::TY);
+}
+
+template <typename T, int V>
+hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, int n, int total,
+                         int blocks, hipStream_t s) {
+  const Consts<T> k = make_consts<T>(p);
+  const int grid = blocks > 0 ? std::min(blocks, total) : std::min(total, 8 * device_cus());
+  const unsigned small = (unsigned)((n + 255) / 256);
+  k_begin_batched<<<small, 256, 0, s>>>(inst, n);
+  k_alpha_batched<T, V><<<grid, 256, 0, s>>>(inst, n, total, k);
+  timed(s, [&] { k_stage_batched<T, V, 1><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
+  timed(s, [&] { k_stage_batched<T, V, 2><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
+  timed(s, [&] { k_stage_batched<T, V, 3><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
+  k_finish_batched<<<small, 256, 0, s>>>(inst, n);
+  return launch_check("rk3_step_batched");
+}
+
+hweno_status batch_common_ok(const hweno_problem* common) {
+  if (!common) return fail(HWENO_ERR_INVALID_ARG, "problem pointer is NULL");
+  if (common->dim != 2 || common->physics != HWENO_EULER)
+    return fail(HWENO_ERR_UNSUPPORTED, "batched stepping is built for 2D Euler only");
+  hweno_problem q = *common;
+  if (q.nx < 1) q.nx = 1;
+  if (q.ny < 1) q.ny = 1;
+  return validate(&q);
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -818,6 +988,66 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, con
   if (st) return st;
   (void)state; (void)alpha; (void)lam_rhs; (void)lam_lim; (void)lam_state; (void)stream;
   return fail(HWENO_ERR_UNSUPPORTED, "adjoint not built yet");
+}
+
+hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* inst,
+                                 int32_t n_inst, int32_t* total_tiles) {
+  hweno_status st = batch_common_ok(common);
+  if (st) return st;
+  if (!inst || !total_tiles || n_inst < 1)
+    return fail(HWENO_ERR_INVALID_ARG, "inst, total_tiles must be non-NULL and n_inst >= 1");
+  long long tot[HWENO_BATCH_VARIANTS] = {0, 0};
+  for (int q = 0; q < n_inst; ++q) {
+    hweno_instance& I = inst[q];
+    hweno_problem p = *common;
+    p.nx = I.nx;
+    p.ny = I.ny;
+    p.bc_x = I.bc_x;
+    p.bc_y = I.bc_y;
+    p.dx = I.dx;
+    p.dy = I.dy;
+    st = validate(&p);
+    if (st) return fail(st, "instance %d: %s", q, g_last_error.c_str());
+    if (I.nx < 1 || I.ny < 1) return fail(HWENO_ERR_INVALID_ARG, "instance %d: nx, ny must be >= 1", q);
+    if (!std::isfinite(I.dt_fixed) || !std::isfinite(I.t_end))
+      return fail(HWENO_ERR_INVALID_ARG, "instance %d: dt_fixed, t_end must be finite", q);
+    const WsLayout L = ws_layout(&p);
+    I.ws_bytes = (int64_t)L.total;
+    I.off_s1 = (int64_t)L.s1;
+    I.off_s2 = (int64_t)L.s2;
+    I.off_base = (int64_t)L.base;
+    const int nt[HWENO_BATCH_VARIANTS] = {tiles_of<0>(I.nx, I.ny), tiles_of<1>(I.nx, I.ny)};
+    for (int v = 0; v < HWENO_BATCH_VARIANTS; ++v) {
+      I.tile_begin[v] = (int32_t)tot[v];
+      I.n_tiles[v] = nt[v];
+      tot[v] += nt[v];
+      if (tot[v] > (1ll << 30)) return fail(HWENO_ERR_INVALID_ARG, "too many tiles");
+    }
+  }
+  for (int v = 0; v < HWENO_BATCH_VARIANTS; ++v) total_tiles[v] = (int32_t)tot[v];
+  return ok();
+}
+
+hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_instance* inst_dev,
+                                    int32_t n_inst, int32_t total_tiles, int32_t variant,
+                                    int32_t blocks, void* stream) {
+  hweno_status st = batch_common_ok(common);
+  if (st) return st;
+  if (!inst_dev || n_inst < 1 || total_tiles < n_inst)
+    return fail(HWENO_ERR_INVALID_ARG, "inst_dev must be non-NULL, n_inst >= 1, total_tiles >= n_inst");
+  if (variant < 0 || variant >= HWENO_BATCH_VARIANTS)
+    return fail(HWENO_ERR_INVALID_ARG, "variant must be in [0, %d)", HWENO_BATCH_VARIANTS);
+  if (blocks < 0) return fail(HWENO_ERR_INVALID_ARG, "blocks must be >= 0");
+  hipStream_t s = (hipStream_t)stream;
+  if (common->dtype == HWENO_F64) {
+    st = variant == 0 ? run_batched<double, 0>(common, inst_dev, n_inst, total_tiles, blocks, s)
+                      : run_batched<double, 1>(common, inst_dev, n_inst, total_tiles, blocks, s);
+  } else {
+    st = variant == 0 ? run_batched<float, 0>(common, inst_dev, n_inst, total_tiles, blocks, s)
+                      : run_batched<float, 1>(common, inst_dev, n_inst, total_tiles, blocks, s);
+  }
+  if (st) return st;
+  return ok();
 }
 
 hweno_status hweno_timing_begin(int32_t enable) {

@@ -46,6 +46,20 @@ class _CProblem(ctypes.Structure):
     ]
 
 
+class _CInstance(ctypes.Structure):
+    _fields_ = [
+        ("state", ctypes.c_void_p), ("ws", ctypes.c_void_p),
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
+        ("dx", ctypes.c_double), ("dy", ctypes.c_double),
+        ("dt_fixed", ctypes.c_double), ("t_end", ctypes.c_double),
+        ("ws_bytes", ctypes.c_int64),
+        ("off_s1", ctypes.c_int64), ("off_s2", ctypes.c_int64), ("off_base", ctypes.c_int64),
+        ("tile_begin", ctypes.c_int32 * 2), ("n_tiles", ctypes.c_int32 * 2),
+    ]
+
+
+BATCH_VARIANTS = 2
 _lib = None
 
 
@@ -68,6 +82,10 @@ def lib() -> ctypes.CDLL:
             "hweno_rk3_step": ([P, vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
                                 vp, vp, vp], ctypes.c_int),
             "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+            "hweno_batch_prepare": ([P, ctypes.POINTER(_CInstance), ctypes.c_int32,
+                                     ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+            "hweno_rk3_step_batched": ([P, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.c_int32, vp], ctypes.c_int),
             "hweno_timing_begin": ([ctypes.c_int32], ctypes.c_int),
             "hweno_timing_end": ([ctypes.POINTER(ctypes.c_int64), dp], ctypes.c_int),
             "hweno_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -269,3 +287,126 @@ def timing_end() -> Tuple[int, float]:
 def rk3_step_(S: torch.Tensor, prob: Problem, dt: Optional[float] = None) -> torch.Tensor:
     """One in-place step with a throw-away workspace (convenience)."""
     return Stepper(prob, device=S.device).step(S, dt=dt)
+
+
+class BatchedStepper:
+    """Many independent 2D Euler grids advanced together (hweno_rk3_step_batched).
+
+    ``states``: list of GPU tensors [12, ny_k, nx_k] (advanced in place);
+    ``grids``: list of dicts with dx, dy, bc_x, bc_y (and optional dt_fixed,
+    t_end) per instance; ``common``: the shared Problem (weights, eps, cfl,
+    dtype, ...).  All workspaces live in one caller-side buffer.
+    """
+
+    def __init__(self, states, grids, common: Problem):
+        if common.dim != 2 or common.physics != "euler":
+            raise ValueError("batched stepping is for 2D Euler")
+        n = len(states)
+        if n < 1 or len(grids) != n:
+            raise ValueError("need one grid description per state")
+        self.common = common
+        self._c = common.c()
+        self.states = states
+        self.n = n
+        arr = (_CInstance * n)()
+        for q, (S, g) in enumerate(zip(states, grids)):
+            _require(S, Problem(dim=2, nx=S.shape[2], ny=S.shape[1], dtype=common.dtype), 12, "state")
+            I = arr[q]
+            I.nx, I.ny = S.shape[2], S.shape[1]
+            I.bc_x, I.bc_y = int(g.get("bc_x", PERIODIC)), int(g.get("bc_y", PERIODIC))
+            I.dx, I.dy = float(g["dx"]), float(g["dy"])
+            I.dt_fixed = float(g.get("dt_fixed", 0.0) or 0.0)
+            I.t_end = float(g.get("t_end", 0.0) or 0.0)
+        tot = (ctypes.c_int32 * BATCH_VARIANTS)()
+        _check(lib().hweno_batch_prepare(ctypes.byref(self._c), arr, n, tot), "hweno_batch_prepare")
+        self.total_tiles = [int(t) for t in tot]
+        offs, total = [], 0
+        for q in range(n):
+            offs.append(total)
+            total += (int(arr[q].ws_bytes) + 255) // 256 * 256
+        device = states[0].device
+        raw = torch.zeros(total + 256, dtype=torch.uint8, device=device)
+        base = (-raw.data_ptr()) % 256
+        self.ws = raw[base:base + total]
+        for q in range(n):
+            arr[q].state = states[q].data_ptr()
+            arr[q].ws = self.ws.data_ptr() + offs[q]
+        self._offs = offs
+        self._host = arr
+        blob = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
+        self.desc = blob.to(device)
+        self.cells = sum(int(S.shape[1]) * int(S.shape[2]) for S in states)
+        self.variant = 0
+        self.blocks = 0
+        self.graph = None
+
+    def ctrl(self, q: int) -> torch.Tensor:
+        o = self._offs[q]
+        return self.ws[o:o + CTRL_LEN * 8].view(torch.float64)
+
+    def step(self, variant: Optional[int] = None, blocks: Optional[int] = None):
+        v = self.variant if variant is None else int(variant)
+        b = self.blocks if blocks is None else int(blocks)
+        _check(lib().hweno_rk3_step_batched(ctypes.byref(self._c), self.desc.data_ptr(), self.n,
+                                            self.total_tiles[v], v, b, _stream()),
+               "hweno_rk3_step_batched")
+
+    def statuses(self):
+        return [int(self.ctrl(q)[8:9].view(torch.int64).item()) for q in range(self.n)]
+
+    def capture(self, steps: int = 1):
+        """Capture ``steps`` batched steps (speeds, 3 stages, time update each) in one graph."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    self.step()
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+
+_AUTOTUNE_CACHE = {}
+
+
+def autotune_batched(stepper: BatchedStepper, trials: int = 2):
+    """Choose tile variant and persistent grid size by timing steps on scratch copies.
+
+    Runs on clones of the states (the originals are untouched), keeps the
+    fastest configuration in ``stepper`` and in a process-wide cache keyed by
+    the batch's dtype, instance count and total cell count.
+    """
+    key = (stepper.common.dtype, stepper.n, stepper.cells)
+    if key in _AUTOTUNE_CACHE:
+        stepper.variant, stepper.blocks = _AUTOTUNE_CACHE[key]
+        return _AUTOTUNE_CACHE[key], None
+    cus = torch.cuda.get_device_properties(stepper.states[0].device).multi_processor_count
+    scratch_states = [S.clone() for S in stepper.states]
+    grids = [dict(nx=int(stepper._host[q].nx), dx=stepper._host[q].dx, dy=stepper._host[q].dy,
+                  bc_x=stepper._host[q].bc_x, bc_y=stepper._host[q].bc_y,
+                  dt_fixed=stepper._host[q].dt_fixed, t_end=stepper._host[q].t_end)
+             for q in range(stepper.n)]
+    scratch = BatchedStepper(scratch_states, grids, stepper.common)
+    results = {}
+    for v in range(BATCH_VARIANTS):
+        for b in (0, 2 * cus, 4 * cus, 16 * cus):
+            scratch.step(v, b)  # warm-up
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(trials):
+                scratch.step(v, b)
+            e1.record()
+            torch.cuda.synchronize()
+            results[(v, b)] = e0.elapsed_time(e1) / trials
+    best = min(results, key=results.get)
+    del scratch, scratch_states
+    stepper.variant, stepper.blocks = best
+    _AUTOTUNE_CACHE[key] = best
+    return best, results

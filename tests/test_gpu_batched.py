@@ -1,0 +1,137 @@
+"""Batched uneven 2D Euler instances: the persistent batched kernels against
+per-instance hweno_rk3_step (bitwise: same arithmetic) and against the oracle,
+plus hipGraph capture and replay."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import hweno_inputs as hi
+from oracle import hweno_ref as o
+from tests import parity as P
+
+pytestmark = pytest.mark.gpu
+
+h = pytest.importorskip("paper_2207_05258_amd")
+
+
+def announce(*what):
+    print("\n[case]", *what, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    h.lib()
+    yield
+    torch.cuda.synchronize()
+
+
+def _batch(ws, dtype, **common_kw):
+    states = [P.to_gpu(w, dtype) for w in ws]
+    grids = [dict(dx=w.dx, dy=w.dy, bc_x=w.bc_x, bc_y=w.bc_y) for w in ws]
+    common = h.Problem(dim=2, nx=1, ny=1, physics="euler", dtype=dtype, **common_kw)
+    return states, grids, common
+
+
+def _individual(ws, dtype, steps=1, **common_kw):
+    outs, ctrls = [], []
+    for w in ws:
+        S = P.to_gpu(w, dtype)
+        st = h.Stepper(P.gpu_problem(w, dtype, **common_kw))
+        for _ in range(steps):
+            st.step(S)
+        outs.append(S)
+        ctrls.append(st.ctrl.clone())
+    return outs, ctrls
+
+
+UNEVEN = [(37, 29), (16, 15), (5, 3), (64, 7), (1, 1), (33, 46), (100, 18)]
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_batched_equals_individual_bitwise(variant, dtype):
+    ws = hi.batched_instances(len(UNEVEN), 3, sizes=UNEVEN)
+    announce("batched == individual", variant, dtype)
+    states, grids, common = _batch(ws, dtype)
+    b = h.BatchedStepper(states, grids, common)
+    for _ in range(2):
+        b.step(variant=variant)
+    ref, ctrls = _individual(ws, dtype, steps=2)
+    for q in range(len(ws)):
+        assert torch.equal(states[q], ref[q]), (q, ws[q].name)
+        assert torch.equal(b.ctrl(q)[:10], ctrls[q][:10]), q
+
+
+def test_batched_against_oracle():
+    ws = hi.batched_instances(4, 11, sizes=[(40, 23), (18, 35), (64, 16), (9, 9)])
+    announce("batched vs oracle")
+    states, grids, common = _batch(ws, torch.float64)
+    S0 = [P.exact_input(S) for S in states]
+    b = h.BatchedStepper(states, grids, common)
+    b.step(variant=1, blocks=3)
+    for q, w in enumerate(ws):
+        ref, dt, _ = o.rk3_step(S0[q], P.oracle_problem(w))
+        assert float(b.ctrl(q)[6]) == pytest.approx(dt, rel=1e-13)
+        P.assert_within(P.step_errors(states[q], ref, w), 1e-12, f"batched {w.name}")
+
+
+def test_batched_per_instance_time_control():
+    ws = hi.batched_instances(3, 5, sizes=[(20, 20), (24, 16), (16, 24)])
+    announce("batched dt/t_end")
+    states, grids, common = _batch(ws, torch.float64)
+    grids[0]["dt_fixed"] = 1e-4
+    grids[1]["t_end"] = 1e-12       # reached after the first (tiny) step
+    S0 = [S.clone() for S in states]
+    b = h.BatchedStepper(states, grids, common)
+    b.step()
+    b.step()
+    assert float(b.ctrl(0)[6]) == 1e-4 and float(b.ctrl(0)[7]) == pytest.approx(2e-4)
+    assert float(b.ctrl(1)[7]) == pytest.approx(1e-12, rel=1e-9)
+    assert b.statuses()[1] & h.hweno.ST_SKIPPED
+    assert float(b.ctrl(1)[9]) == 1.0 and float(b.ctrl(2)[9]) == 2.0
+    ref, _, _ = o.rk3_step(P.exact_input(S0[0]), P.oracle_problem(ws[0]), 1e-4)
+    ref, _, _ = o.rk3_step(ref, P.oracle_problem(ws[0]), 1e-4)
+    P.assert_within(P.step_errors(states[0], ref, ws[0]), 1e-12, "fixed dt instance")
+
+
+def test_batched_graph_replays_match_eager():
+    ws = hi.batched_instances(9, 2, side_lo=20, side_hi=70)
+    announce("graph replay")
+    states, grids, common = _batch(ws, torch.float32)
+    eager_states = [S.clone() for S in states]
+    b = h.BatchedStepper(states, grids, common)
+    e = h.BatchedStepper(eager_states, grids, common)
+    b.capture(steps=1)
+    for r in range(4):
+        b.replay()
+        e.step()
+        torch.cuda.synchronize()
+        # eager work of the program between replays
+        junk = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        for q in range(len(ws)):
+            assert torch.equal(states[q], eager_states[q]), (r, q)
+            assert torch.equal(b.ctrl(q)[:10], e.ctrl(q)[:10]), (r, q)
+        del junk
+
+
+def test_batched_full_config_256_instances():
+    """The configured batch: 256 instances, sides ~ U{64..512}, FP32, autotuned."""
+    ws = hi.batched_instances(256, 0)
+    announce("256 instances")
+    states, grids, common = _batch(ws, torch.float32)
+    b = h.BatchedStepper(states, grids, common)
+    best, res = h.autotune_batched(b)
+    assert best in res
+    b.step()
+    torch.cuda.synchronize()
+    assert all(s == 0 for s in b.statuses())
+    rng = np.random.default_rng(1)
+    for q in sorted(rng.choice(256, size=8, replace=False)):
+        ref, ctrls = _individual([ws[q]], torch.float32)
+        assert torch.equal(states[q], ref[0]), q
