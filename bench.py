@@ -150,6 +150,41 @@ def run_batched(steps: int, warmup: int, n_inst: int = 256, seed: int = 0):
             "graph": "one hipGraph per step (speeds, 3 persistent stages, time update)"}
 
 
+def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 20, dtype_name: str = "f32"):
+    """Differentiable rollout on a smooth periodic 2D Euler state: forward with
+    checkpoints, backward by segment recomputation and hand-written step
+    adjoints; loss = 1/2 sum dx dy (rho_N - rho_target)^2."""
+    import torch
+
+    import hweno_inputs as hi
+    import paper_2207_05258_amd as h
+    dtype = torch.float64 if dtype_name == "f64" else torch.float32
+    base, target = hi.adjoint_pair(n, 0)
+    prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=dtype, dx=base.dx, dy=base.dy)
+    U0 = torch.as_tensor(base.S).to(dtype).cuda().contiguous()
+    tgt = torch.as_tensor(target.S[0]).to(dtype).cuda()
+    # warm-up (compiles nothing, but touches every kernel once)
+    X = U0.clone().requires_grad_(True)
+    S = h.Rollout.apply(X, prob, 2, 2, None)
+    (0.5 * base.dx * base.dy * ((S[0] - tgt) ** 2).sum()).backward()
+    torch.cuda.synchronize()
+    X = U0.clone().requires_grad_(True)
+    t0 = time.perf_counter()
+    S = h.Rollout.apply(X, prob, steps, ckpt, None)
+    loss = 0.5 * base.dx * base.dy * ((S[0] - tgt) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, bwd = t1 - t0, t2 - t1
+    g = X.grad
+    return {"grid": f"{n}x{n}", "dtype": dtype_name, "steps": steps, "checkpoint_every": ckpt,
+            "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3, "backward_over_forward": bwd / fwd,
+            "loss": float(loss.detach()),
+            "grad_finite": bool(torch.isfinite(g).all()), "grad_norm_U": float(g[:4].norm())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -162,6 +197,7 @@ def main():
                     help="skip the secondary run in the other precision")
     ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
@@ -210,6 +246,12 @@ def main():
         print(f"# batched: {batched['value']:.4e} cell-stage/s "
               f"(ratio {batched['ratio_vs_single_grid_f32']})", file=sys.stderr, flush=True)
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = run_adjoint()
+        print(f"# adjoint: backward/forward {adjoint['backward_over_forward']:.2f}",
+              file=sys.stderr, flush=True)
+
     sha = kernel_sha()
     traffic = MEASURED_TRAFFIC.get((sha, args.dtype, args.n))
     roofline = {
@@ -246,6 +288,7 @@ def main():
         "cpu_baseline": cpu,
         "variant": variant,
         "batched": batched,
+        "adjoint": adjoint,
         "status_word": main_run["status"],
         "kernel_sha": sha,
     }

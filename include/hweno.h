@@ -156,17 +156,37 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws,
                             size_t ws_bytes, double dt_fixed, double t_end,
                             double* tape, const double* replay, void* stream);
 
-/* Vector-Jacobian product of one stage with frozen wave speeds (discrete
- * adjoint of eqs. odeH / ode2H and of the limiter of Section 2.2):
+/* Bytes of device workspace the adjoint entry points need for `prob`
+ * (a ghost-padded adjoint buffer and three stage adjoints).  0 if invalid. */
+size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob);
+
+/* Vector-Jacobian product of the right-hand side and the limiter with frozen
+ * wave speeds (discrete adjoint of eqs. odeH / ode2H with the reconstruction
+ * of Section 2.1, and of the limiter of Section 2.2):
  *   lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim
- * alpha: device double[2], the speeds the forward stage used (replayed);
- * the absolute values in tau are differentiated with sign(0) = 0.
- * lam_rhs: nf fields; lam_lim: m * dim fields or NULL; lam_state: nf fields,
- * accumulated into. */
+ * evaluated at `state`.  The absolute values in tau are differentiated as
+ * sign(x) with sign(0) = 0; ghost cells are differentiated through the
+ * boundary index maps (periodic wrap, outflow copy).
+ * alpha: device double[2], the speeds of the forward evaluation (replayed).
+ * lam_rhs: nf fields; lam_lim: m * dim fields (limited-derivative layout of
+ * hweno_limit) or NULL; lam_state: nf fields, accumulated into.
+ * ws: device workspace of >= hweno_adjoint_workspace_bytes(prob) bytes. */
 hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
                                const double* alpha, const void* lam_rhs,
-                               const void* lam_lim, void* lam_state,
-                               void* stream);
+                               const void* lam_lim, void* lam_state, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* Discrete adjoint of one hweno_rk3_step taken with `tape` (speeds of the
+ * three stages and dt held fixed):
+ *   lam <- (d S^{n+1} / d S^n)^T lam        (in place)
+ * state0: S^n, the step's input; step_ws: the workspace of a forward step
+ * from state0 taken with that tape (it holds the stage states S1, S2 until
+ * the next step on it); tape: device double[HWENO_CTRL_LEN] (as written by
+ * hweno_rk3_step); ws: >= hweno_adjoint_workspace_bytes(prob) bytes. */
+hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state0,
+                                    const void* step_ws, size_t step_ws_bytes,
+                                    const double* tape, void* lam, void* ws,
+                                    size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------------------
  * Batched 2D Euler: many independent grids advanced by one persistent launch

@@ -1,0 +1,557 @@
+// Hand-written reverse-mode derivatives (vector-Jacobian products) of the
+// device math in hweno_math.h: the discrete adjoint of the semi-discrete
+// operator (eqs. odeH / ode2H with the reconstruction of Section 2.1) and of
+// the limiter (Section 2.2), with the Lax-Friedrichs speeds held fixed.
+//
+// Conventions: every *_vjp function recomputes the forward quantities it
+// needs from the same inputs and ACCUMULATES (+=) the input adjoints.
+// |x| is differentiated as sign(x) with sign(0) = 0.
+#pragma once
+
+#include "hweno_math.h"
+
+namespace hweno {
+
+template <typename T>
+HW_HD T sgn(T x) {
+  return T((x > T(0)) - (x < T(0)));
+}
+
+// reverse of combine(): adjoints of P0, P1, P2 and b0, b1, b2 (overwritten)
+template <typename T>
+HW_HD void combine_vjp(T P0, T P1, T P2, T b0, T b1, T b2, const Weights<T>& w, T g,
+                       T& gP0, T& gP1, T& gP2, T& gb0, T& gb1, T& gb2) {
+  const T d01 = b0 - b1, d02 = b0 - b2;
+  const T sa = fabs(d01) + fabs(d02);
+  const T tau = T(0.25) * sa * sa;
+  const T i0 = T(1) / (b0 + w.eps), i1 = T(1) / (b1 + w.eps), i2 = T(1) / (b2 + w.eps);
+  const T e0 = T(1) + tau * i0, e1 = T(1) + tau * i1, e2 = T(1) + tau * i2;
+  const T iden = T(1) / (w.g0 * e0 + w.g1 * e1 + w.g2 * e2);
+  const T r = (e0 * P0 + w.g1 * P1 * (e1 - e0) + w.g2 * P2 * (e2 - e0)) * iden;
+  const T gi = g * iden;
+  gP0 = gi * e0;
+  gP1 = gi * w.g1 * (e1 - e0);
+  gP2 = gi * w.g2 * (e2 - e0);
+  const T ge0 = gi * (P0 - w.g1 * P1 - w.g2 * P2 - w.g0 * r);
+  const T ge1 = gi * w.g1 * (P1 - r);
+  const T ge2 = gi * w.g2 * (P2 - r);
+  const T gs = T(0.5) * sa * (ge0 * i0 + ge1 * i1 + ge2 * i2);  // d tau / d sa = sa / 2
+  const T s01 = sgn(d01), s02 = sgn(d02);
+  gb0 = -ge0 * tau * i0 * i0 + gs * (s01 + s02);
+  gb1 = -ge1 * tau * i1 * i1 - gs * s01;
+  gb2 = -ge2 * tau * i2 * i2 - gs * s02;
+}
+
+// reverse of hw_plus()
+template <typename T>
+HW_HD void hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, T g, T& gfm,
+                       T& gf0, T& gfp, T& gHm, T& gH0, T& gHp) {
+  const T s = fm + fp, dl = fm - fp, lap = s - T(2) * f0;
+  const T Hs = Hm + Hp, Hd = Hm - Hp;
+  const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
+  const T p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
+  const T p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
+  const T a1 = T(19.0 / 192.0) * Hs + T(79.0 / 48.0) * H0 + T(27.0 / 64.0) * dl;
+  const T a2 = T(0.375) * Hd + T(1.25) * lap;
+  const T a3 = -(T(11.0 / 24.0) * Hs + T(17.0 / 6.0) * H0) - T(1.875) * dl;
+  const T a4 = T(-0.25) * Hd - T(0.5) * lap;
+  const T a5 = T(0.25) * Hs + H0 + T(0.75) * dl;
+  const T t0 = a1 + T(0.25) * a3 + T(0.0625) * a5;
+  const T t1 = a2 + T(63.0 / 130.0) * a4;
+  const T t2 = a3 + T(8825.0 / 10934.0) * a5;
+  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * t2 * t2 +
+               T(1421461.0 / 2275.0) * a4 * a4 + T(21520059541.0 / 1377684.0) * a5 * a5;
+  const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp, h2 = H0 * H0;
+  const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
+  const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
+  T gp0, gp1, gp2, gb0, gb1, gb2;
+  combine_vjp(p0, p1, p2, b0, b1, b2, w, g, gp0, gp1, gp2, gb0, gb1, gb2);
+  // smoothness indicators
+  const T gt0 = T(2) * t0 * gb0;
+  const T gt1 = T(26.0 / 3.0) * t1 * gb0;
+  const T gt2 = T(781.0 / 10.0) * t2 * gb0;
+  const T ga1 = gt0;
+  const T ga2 = gt1;
+  const T ga3 = T(0.25) * gt0 + gt2;
+  const T ga4 = T(2.0 * 1421461.0 / 2275.0) * a4 * gb0 + T(63.0 / 130.0) * gt1;
+  const T ga5 = T(2.0 * 21520059541.0 / 1377684.0) * a5 * gb0 + T(0.0625) * gt0 +
+                T(8825.0 / 10934.0) * gt2;
+  const T gu1 = T(26.0 / 3.0) * u1 * gb1;
+  const T gu2 = T(26.0 / 3.0) * u2 * gb2;
+  T gH0_ = T(2) * H0 * (gb1 + gb2) + gu1 + gu2;
+  T gfm_ = gu1, gf0_ = gu2 - gu1, gfp_ = -gu2;
+  // candidate values
+  T gs_ = T(11.0 / 60.0) * gp0;
+  gf0_ += T(19.0 / 30.0) * gp0;
+  T gHd = T(0.05) * gp0;
+  gH0_ += T(0.5) * gp0;
+  gfm_ += T(1.0 / 6.0) * gp1;
+  gf0_ += T(5.0 / 6.0) * gp1 + T(5.0 / 6.0) * gp2;
+  gH0_ += T(2.0 / 3.0) * gp1 + T(1.0 / 3.0) * gp2;
+  gfp_ += T(1.0 / 6.0) * gp2;
+  // monomial coefficients
+  const T gHs = T(19.0 / 192.0) * ga1 - T(11.0 / 24.0) * ga3 + T(0.25) * ga5;
+  gH0_ += T(79.0 / 48.0) * ga1 - T(17.0 / 6.0) * ga3 + ga5;
+  const T gdl = T(27.0 / 64.0) * ga1 - T(1.875) * ga3 + T(0.75) * ga5;
+  gHd += T(0.375) * ga2 - T(0.25) * ga4;
+  const T glap = T(1.25) * ga2 - T(0.5) * ga4;
+  gs_ += glap;
+  gf0_ -= T(2) * glap;
+  gfm += gfm_ + gs_ + gdl;
+  gfp += gfp_ + gs_ - gdl;
+  gf0 += gf0_;
+  gHm += gHs + gHd;
+  gHp += gHs - gHd;
+  gH0 += gH0_;
+}
+
+// reverse of limit1()
+template <typename T>
+HW_HD void limit1_vjp(T um, T u0, T up, T vm, T vp, T h, T ih, const Weights<T>& w, T g,
+                      T& gum, T& gu0, T& gup, T& gvm, T& gvp) {
+  const T Vs = h * (vm + vp), Vd = h * (vm - vp);
+  const T lap = um - T(2) * u0 + up;
+  const T a1 = T(0.75) * (up - um) - T(0.25) * Vs;
+  const T a2 = T(0.25) * Vd + lap;
+  const T a3 = T(0.25) * Vs + T(0.25) * (um - up);
+  const T a4 = T(-0.25) * Vd - T(0.5) * lap;
+  const T t0 = a1 + T(0.25) * a3;
+  const T t1 = a2 + T(63.0 / 130.0) * a4;
+  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * a3 * a3 +
+               T(1421461.0 / 2275.0) * a4 * a4;
+  const T d1 = u0 - um, d2 = up - u0;
+  T gP0, gP1, gP2, gb0, gb1, gb2;
+  combine_vjp(a1 * ih, d1 * ih, d2 * ih, b0, d1 * d1, d2 * d2, w, g, gP0, gP1, gP2, gb0, gb1, gb2);
+  const T gd1 = gP1 * ih + T(2) * d1 * gb1;
+  const T gd2 = gP2 * ih + T(2) * d2 * gb2;
+  const T gt0 = T(2) * t0 * gb0;
+  const T gt1 = T(26.0 / 3.0) * t1 * gb0;
+  const T ga1 = gP0 * ih + gt0;
+  const T ga2 = gt1;
+  const T ga3 = T(781.0 / 10.0) * a3 * gb0 + T(0.25) * gt0;
+  const T ga4 = T(2.0 * 1421461.0 / 2275.0) * a4 * gb0 + T(63.0 / 130.0) * gt1;
+  const T gVs = T(-0.25) * ga1 + T(0.25) * ga3;
+  const T gVd = T(0.25) * ga2 - T(0.25) * ga4;
+  const T glap = ga2 - T(0.5) * ga4;
+  gup += T(0.75) * ga1 - T(0.25) * ga3 + glap + gd2;
+  gum += T(-0.75) * ga1 + T(0.25) * ga3 + glap - gd1;
+  gu0 += T(-2) * glap + gd1 - gd2;
+  gvm += h * (gVs + gVd);
+  gvp += h * (gVs - gVd);
+}
+
+// reverse of point_fluxes(): from adjoints of F, A = A_n Dn, B = A_n Dt
+template <typename T, int PHYS, int M, bool MIXED>
+HW_HD void point_fluxes_vjp(const T* U, const T* Dn, const T* Dt, const Consts<T>& k, T an,
+                            const T* gF, const T* gA, const T* gB, T* gU, T* gDn, T* gDt) {
+  if constexpr (PHYS == PH_EULER) {
+    const T rho = U[0], mn = U[1], mt = (M == 4) ? U[2] : T(0), E = U[M - 1];
+    const T ir = T(1) / rho;
+    const T un = mn * ir, ut = mt * ir;
+    const T q2 = un * un + ut * ut;
+    const T p = k.gm1 * (E - T(0.5) * rho * q2);
+    const T Ep = E + p;
+    T grho = 0, gmn = 0, gmt = 0, gE = 0, gun = 0, gut = 0, gq2 = 0, gEp = 0, gp = 0, gir = 0;
+    // F = (mn, mn un + p, mn ut, un Ep)
+    gmn += gF[0] + un * gF[1];
+    gun += mn * gF[1];
+    gp += gF[1];
+    if constexpr (M == 4) {
+      gmn += ut * gF[2];
+      gut += mn * gF[2];
+    }
+    gun += Ep * gF[M - 1];
+    gEp += un * gF[M - 1];
+    auto jvp_vjp = [&](const T* D, const T* go, T* gD) {
+      const T r = D[0], a = D[1], b = (M == 4) ? D[2] : T(0), e = D[M - 1];
+      const T us = (a - un * r) * ir;
+      const T ts = (b - ut * r) * ir;
+      const T ps = k.gm1 * (e - un * a - ut * b + T(0.5) * q2 * r);
+      T gr = 0, ga = go[0], gb = 0, ge = 0, gus = 0, gts = 0, gps = 0;
+      // out1 = a un + mn us + ps
+      ga += un * go[1];
+      gun += a * go[1];
+      gmn += us * go[1];
+      gus += mn * go[1];
+      gps += go[1];
+      if constexpr (M == 4) {  // out2 = a ut + mn ts
+        ga += ut * go[2];
+        gut += a * go[2];
+        gmn += ts * go[2];
+        gts += mn * go[2];
+      }
+      // out3 = us Ep + un (e + ps)
+      gus += Ep * go[M - 1];
+      gEp += us * go[M - 1];
+      gun += (e + ps) * go[M - 1];
+      ge += un * go[M - 1];
+      gps += un * go[M - 1];
+      // ps = gm1 (e - un a - ut b + q2 r / 2)
+      const T gq = k.gm1 * gps;
+      ge += gq;
+      gun -= a * gq;
+      ga -= un * gq;
+      gut -= b * gq;
+      gb -= ut * gq;
+      gq2 += T(0.5) * r * gq;
+      gr += T(0.5) * q2 * gq;
+      // ts = (b - ut r) ir, us = (a - un r) ir
+      gb += ir * gts;
+      gut -= r * ir * gts;
+      gr -= ut * ir * gts;
+      gir += (b - ut * r) * gts;
+      ga += ir * gus;
+      gun -= r * ir * gus;
+      gr -= un * ir * gus;
+      gir += (a - un * r) * gus;
+      gD[0] += gr;
+      gD[1] += ga;
+      if constexpr (M == 4) gD[2] += gb;
+      gD[M - 1] += ge;
+    };
+    jvp_vjp(Dn, gA, gDn);
+    if constexpr (MIXED) jvp_vjp(Dt, gB, gDt);
+    gE += gEp;
+    gp += gEp;
+    gE += k.gm1 * gp;
+    grho -= T(0.5) * k.gm1 * q2 * gp;
+    gq2 -= T(0.5) * k.gm1 * rho * gp;
+    gun += T(2) * un * gq2;
+    gut += T(2) * ut * gq2;
+    gmn += ir * gun;
+    gir += mn * gun;
+    gmt += ir * gut;
+    gir += mt * gut;
+    grho -= ir * ir * gir;
+    gU[0] += grho;
+    gU[1] += gmn;
+    if constexpr (M == 4) gU[2] += gmt;
+    gU[M - 1] += gE;
+  } else if constexpr (PHYS == PH_BURGERS) {
+    gU[0] += U[0] * gF[0] + Dn[0] * gA[0];
+    gDn[0] += U[0] * gA[0];
+    if constexpr (MIXED) {
+      gU[0] += Dt[0] * gB[0];
+      gDt[0] += U[0] * gB[0];
+    }
+  } else {
+    gU[0] += an * gF[0];
+    gDn[0] += an * gA[0];
+    if constexpr (MIXED) gDt[0] += an * gB[0];
+  }
+}
+
+// adjoints of the Roe eigen-system quantities used by project() / back()
+template <typename T>
+struct EigenAdj {
+  T un = 0, ut = 0, H = 0, c = 0, ic = 0, b1 = 0, b2 = 0, hq2 = 0;
+};
+
+// reverse of Eigen::project(): gx = L^T gw, plus eigen-system adjoints
+template <typename T, int M>
+HW_HD void project_vjp(const Eigen<T, M>& e, const T* x, const T* gw, T* gx, EigenAdj<T>& ge) {
+  if constexpr (M == 4) {
+    const T gphi = T(0.5) * gw[0] - gw[1] + T(0.5) * gw[3];
+    const T gpsi = T(0.5) * (gw[0] - gw[3]);
+    gx[0] = e.b2 * gphi + e.un * e.ic * gpsi + gw[1] - e.ut * gw[2];
+    gx[1] = -e.b1 * e.un * gphi - e.ic * gpsi;
+    gx[2] = -e.b1 * e.ut * gphi + gw[2];
+    gx[3] = e.b1 * gphi;
+    ge.b2 += x[0] * gphi;
+    ge.b1 -= (e.un * x[1] + e.ut * x[2] - x[3]) * gphi;
+    ge.un += -e.b1 * x[1] * gphi + e.ic * x[0] * gpsi;
+    ge.ut += -e.b1 * x[2] * gphi - x[0] * gw[2];
+    ge.ic += (e.un * x[0] - x[1]) * gpsi;
+  } else {
+    const T gphi = T(0.5) * gw[0] - gw[1] + T(0.5) * gw[2];
+    const T gpsi = T(0.5) * (gw[0] - gw[2]);
+    gx[0] = e.b2 * gphi + e.un * e.ic * gpsi + gw[1];
+    gx[1] = -e.b1 * e.un * gphi - e.ic * gpsi;
+    gx[2] = e.b1 * gphi;
+    ge.b2 += x[0] * gphi;
+    ge.b1 -= (e.un * x[1] - x[2]) * gphi;
+    ge.un += -e.b1 * x[1] * gphi + e.ic * x[0] * gpsi;
+    ge.ic += (e.un * x[0] - x[1]) * gpsi;
+  }
+}
+
+// reverse of Eigen::back(): gw = R^T gy, plus eigen-system adjoints
+template <typename T, int M>
+HW_HD void back_vjp(const Eigen<T, M>& e, const T* w, const T* gy, T* gw, EigenAdj<T>& ge) {
+  if constexpr (M == 4) {
+    const T s = w[0] + w[1] + w[3], dif = w[3] - w[0];
+    const T gs = gy[0] + e.un * gy[1] + e.ut * gy[2];
+    const T gdif = e.c * gy[1] + e.un * e.c * gy[3];
+    gw[0] = gs - gdif + e.H * gy[3];
+    gw[1] = gs + e.hq2 * gy[3];
+    gw[2] = gy[2] + e.ut * gy[3];
+    gw[3] = gs + gdif + e.H * gy[3];
+    ge.un += s * gy[1] + e.c * dif * gy[3];
+    ge.c += dif * gy[1] + e.un * dif * gy[3];
+    ge.ut += s * gy[2] + w[2] * gy[3];
+    ge.H += (w[0] + w[3]) * gy[3];
+    ge.hq2 += w[1] * gy[3];
+  } else {
+    const T s = w[0] + w[1] + w[2], dif = w[2] - w[0];
+    const T gs = gy[0] + e.un * gy[1];
+    const T gdif = e.c * gy[1] + e.un * e.c * gy[2];
+    gw[0] = gs - gdif + e.H * gy[2];
+    gw[1] = gs + e.hq2 * gy[2];
+    gw[2] = gs + gdif + e.H * gy[2];
+    ge.un += s * gy[1] + e.c * dif * gy[2];
+    ge.c += dif * gy[1] + e.un * dif * gy[2];
+    ge.H += (w[0] + w[2]) * gy[2];
+    ge.hq2 += w[1] * gy[2];
+  }
+}
+
+// reverse of Eigen::roe(): eigen-system adjoints -> adjoints of UL, UR (accumulated)
+template <typename T, int M>
+HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL, T* gUR) {
+  const T irL = T(1) / UL[0], irR = T(1) / UR[0];
+  const T sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+  const T uL = UL[1] * irL, uR = UR[1] * irR;
+  const T tL = (M == 4) ? UL[2] * irL : T(0), tR = (M == 4) ? UR[2] * irR : T(0);
+  const T pL = gm1 * (UL[M - 1] - T(0.5) * UL[0] * (uL * uL + tL * tL));
+  const T pR = gm1 * (UR[M - 1] - T(0.5) * UR[0] * (uR * uR + tR * tR));
+  const T HL = (UL[M - 1] + pL) * irL, HR = (UR[M - 1] + pR) * irR;
+  const T iw = T(1) / (sL + sR);
+  const T wL = sL * iw, wR = sR * iw;
+  const T un = wL * uL + wR * uR, ut = wL * tL + wR * tR, H = wL * HL + wR * HR;
+  const T hq2 = T(0.5) * (un * un + ut * ut);
+  const T c = sqrt(gm1 * (H - hq2));
+  const T ic = T(1) / c;
+  const T b1 = gm1 * ic * ic;
+  // b2 = b1 hq2, b1 = gm1 ic^2, ic = 1/c, c = sqrt(gm1 (H - hq2))
+  const T gb1 = g.b1 + hq2 * g.b2;
+  T ghq2 = g.hq2 + b1 * g.b2;
+  const T gic = g.ic + T(2) * gm1 * ic * gb1;
+  const T gc = g.c - ic * ic * gic;
+  const T gcc = gm1 * T(0.5) * ic * gc;
+  const T gH = g.H + gcc;
+  ghq2 -= gcc;
+  const T gun = g.un + un * ghq2, gut = g.ut + ut * ghq2;
+  // Roe weights
+  const T gwL = uL * gun + tL * gut + HL * gH, gwR = uR * gun + tR * gut + HR * gH;
+  const T giw = sL * gwL + sR * gwR;
+  const T gsL = iw * gwL - iw * iw * giw, gsR = iw * gwR - iw * iw * giw;
+  auto side = [&](const T* U, T ir, T s, T u, T t, T p, T w, T gs, T* gU) {
+    const T gHs = w * gH, gu = w * gun, gt = w * gut;
+    T gE = ir * gHs, gp = ir * gHs, gir = (U[M - 1] + p) * gHs;
+    gE += gm1 * gp;
+    T grho = -T(0.5) * gm1 * (u * u + t * t) * gp;
+    const T gu2 = gu - gm1 * U[0] * u * gp;
+    const T gt2 = gt - gm1 * U[0] * t * gp;
+    const T gm = ir * gu2;
+    gir += U[1] * gu2;
+    T gn = 0;
+    if constexpr (M == 4) {
+      gn = ir * gt2;
+      gir += U[2] * gt2;
+    }
+    grho += T(0.5) * gs / s - ir * ir * gir;
+    gU[0] += grho;
+    gU[1] += gm;
+    if constexpr (M == 4) gU[2] += gn;
+    gU[M - 1] += gE;
+  };
+  side(UL, irL, sL, uL, tL, pL, wL, gsL, gUL);
+  side(UR, irR, sR, uR, tR, pR, wR, gsR, gUR);
+}
+
+// ---------------------------------------------------------------------------
+// VJP of interface_fluxes(): given the adjoints of f-hat, h-hat and the mixed
+// flux (normal frame), emit(s, gU, gDn, gDt) receives the adjoints of the
+// state of stencil point s (called once for each s = 0..3).
+// ---------------------------------------------------------------------------
+template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Emit>
+HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Consts<T>& k,
+                         const T* gfh, const T* ghh, const T* gxh, const Emit& emit) {
+  constexpr bool CHARW = (PHYS == PH_EULER);
+  const bool proj = CHARW && k.characteristic;
+  Eigen<T, M> eg;
+  T U1[M], U2[M];
+  {
+    T dn[M], dt[M];
+    ld(1, U1, dn, dt);
+    ld(2, U2, dn, dt);
+  }
+  if constexpr (CHARW) {
+    if (proj) eg.roe(U1, U2, k.gm1);
+  }
+  const T hh2 = T(0.5) * h;
+  auto split = [&](const int s, const T sign, T* x, T* y) {
+    T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
+    ld(s, U, Dn, Dt);
+    point_fluxes<T, PHYS, M, false>(U, Dn, Dt, k, an, F, A, B);
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      x[c] = T(0.5) * (F[c] + sign * alpha * U[c]);
+      y[c] = hh2 * (A[c] + sign * alpha * Dn[c]);
+    }
+  };
+  // ---- forward recomputation of the projected split data ----
+  T fP[3][M], HP[3][M], fM[3][M], HM[3][M];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    if (s <= 2) {
+      T x[M], y[M];
+      split(s, T(1), x, y);
+      if (proj) {
+        eg.project(x, fP[s]);
+        eg.project(y, HP[s]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          fP[s][c] = x[c];
+          HP[s][c] = y[c];
+        }
+      }
+    }
+    if (s >= 1) {
+      T x[M], y[M];
+      split(s, T(-1), x, y);
+      if (proj) {
+        eg.project(x, fM[s - 1]);
+        eg.project(y, HM[s - 1]);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          fM[s - 1][c] = x[c];
+          HM[s - 1][c] = y[c];
+        }
+      }
+    }
+  }
+  EigenAdj<T> ge;
+  // ---- reverse: back projection ----
+  T gfc[M];
+  if (proj) {
+    T fc[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c)
+      fc[c] = hw_plus(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw) +
+              hw_plus(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw);
+    back_vjp(eg, fc, gfh, gfc, ge);
+  } else {
+#pragma unroll
+    for (int c = 0; c < M; ++c) gfc[c] = gfh[c];
+  }
+  // ---- reverse: nonlinear reconstructions ----
+  T gfP[3][M], gHP[3][M], gfM[3][M], gHM[3][M];
+#pragma unroll
+  for (int s = 0; s < 3; ++s)
+#pragma unroll
+    for (int c = 0; c < M; ++c) gfP[s][c] = gHP[s][c] = gfM[s][c] = gHM[s][c] = T(0);
+#pragma unroll
+  for (int c = 0; c < M; ++c) {
+    hw_plus_vjp(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw, gfc[c],
+                gfP[0][c], gfP[1][c], gfP[2][c], gHP[0][c], gHP[1][c], gHP[2][c]);
+    T n2 = 0, n1 = 0, n0 = 0;  // adjoints of the negated derivative data
+    hw_plus_vjp(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw, gfc[c],
+                gfM[2][c], gfM[1][c], gfM[0][c], n2, n1, n0);
+    gHM[2][c] -= n2;
+    gHM[1][c] -= n1;
+    gHM[0][c] -= n0;
+  }
+  // ---- reverse: split, projection, linear fluxes and point physics ----
+  constexpr T cF[4] = {T(1), T(-15), T(15), T(-1)};
+  constexpr T cU[4] = {T(1), T(-1), T(-1), T(1)};
+  constexpr T cA[4] = {T(1), T(-7), T(-7), T(1)};
+  constexpr T cD[4] = {T(1), T(3), T(-3), T(-1)};
+  constexpr T cX[4] = {T(-1), T(7), T(7), T(-1)};
+  const T i8 = T(0.125) * ih;
+  T gU1[M], gU2[M], gDn1[M], gDn2[M], gDt1[M], gDt2[M];
+  const int order[4] = {0, 3, 1, 2};
+#pragma unroll
+  for (int oi = 0; oi < 4; ++oi) {
+    const int s = order[oi];
+    T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
+    ld(s, U, Dn, Dt);
+    point_fluxes<T, PHYS, M, false>(U, Dn, Dt, k, an, F, A, B);
+    T gF[M], gA[M], gB[M], gUd[M], gDnd[M], gDtd[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      gF[c] = cF[s] * i8 * ghh[c];
+      gUd[c] = alpha * cU[s] * i8 * ghh[c];
+      gA[c] = cA[s] * T(1.0 / 24.0) * ghh[c];
+      gDnd[c] = alpha * cD[s] * T(1.0 / 24.0) * ghh[c];
+      gB[c] = MIXED ? cX[s] * T(1.0 / 12.0) * gxh[c] : T(0);
+      gDtd[c] = T(0);
+    }
+    if (s <= 2) {
+      T x[M], y[M], gx[M], gy[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        x[c] = T(0.5) * (F[c] + alpha * U[c]);
+        y[c] = hh2 * (A[c] + alpha * Dn[c]);
+      }
+      if (proj) {
+        project_vjp(eg, x, gfP[s], gx, ge);
+        project_vjp(eg, y, gHP[s], gy, ge);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          gx[c] = gfP[s][c];
+          gy[c] = gHP[s][c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        gF[c] += T(0.5) * gx[c];
+        gUd[c] += T(0.5) * alpha * gx[c];
+        gA[c] += hh2 * gy[c];
+        gDnd[c] += hh2 * alpha * gy[c];
+      }
+    }
+    if (s >= 1) {
+      T x[M], y[M], gx[M], gy[M];
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        x[c] = T(0.5) * (F[c] - alpha * U[c]);
+        y[c] = hh2 * (A[c] - alpha * Dn[c]);
+      }
+      if (proj) {
+        project_vjp(eg, x, gfM[s - 1], gx, ge);
+        project_vjp(eg, y, gHM[s - 1], gy, ge);
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          gx[c] = gfM[s - 1][c];
+          gy[c] = gHM[s - 1][c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        gF[c] += T(0.5) * gx[c];
+        gUd[c] -= T(0.5) * alpha * gx[c];
+        gA[c] += hh2 * gy[c];
+        gDnd[c] -= hh2 * alpha * gy[c];
+      }
+    }
+    point_fluxes_vjp<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, gF, gA, gB, gUd, gDnd, gDtd);
+    if (s == 0 || s == 3) {
+      emit(s, gUd, gDnd, gDtd);
+    } else {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        if (s == 1) {
+          gU1[c] = gUd[c];
+          gDn1[c] = gDnd[c];
+          gDt1[c] = gDtd[c];
+        } else {
+          gU2[c] = gUd[c];
+          gDn2[c] = gDnd[c];
+          gDt2[c] = gDtd[c];
+        }
+      }
+    }
+  }
+  if constexpr (CHARW) {
+    if (proj) roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
+  }
+  emit(1, gU1, gDn1, gDt1);
+  emit(2, gU2, gDn2, gDt2);
+}
+
+}  // namespace hweno

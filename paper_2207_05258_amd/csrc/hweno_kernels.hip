@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "../../include/hweno.h"
+#include "hweno_adjoint.h"
 #include "hweno_math.h"
 
 namespace hweno {
@@ -491,6 +492,251 @@ __global__ void k_finish_batched(const hweno_instance* __restrict__ inst, int n_
   }
 }
 
+// ---------------------------------------------------------------------------
+// Discrete adjoint.  The forward operator reads ghost cells through the
+// boundary index maps; its adjoint scatters into a ghost-padded buffer E
+// ([nf][ny+4][nx+4] in 2D, [nf][1][nx+4] in 1D) and k_fold then adds every
+// ghost entry onto the cell it was copied from.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct AdjArgs {
+  const T* S;           // state the operator is linearised at
+  const T* XL;          // adjoint of L is cr * XL (nf fields)
+  const T* XM;          // adjoint of the limited derivatives is cl * XM (m*dim fields) or NULL
+  T* E;                 // ghost-padded output
+  const double* alpha;  // speeds used by the forward evaluation
+  const double* dtp;    // if non-NULL, cr is multiplied by *dtp
+  double cr, cl;
+  int nx, ny, bc_x, bc_y;
+  long long fs;
+  int nxe, nye;
+  double dx, dy;
+};
+
+template <typename T, int PHYS, int DIM, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adjoint(AdjArgs<T> a, Consts<T> k) {
+  constexpr int M = Comps<PHYS, DIM>::M;
+  constexpr int NF = Comps<PHYS, DIM>::NF;
+  constexpr int GX = 2, GY = (DIM == 2) ? 2 : 0;  // ghost width of E
+  constexpr int HX = 3, HY = (DIM == 2) ? 3 : 0;  // state halo around the tile
+  constexpr int W = TX + 2 * HX, HR = TY + 2 * HY;
+  __shared__ T sm[NF * HR * W];
+  __shared__ T acc[NF * TY * TX];
+  const int nx = a.nx, ny = a.ny;
+  const long long fs = a.fs;
+  const int ntx = (a.nxe + TX - 1) / TX;
+  const int t = xcd_band(blockIdx.x, gridDim.x);
+  const int bty = t / ntx, btx = t - bty * ntx;
+  const int rx0 = btx * TX - GX, ry0 = bty * TY - GY;  // real coordinates of tile cell (0, 0)
+  const int tid = threadIdx.x;
+  const T cr = T(a.cr * (a.dtp ? *a.dtp : 1.0));
+  const T cl = T(a.cl);
+  for (int q = tid; q < W * HR; q += NT) {
+    const int lr = q / W, lc = q - lr * W;
+    const int gi = map_index(rx0 - HX + lc, nx, a.bc_x);
+    const int gj = (DIM == 2) ? map_index(ry0 - HY + lr, ny, a.bc_y) : 0;
+    const long long g = (long long)gj * nx + gi;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sm[(f * HR + lr) * W + lc] = a.S[f * fs + g];
+  }
+  for (int q = tid; q < NF * TY * TX; q += NT) acc[q] = T(0);
+  __syncthreads();
+
+  auto xl = [&](int f, int i, int j) -> T {
+    return (i >= 0 && i < nx && j >= 0 && j < ny) ? a.XL[f * fs + (long long)j * nx + i] : T(0);
+  };
+  auto add = [&](int f, int i, int j, T v) {
+    const int lx = i - rx0, ly = j - ry0;
+    if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && v != T(0)) atomicAdd(&acc[(f * TY + ly) * TX + lx], v);
+  };
+  const T idx = T(1.0 / a.dx), hx = T(a.dx);
+
+  // ---- x-interfaces I (between cells I and I+1) that touch the tile ----
+  for (int q = tid; q < TY * (TX + 3); q += NT) {
+    const int r = q / (TX + 3), ii = q - r * (TX + 3);
+    const int j = ry0 + r, I = rx0 - 2 + ii;
+    if (j < 0 || j >= ny || I < -1 || I > nx - 1) continue;
+    T gf[M], gh[M], gx[M];
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      gf[c] = cr * (xl(c, I + 1, j) - xl(c, I, j)) * idx;
+      gh[c] = cr * (xl(M + c, I + 1, j) - xl(M + c, I, j)) * idx;
+      gx[c] = (DIM == 2) ? cr * (xl(2 * M + c, I + 1, j) - xl(2 * M + c, I, j)) * idx : T(0);
+      any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
+    }
+    if (!any) continue;
+    const T* row = sm + (j - (ry0 - HY)) * W + (I - 1 - (rx0 - HX));
+    auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        U[c] = row[(c * HR) * W + s];
+        Dn[c] = row[((M + c) * HR) * W + s];
+        Dt[c] = (DIM == 2) ? row[((2 * M + c) * HR) * W + s] : T(0);
+      }
+    };
+    auto emit = [&](int s, const T* gU, const T* gDn, const T* gDt) {
+      const int P = I - 1 + s;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        add(c, P, j, gU[c]);
+        add(M + c, P, j, gDn[c]);
+        if constexpr (DIM == 2) add(2 * M + c, P, j, gDt[c]);
+      }
+    };
+    interface_vjp<T, PHYS, M, DIM == 2>(ld, T(a.alpha[0]), hx, idx, k.ax, k, gf, gh, gx, emit);
+  }
+
+  if constexpr (DIM == 2) {
+    const T idy = T(1.0 / a.dy), hy = T(a.dy);
+    // ---- y-interfaces J (between rows J and J+1) that touch the tile ----
+    for (int q = tid; q < TX * (TY + 3); q += NT) {
+      const int jj = q / TX, cc = q - jj * TX;
+      const int i = rx0 + cc, J = ry0 - 2 + jj;
+      if (i < 0 || i >= nx || J < -1 || J > ny - 1) continue;
+      T gf[M], gh[M], gx[M];
+      bool any = false;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        gf[c] = cr * (xl(cs, i, J + 1) - xl(cs, i, J)) * idy;
+        gh[c] = cr * (xl(2 * M + cs, i, J + 1) - xl(2 * M + cs, i, J)) * idy;  // theta-hat
+        gx[c] = cr * (xl(M + cs, i, J + 1) - xl(M + cs, i, J)) * idy;          // xi-hat
+        any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
+      }
+      if (!any) continue;
+      const T* col = sm + (J - 1 - (ry0 - HY)) * W + (i - (rx0 - HX));
+      auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          U[c] = col[(cs * HR + s) * W];
+          Dn[c] = col[((2 * M + cs) * HR + s) * W];
+          Dt[c] = col[((M + cs) * HR + s) * W];
+        }
+      };
+      auto emit = [&](int s, const T* gU, const T* gDn, const T* gDt) {
+        const int P = J - 1 + s;
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          add(cs, i, P, gU[c]);
+          add(2 * M + cs, i, P, gDn[c]);
+          add(M + cs, i, P, gDt[c]);
+        }
+      };
+      interface_vjp<T, PHYS, M, true>(ld, T(a.alpha[1]), hy, idy, k.ay, k, gf, gh, gx, emit);
+    }
+  }
+
+  // ---- limiter: U_x along x (and U_y along y) of cells near the tile ----
+  if (a.XM) {
+    for (int q = tid; q < TY * (TX + 2); q += NT) {
+      const int r = q / (TX + 2), ii = q - r * (TX + 2);
+      const int j = ry0 + r, C = rx0 - 1 + ii;
+      if (j < 0 || j >= ny || C < 0 || C >= nx) continue;
+      const T* p = sm + (j - (ry0 - HY)) * W + (C - (rx0 - HX));
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const T mu = cl * a.XM[c * fs + (long long)j * nx + C];
+        if (mu == T(0)) continue;
+        const T* u = p + (c * HR) * W;
+        const T* v = p + ((M + c) * HR) * W;
+        T gum = 0, gu0 = 0, gup = 0, gvm = 0, gvp = 0;
+        limit1_vjp(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw, mu, gum, gu0, gup, gvm, gvp);
+        add(c, C - 1, j, gum);
+        add(c, C, j, gu0);
+        add(c, C + 1, j, gup);
+        add(M + c, C - 1, j, gvm);
+        add(M + c, C + 1, j, gvp);
+      }
+    }
+    if constexpr (DIM == 2) {
+      const T idy = T(1.0 / a.dy), hy = T(a.dy);
+      for (int q = tid; q < TX * (TY + 2); q += NT) {
+        const int jj = q / TX, cc = q - jj * TX;
+        const int i = rx0 + cc, C = ry0 - 1 + jj;
+        if (i < 0 || i >= nx || C < 0 || C >= ny) continue;
+        const T* p = sm + (C - (ry0 - HY)) * W + (i - (rx0 - HX));
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const T mu = cl * a.XM[(M + c) * fs + (long long)C * nx + i];
+          if (mu == T(0)) continue;
+          const T* u = p + (c * HR) * W;
+          const T* w = p + ((2 * M + c) * HR) * W;
+          T gum = 0, gu0 = 0, gup = 0, gwm = 0, gwp = 0;
+          limit1_vjp(u[-W], u[0], u[W], w[-W], w[W], hy, idy, k.lw, mu, gum, gu0, gup, gwm, gwp);
+          add(c, i, C - 1, gum);
+          add(c, i, C, gu0);
+          add(c, i, C + 1, gup);
+          add(2 * M + c, i, C - 1, gwm);
+          add(2 * M + c, i, C + 1, gwp);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int q = tid; q < TX * TY; q += NT) {
+    const int lx = q % TX, ly = q / TX;
+    const int ex = btx * TX + lx, ey = bty * TY + ly;
+    if (ex < a.nxe && ey < a.nye) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f)
+        a.E[((long long)f * a.nye + ey) * a.nxe + ex] = acc[(f * TY + ly) * TX + lx];
+    }
+  }
+}
+
+// Fold the ghost-padded adjoint onto the grid and apply the pointwise
+// Runge-Kutta transposes:
+//   out  = [out] + fold(E) + cu * XU   (XU on U only, or on all fields when
+//                                       identity_all; nothing when XU is NULL)
+//   L0   = ca * A + cb * B + out       (when L0 is non-NULL)
+template <typename T>
+struct FoldArgs {
+  const T* E;
+  int nxe, nye;
+  int nx, ny, bc_x, bc_y, dim, nf, m;
+  long long fs;
+  T* out;
+  int accumulate;
+  const T* XU;
+  double cu;
+  int identity_all;
+  T* L0;
+  const T* A;
+  const T* B;
+  double ca, cb;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold(FoldArgs<T> a) {
+  const long long n = a.fs;
+  const long long q = blockIdx.x * 256ll + threadIdx.x;
+  if (q >= n) return;
+  const int j = (int)(q / a.nx), i = (int)(q - (long long)j * a.nx);
+  const int GX = 2, GY = (a.dim == 2) ? 2 : 0;
+  const int gx[4] = {-2, -1, a.nx, a.nx + 1};
+  const int gy[4] = {-2, -1, a.ny, a.ny + 1};
+  for (int f = 0; f < a.nf; ++f) {
+    const T* Ef = a.E + (long long)f * a.nye * a.nxe;
+    T v = Ef[(long long)(j + GY) * a.nxe + (i + GX)];
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      if (map_index(gx[g], a.nx, a.bc_x) == i) v += Ef[(long long)(j + GY) * a.nxe + (gx[g] + GX)];
+    if (a.dim == 2) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+        if (map_index(gy[g], a.ny, a.bc_y) == j) v += Ef[(long long)(gy[g] + GY) * a.nxe + (i + GX)];
+    }
+    const long long o = (long long)f * n + q;
+    T r = a.accumulate ? a.out[o] + v : v;
+    if (a.XU && (f < a.m || a.identity_all)) r += T(a.cu) * a.XU[o];
+    a.out[o] = r;
+    if (a.L0) a.L0[o] = T(a.ca) * a.A[o] + T(a.cb) * a.B[o] + r;
+  }
+}
+
 // global speeds of a state: alpha[0..1] = max over cells (target pre-zeroed)
 template <typename T, int PHYS, int DIM>
 __global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, long long n,
@@ -872,6 +1118,136 @@ struct RunStep {
   }
 };
 
+template <int DIM>
+struct AdjTile {
+  static constexpr int TX = (DIM == 2) ? 16 : 256;
+  static constexpr int TY = (DIM == 2) ? 16 : 1;
+  static constexpr int NT = 256;
+};
+
+struct AdjLayout {
+  size_t e, y2, y1, l0, total;
+  int nxe, nye;
+};
+
+AdjLayout adj_layout(const hweno_problem* p) {
+  AdjLayout L;
+  L.nxe = p->nx + 4;
+  L.nye = p->dim == 2 ? p->ny + 4 : 1;
+  const size_t es = elem_size(p);
+  const size_t st = (size_t)cells_of(p) * es * n_fields(p);
+  L.e = 0;
+  L.y2 = align256((size_t)L.nxe * L.nye * es * n_fields(p));
+  L.y1 = L.y2 + align256(st);
+  L.l0 = L.y1 + align256(st);
+  L.total = L.l0 + align256(st);
+  return L;
+}
+
+// one adjoint evaluation into E followed by one fold
+struct RunAdj {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* S, const void* XL, double cr,
+                          const double* dtp, const void* XM, double cl, const double* alpha,
+                          void* ws, FoldArgs<T> fo, hipStream_t s) {
+    const AdjLayout L = adj_layout(p);
+    AdjArgs<T> a;
+    a.S = (const T*)S;
+    a.XL = (const T*)XL;
+    a.XM = (const T*)XM;
+    a.E = (T*)((char*)ws + L.e);
+    a.alpha = alpha;
+    a.dtp = dtp;
+    a.cr = cr;
+    a.cl = cl;
+    a.nx = p->nx;
+    a.ny = DIM == 2 ? p->ny : 1;
+    a.bc_x = p->bc_x;
+    a.bc_y = p->bc_y;
+    a.fs = cells_of(p);
+    a.nxe = L.nxe;
+    a.nye = L.nye;
+    a.dx = p->dx;
+    a.dy = DIM == 2 ? p->dy : 1.0;
+    constexpr int TX = AdjTile<DIM>::TX, TY = AdjTile<DIM>::TY, NT = AdjTile<DIM>::NT;
+    const unsigned tiles = (unsigned)(((L.nxe + TX - 1) / TX) * ((L.nye + TY - 1) / TY));
+    timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+    fo.E = a.E;
+    fo.nxe = L.nxe;
+    fo.nye = L.nye;
+    fo.nx = a.nx;
+    fo.ny = a.ny;
+    fo.bc_x = p->bc_x;
+    fo.bc_y = p->bc_y;
+    fo.dim = DIM;
+    fo.nf = Comps<PHYS, DIM>::NF;
+    fo.m = Comps<PHYS, DIM>::M;
+    fo.fs = a.fs;
+    k_fold<T><<<(unsigned)((a.fs + 255) / 256), 256, 0, s>>>(fo);
+    return launch_check("adjoint");
+  }
+};
+
+template <typename T>
+FoldArgs<T> fold_args(void* out, int accumulate, const void* XU, double cu, int identity_all) {
+  FoldArgs<T> f;
+  std::memset(&f, 0, sizeof f);
+  f.out = (T*)out;
+  f.accumulate = accumulate;
+  f.XU = (const T*)XU;
+  f.cu = cu;
+  f.identity_all = identity_all;
+  return f;
+}
+
+struct RunRhsAdj {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* state, const double* alpha,
+                          const void* lam_rhs, const void* lam_lim, void* lam_state, void* ws,
+                          hipStream_t s) {
+    return RunAdj::run<T, PHYS, DIM>(p, state, lam_rhs, 1.0, nullptr, lam_lim, 1.0, alpha, ws,
+                                     fold_args<T>(lam_state, 1, nullptr, 0.0, 0), s);
+  }
+};
+
+struct RunStepAdj {
+  template <typename T, int PHYS, int DIM>
+  static hweno_status run(const hweno_problem* p, const void* state0, const void* step_ws,
+                          const double* tape, void* lam, void* ws, hipStream_t s) {
+    const WsLayout F = ws_layout(p);
+    const AdjLayout L = adj_layout(p);
+    const char* sw = (const char*)step_ws;
+    const void* S1 = sw + F.s1;
+    const void* S2 = sw + F.s2;
+    char* w = (char*)ws;
+    T* Y2 = (T*)(w + L.y2);
+    T* Y1 = (T*)(w + L.y1);
+    T* L0 = (T*)(w + L.l0);
+    const bool lim = p->limiter_on != 0;
+    const long long mN = (long long)n_comp(p) * cells_of(p);
+    const int ida = lim ? 0 : 1;
+    hweno_status st;
+    // stage 3: S^{n+1} = 1/3 S^0 + 2/3 (S^2 + dt L(S2)),  S^ = (U, Lim(S))
+    st = RunAdj::run<T, PHYS, DIM>(p, S2, lam, 2.0 / 3.0, tape + 6,
+                                   lim ? (const T*)lam + mN : nullptr, 2.0 / 3.0, tape + 4, ws,
+                                   fold_args<T>(Y2, 0, lam, 2.0 / 3.0, ida), s);
+    if (st) return st;
+    // stage 2: S2 = 3/4 S^0 + 1/4 (S^1 + dt L(S1));  L0 = lam/3 + 3/4 Y2 + Y1
+    FoldArgs<T> f2 = fold_args<T>(Y1, 0, Y2, 0.25, ida);
+    f2.L0 = L0;
+    f2.A = (const T*)lam;
+    f2.B = Y2;
+    f2.ca = 1.0 / 3.0;
+    f2.cb = 0.75;
+    st = RunAdj::run<T, PHYS, DIM>(p, S1, Y2, 0.25, tape + 6, lim ? Y2 + mN : nullptr, 0.25,
+                                   tape + 2, ws, f2, s);
+    if (st) return st;
+    // stage 1: S1 = S^0 + dt L(S0); the base S^0 collects L0
+    return RunAdj::run<T, PHYS, DIM>(p, state0, Y1, 1.0, tape + 6, lim ? L0 + mN : nullptr, 1.0,
+                                     tape + 0, ws, fold_args<T>(lam, 0, L0, 1.0, ida), s);
+  }
+};
+
 int device_cus() {
   static int cus = 0;
   if (cus == 0) {
@@ -981,13 +1357,46 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws, si
   return ok();
 }
 
+size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob) {
+  if (validate(prob) != HWENO_OK) return 0;
+  return adj_layout(prob).total;
+}
+
 hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, const double* alpha,
-                               const void* lam_rhs, const void* lam_lim, void* lam_state,
-                               void* stream) {
+                               const void* lam_rhs, const void* lam_lim, void* lam_state, void* ws,
+                               size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
-  (void)state; (void)alpha; (void)lam_rhs; (void)lam_lim; (void)lam_state; (void)stream;
-  return fail(HWENO_ERR_UNSUPPORTED, "adjoint not built yet");
+  if (empty(prob)) return ok();
+  if (!state || !alpha || !lam_rhs || !lam_state || !ws)
+    return fail(HWENO_ERR_INVALID_ARG, "state, alpha, lam_rhs, lam_state and ws must be non-NULL");
+  if (ws_bytes < adj_layout(prob).total)
+    return fail(HWENO_ERR_WORKSPACE, "adjoint workspace too small: %zu < %zu bytes", ws_bytes,
+                adj_layout(prob).total);
+  if (((uintptr_t)ws & 255u) != 0) return fail(HWENO_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  st = dispatch<RunRhsAdj>(prob, state, alpha, lam_rhs, lam_lim, lam_state, ws, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state0,
+                                    const void* step_ws, size_t step_ws_bytes, const double* tape,
+                                    void* lam, void* ws, size_t ws_bytes, void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state0 || !step_ws || !tape || !lam || !ws)
+    return fail(HWENO_ERR_INVALID_ARG, "state0, step_ws, tape, lam and ws must be non-NULL");
+  if (step_ws_bytes < ws_layout(prob).total)
+    return fail(HWENO_ERR_WORKSPACE, "step workspace too small");
+  if (ws_bytes < adj_layout(prob).total)
+    return fail(HWENO_ERR_WORKSPACE, "adjoint workspace too small: %zu < %zu bytes", ws_bytes,
+                adj_layout(prob).total);
+  if (((uintptr_t)ws & 255u) != 0 || ((uintptr_t)step_ws & 255u) != 0)
+    return fail(HWENO_ERR_WORKSPACE, "workspaces must be 256-byte aligned");
+  st = dispatch<RunStepAdj>(prob, state0, step_ws, tape, lam, ws, (hipStream_t)stream);
+  if (st) return st;
+  return ok();
 }
 
 hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* inst,

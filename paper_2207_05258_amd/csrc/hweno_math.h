@@ -16,6 +16,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// math below is host+device so that it can be unit-checked on the CPU
+#define HW_HD __host__ __device__ __forceinline__
+
 namespace hweno {
 
 enum { PH_LINADV = 0, PH_BURGERS = 1, PH_EULER = 2 };
@@ -44,13 +47,17 @@ struct Consts {
 };
 
 template <typename T>
-__device__ __forceinline__ T fast_rcp(T x);
+HW_HD T fast_rcp(T x);
 template <>
-__device__ __forceinline__ float fast_rcp<float>(float x) {
-  return __builtin_amdgcn_rcpf(x);
+HW_HD float fast_rcp<float>(float x) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  return __builtin_amdgcn_rcpf(x);  // v_rcp_f32
+#else
+  return 1.0f / x;  // host build of the math (CPU unit checks)
+#endif
 }
 template <>
-__device__ __forceinline__ double fast_rcp<double>(double x) {
+HW_HD double fast_rcp<double>(double x) {
   return 1.0 / x;
 }
 
@@ -63,7 +70,7 @@ __device__ __forceinline__ double fast_rcp<double>(double x) {
 //   (e0 P0 + g1 P1 (e1-e0) + g2 P2 (e2-e0)) / (g0 e0 + g1 e1 + g2 e2).
 // ---------------------------------------------------------------------------
 template <typename T>
-__device__ __forceinline__ T combine(T P0, T P1, T P2, T b0, T b1, T b2,
+HW_HD T combine(T P0, T P1, T P2, T b0, T b1, T b2,
                                      const Weights<T>& w) {
   T tau = fabs(b0 - b1) + fabs(b0 - b2);
   tau = T(0.25) * tau * tau;
@@ -92,7 +99,7 @@ __device__ __forceinline__ T combine(T P0, T P1, T P2, T b0, T b1, T b2,
 // the quintic p0 and quadratics p1, p2, their smoothness indicators (beta2
 // from its integral definition, eq. GHYZ) and the combination above.
 template <typename T>
-__device__ __forceinline__ T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
+HW_HD T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
                                      const Weights<T>& w) {
   const T s = fm + fp, dl = fm - fp, lap = s - T(2) * f0;
   const T Hs = Hm + Hp, Hd = Hm - Hp;
@@ -121,7 +128,7 @@ __device__ __forceinline__ T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
 // v_{i-1}, v_{i+1}: quartic q0 and linear q1, q2, their derivatives at x_i
 // and smoothness indicators.  h = dx, ih = 1/dx.
 template <typename T>
-__device__ __forceinline__ T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
+HW_HD T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
                                     const Weights<T>& w) {
   const T Vs = h * (vm + vp), Vd = h * (vm - vp);
   const T lap = um - T(2) * u0 + up;
@@ -146,7 +153,7 @@ __device__ __forceinline__ T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
 // flux F_n(U) and the chain-rule products A_n(U) Dn and A_n(U) Dt
 // (h, xi, eta, theta of eq. EQ3), for one stencil point.
 template <typename T, int PHYS, int M, bool MIXED>
-__device__ __forceinline__ void point_fluxes(const T* U, const T* Dn, const T* Dt,
+HW_HD void point_fluxes(const T* U, const T* Dn, const T* Dt,
                                              const Consts<T>& k, T an, T* F,
                                              T* A, T* B) {
   if constexpr (PHYS == PH_EULER) {
@@ -191,7 +198,7 @@ template <typename T, int M>
 struct Eigen {
   T un, ut, H, c, ic, b1, b2, hq2;
 
-  __device__ __forceinline__ void roe(const T* UL, const T* UR, T gm1) {
+  HW_HD void roe(const T* UL, const T* UR, T gm1) {
     const T irL = T(1) / UL[0], irR = T(1) / UR[0];
     const T sL = sqrt(UL[0]), sR = sqrt(UR[0]);
     const T uL = UL[1] * irL, uR = UR[1] * irR;
@@ -213,7 +220,7 @@ struct Eigen {
   }
 
   // w = L x
-  __device__ __forceinline__ void project(const T* x, T* w) const {
+  HW_HD void project(const T* x, T* w) const {
     if constexpr (M == 4) {
       const T phi = b2 * x[0] - b1 * (un * x[1] + ut * x[2] - x[3]);
       const T psi = (un * x[0] - x[1]) * ic;
@@ -231,7 +238,7 @@ struct Eigen {
   }
 
   // y = R w
-  __device__ __forceinline__ void back(const T* w, T* y) const {
+  HW_HD void back(const T* w, T* y) const {
     if constexpr (M == 4) {
       const T s = w[0] + w[1] + w[3], dif = w[3] - w[0];
       y[0] = s;
@@ -257,7 +264,7 @@ struct Eigen {
 //   alpha: global LF speed of this direction; h: cell size; ih = 1/h.
 // ---------------------------------------------------------------------------
 template <typename T, int PHYS, int M, bool MIXED, typename Loader>
-__device__ __forceinline__ void interface_fluxes(const Loader& ld, T alpha, T h,
+HW_HD void interface_fluxes(const Loader& ld, T alpha, T h,
                                                  T ih, T an, const Consts<T>& k,
                                                  T* fh, T* hh, T* xh) {
   constexpr bool CHARW = (PHYS == PH_EULER);
@@ -370,7 +377,7 @@ __device__ __forceinline__ void interface_fluxes(const Loader& ld, T alpha, T h,
 // wave speeds |u_n| + c (Euler), |u| (Burgers), |a| (linear advection) of
 // one point in each direction, plus admissibility flags.
 template <typename T, int PHYS, int DIM>
-__device__ __forceinline__ void point_speeds(const T* U, const Consts<T>& k,
+HW_HD void point_speeds(const T* U, const Consts<T>& k,
                                              T& sx, T& sy, uint32_t& flags) {
   if constexpr (PHYS == PH_EULER) {
     constexpr int M = Comps<PHYS, DIM>::M;

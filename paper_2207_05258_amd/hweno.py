@@ -81,7 +81,10 @@ def lib() -> ctypes.CDLL:
             "hweno_limit": ([P, vp, vp, vp], ctypes.c_int),
             "hweno_rk3_step": ([P, vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
                                 vp, vp, vp], ctypes.c_int),
-            "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp], ctypes.c_int),
+            "hweno_adjoint_workspace_bytes": ([P], ctypes.c_size_t),
+            "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
+            "hweno_rk3_step_adjoint": ([P, vp, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t,
+                                        vp], ctypes.c_int),
             "hweno_batch_prepare": ([P, ctypes.POINTER(_CInstance), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "hweno_rk3_step_batched": ([P, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -174,6 +177,15 @@ def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
     return None if t is None else t.data_ptr()
 
 
+def _speeds(alpha_, device) -> torch.Tensor:
+    """Wave speeds as a float64 device tensor; float32 input is refused (it would round them)."""
+    if not torch.is_tensor(alpha_):
+        alpha_ = torch.tensor([float(x) for x in alpha_], dtype=torch.float64)
+    if alpha_.dtype != torch.float64:
+        raise ValueError("wave speeds must be float64 (got %s)" % alpha_.dtype)
+    return alpha_.to(device=device).contiguous()
+
+
 def _require(t: torch.Tensor, prob: Problem, nfields: int, what: str):
     if not t.is_cuda:
         raise ValueError(f"{what} must be a GPU tensor")
@@ -211,7 +223,7 @@ def rhs(S: torch.Tensor, prob: Problem, alpha_: Optional[torch.Tensor] = None,
         a = torch.zeros(2, dtype=torch.float64, device=S.device)
         compute = 1
     else:
-        a = alpha_.to(device=S.device, dtype=torch.float64).contiguous()
+        a = _speeds(alpha_, S.device)
         compute = 0
     _check(lib().hweno_rhs(ctypes.byref(prob.c()), _ptr(S), _ptr(L), _ptr(a), compute, _stream()),
            "hweno_rhs")
@@ -410,3 +422,104 @@ def autotune_batched(stepper: BatchedStepper, trials: int = 2):
     stepper.variant, stepper.blocks = best
     _AUTOTUNE_CACHE[key] = best
     return best, results
+
+
+def _aligned_buffer(nbytes: int, device) -> torch.Tensor:
+    raw = torch.zeros(max(nbytes, 256) + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw[off:off + max(nbytes, 256)]
+
+
+def adjoint_workspace(prob: Problem, device="cuda") -> torch.Tensor:
+    """Device workspace for hweno_rhs_adjoint / hweno_rk3_step_adjoint."""
+    n = int(lib().hweno_adjoint_workspace_bytes(ctypes.byref(prob.c())))
+    if n == 0:
+        validate(prob)
+    return _aligned_buffer(n, device)
+
+
+def rhs_adjoint(S: torch.Tensor, prob: Problem, alpha_: torch.Tensor, lam_rhs: torch.Tensor,
+                lam_lim: Optional[torch.Tensor] = None, lam_state: Optional[torch.Tensor] = None,
+                ws: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim with the speeds frozen."""
+    _require(S, prob, prob.nf, "state")
+    _require(lam_rhs, prob, prob.nf, "lam_rhs")
+    if lam_lim is not None:
+        _require(lam_lim, prob, prob.m * prob.dim, "lam_lim")
+    out = lam_state if lam_state is not None else torch.zeros_like(S)
+    _require(out, prob, prob.nf, "lam_state")
+    ws = ws if ws is not None else adjoint_workspace(prob, S.device)
+    a = _speeds(alpha_, S.device)
+    _check(lib().hweno_rhs_adjoint(ctypes.byref(prob.c()), _ptr(S), _ptr(a), _ptr(lam_rhs),
+                                   _ptr(lam_lim), _ptr(out), _ptr(ws), ws.numel(), _stream()),
+           "hweno_rhs_adjoint")
+    return out
+
+
+def step_adjoint(prob: Problem, state0: torch.Tensor, stepper: "Stepper", tape: torch.Tensor,
+                 lam: torch.Tensor, ws: torch.Tensor) -> torch.Tensor:
+    """lam <- (dS^{n+1}/dS^n)^T lam in place, for the step that ``stepper`` took from state0."""
+    _require(state0, prob, prob.nf, "state0")
+    _require(lam, prob, prob.nf, "lam")
+    _check(lib().hweno_rk3_step_adjoint(ctypes.byref(prob.c()), _ptr(state0), _ptr(stepper.ws),
+                                        stepper.nbytes, _ptr(tape), _ptr(lam), _ptr(ws),
+                                        ws.numel(), _stream()), "hweno_rk3_step_adjoint")
+    return lam
+
+
+def rollout_replay(S0: torch.Tensor, prob: Problem, tapes: torch.Tensor) -> torch.Tensor:
+    """Forward steps from S0 with the taped speeds and time steps (no autograd)."""
+    S = S0.detach().clone().contiguous()
+    st = Stepper(prob, device=S.device)
+    for n in range(tapes.shape[0]):
+        st.step(S, replay=tapes[n])
+    return S
+
+
+class Rollout(torch.autograd.Function):
+    """n_steps SSP-RK3 steps as a differentiable function of the initial state.
+
+    Forward: device-side CFL time steps (or ``dt``), one tape record per step
+    (speeds of the three stages and dt), a checkpoint every ``ckpt`` steps.
+    Backward: for each segment, newest first, recompute its steps from the
+    checkpoint with the tape replayed (keeping each step's stage states), then
+    apply the hand-written step adjoints in reverse.  Speeds and time steps
+    are held fixed (replay semantics), so the gradient is that of the taped
+    computation.  Returns the final state; ``Rollout.last_tapes`` keeps the
+    tape of the most recent forward call.
+    """
+
+    last_tapes = None
+
+    @staticmethod
+    def forward(ctx, S0, prob: Problem, n_steps: int, ckpt: int = 20, dt: Optional[float] = None):
+        S = S0.detach().clone().contiguous()
+        st = Stepper(prob, device=S.device)
+        tapes = torch.zeros(n_steps, CTRL_LEN, dtype=torch.float64, device=S.device)
+        ckpts = []
+        for n in range(n_steps):
+            if n % ckpt == 0:
+                ckpts.append(S.clone())
+            st.step(S, dt=dt, tape=tapes[n])
+        ctx.prob, ctx.n_steps, ctx.ckpt = prob, n_steps, ckpt
+        ctx.ckpts, ctx.tapes = ckpts, tapes
+        Rollout.last_tapes = tapes
+        return S
+
+    @staticmethod
+    def backward(ctx, g):
+        prob, n_steps, ckpt = ctx.prob, ctx.n_steps, ctx.ckpt
+        lam = g.detach().contiguous().clone()
+        ws = adjoint_workspace(prob, lam.device)
+        steppers = [Stepper(prob, device=lam.device) for _ in range(min(ckpt, n_steps))]
+        nseg = (n_steps + ckpt - 1) // ckpt
+        for seg in reversed(range(nseg)):
+            n0, n1 = seg * ckpt, min((seg + 1) * ckpt, n_steps)
+            S = ctx.ckpts[seg].clone()
+            inputs = []
+            for n in range(n0, n1):
+                inputs.append(S.clone())
+                steppers[n - n0].step(S, replay=ctx.tapes[n])
+            for n in reversed(range(n0, n1)):
+                step_adjoint(prob, inputs[n - n0], steppers[n - n0], ctx.tapes[n], lam, ws)
+        return lam, None, None, None, None
