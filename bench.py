@@ -198,6 +198,9 @@ def main():
     ap.add_argument("--cpu-n", type=int, default=1024)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
+    ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
+                    help="run only this part and print its JSON object (for profiling)")
+    ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
@@ -224,6 +227,13 @@ def main():
     import paper_2207_05258_amd as h
     h.lib()
 
+    if args.only == "batched":
+        print(json.dumps(run_batched(args.steps, max(args.warmup, 1))), flush=True)
+        return
+    if args.only == "adjoint":
+        print(json.dumps(run_adjoint(steps=args.adjoint_steps)), flush=True)
+        return
+
     main_run = run_gpu(args.n, args.dtype, args.steps, args.warmup)
     print(f"# {args.dtype} {args.n}^2: {main_run['rate']:.4e} cell-stage/s, stage kernel "
           f"{main_run['stage_ms_avg']:.3f} ms, {main_run['achieved_tflops']:.2f} TFLOP/s",
@@ -248,7 +258,7 @@ def main():
 
     adjoint = None
     if not args.no_adjoint:
-        adjoint = run_adjoint()
+        adjoint = run_adjoint(steps=args.adjoint_steps)
         print(f"# adjoint: backward/forward {adjoint['backward_over_forward']:.2f}",
               file=sys.stderr, flush=True)
 

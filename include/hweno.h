@@ -221,16 +221,22 @@ typedef struct {
 hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* inst,
                                  int32_t n_inst, int32_t* total_tiles);
 
+/* Host only: fills map[0..total_tiles) with the instance index of every
+ * global tile of `variant` (from the prepared tile_begin / n_tiles). */
+hweno_status hweno_batch_tile_map(const hweno_instance* inst, int32_t n_inst, int32_t variant,
+                                  int32_t* map, int32_t total_tiles);
+
 /* One SSP-RK3 step of every instance: wave speeds, three persistent stage
- * launches striding over the flattened tile list (instance found by binary
- * search on tile_begin), and the per-instance time update.  Enqueues six
- * kernels and nothing else, so it can be captured in a hipGraph.
- * inst_dev: device copy of the prepared descriptors; total_tiles: the
- * prepared count for `variant`; blocks: persistent grid size (0 = one
- * workgroup per tile up to 8 per compute unit). */
+ * launches striding over the flattened tile list, and the per-instance time
+ * update.  Enqueues six kernels and nothing else, so it can be captured in a
+ * hipGraph.  inst_dev: device copy of the prepared descriptors; tile_map_dev:
+ * device copy of the tile map of `variant`; total_tiles: the prepared count
+ * for `variant`; blocks: persistent grid size (0 = up to 8 workgroups per
+ * compute unit). */
 hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_instance* inst_dev,
-                                    int32_t n_inst, int32_t total_tiles, int32_t variant,
-                                    int32_t blocks, void* stream);
+                                    const int32_t* tile_map_dev, int32_t n_inst,
+                                    int32_t total_tiles, int32_t variant, int32_t blocks,
+                                    void* stream);
 
 /* Diagnostics: kernel timing of the Runge-Kutta stage kernels.
  * hweno_timing_begin(1) makes subsequent hweno_rk3_step calls (on this

@@ -17,16 +17,17 @@ HW_HD T sgn(T x) {
   return T((x > T(0)) - (x < T(0)));
 }
 
-// reverse of combine(): adjoints of P0, P1, P2 and b0, b1, b2 (overwritten)
+// reverse of combine(): adjoints of P0, P1, P2 and b0, b1, b2 (overwritten);
+// returns the forward value
 template <typename T>
-HW_HD void combine_vjp(T P0, T P1, T P2, T b0, T b1, T b2, const Weights<T>& w, T g,
+HW_HD T combine_vjp(T P0, T P1, T P2, T b0, T b1, T b2, const Weights<T>& w, T g,
                        T& gP0, T& gP1, T& gP2, T& gb0, T& gb1, T& gb2) {
   const T d01 = b0 - b1, d02 = b0 - b2;
   const T sa = fabs(d01) + fabs(d02);
   const T tau = T(0.25) * sa * sa;
-  const T i0 = T(1) / (b0 + w.eps), i1 = T(1) / (b1 + w.eps), i2 = T(1) / (b2 + w.eps);
+  const T i0 = fast_rcp(b0 + w.eps), i1 = fast_rcp(b1 + w.eps), i2 = fast_rcp(b2 + w.eps);
   const T e0 = T(1) + tau * i0, e1 = T(1) + tau * i1, e2 = T(1) + tau * i2;
-  const T iden = T(1) / (w.g0 * e0 + w.g1 * e1 + w.g2 * e2);
+  const T iden = fast_rcp(w.g0 * e0 + w.g1 * e1 + w.g2 * e2);
   const T r = (e0 * P0 + w.g1 * P1 * (e1 - e0) + w.g2 * P2 * (e2 - e0)) * iden;
   const T gi = g * iden;
   gP0 = gi * e0;
@@ -40,12 +41,13 @@ HW_HD void combine_vjp(T P0, T P1, T P2, T b0, T b1, T b2, const Weights<T>& w, 
   gb0 = -ge0 * tau * i0 * i0 + gs * (s01 + s02);
   gb1 = -ge1 * tau * i1 * i1 - gs * s01;
   gb2 = -ge2 * tau * i2 * i2 - gs * s02;
+  return r;
 }
 
-// reverse of hw_plus()
+// reverse of hw_plus(); returns the forward value hw_plus(...)
 template <typename T>
-HW_HD void hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, T g, T& gfm,
-                       T& gf0, T& gfp, T& gHm, T& gH0, T& gHp) {
+HW_HD T hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, T g, T& gfm,
+                    T& gf0, T& gfp, T& gHm, T& gH0, T& gHp) {
   const T s = fm + fp, dl = fm - fp, lap = s - T(2) * f0;
   const T Hs = Hm + Hp, Hd = Hm - Hp;
   const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
@@ -65,7 +67,7 @@ HW_HD void hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, 
   const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
   const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
   T gp0, gp1, gp2, gb0, gb1, gb2;
-  combine_vjp(p0, p1, p2, b0, b1, b2, w, g, gp0, gp1, gp2, gb0, gb1, gb2);
+  const T value = combine_vjp(p0, p1, p2, b0, b1, b2, w, g, gp0, gp1, gp2, gb0, gb1, gb2);
   // smoothness indicators
   const T gt0 = T(2) * t0 * gb0;
   const T gt1 = T(26.0 / 3.0) * t1 * gb0;
@@ -103,6 +105,7 @@ HW_HD void hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, 
   gHm += gHs + gHd;
   gHp += gHs - gHd;
   gH0 += gH0_;
+  return value;
 }
 
 // reverse of limit1()
@@ -275,17 +278,30 @@ HW_HD void project_vjp(const Eigen<T, M>& e, const T* x, const T* gw, T* gx, Eig
   }
 }
 
-// reverse of Eigen::back(): gw = R^T gy, plus eigen-system adjoints
+// reverse of Eigen::back(), in two parts: gw = R^T gy (needs no forward
+// value), and the eigen-system adjoints (need the back-projected w)
 template <typename T, int M>
-HW_HD void back_vjp(const Eigen<T, M>& e, const T* w, const T* gy, T* gw, EigenAdj<T>& ge) {
+HW_HD void back_T(const Eigen<T, M>& e, const T* gy, T* gw) {
   if constexpr (M == 4) {
-    const T s = w[0] + w[1] + w[3], dif = w[3] - w[0];
     const T gs = gy[0] + e.un * gy[1] + e.ut * gy[2];
     const T gdif = e.c * gy[1] + e.un * e.c * gy[3];
     gw[0] = gs - gdif + e.H * gy[3];
     gw[1] = gs + e.hq2 * gy[3];
     gw[2] = gy[2] + e.ut * gy[3];
     gw[3] = gs + gdif + e.H * gy[3];
+  } else {
+    const T gs = gy[0] + e.un * gy[1];
+    const T gdif = e.c * gy[1] + e.un * e.c * gy[2];
+    gw[0] = gs - gdif + e.H * gy[2];
+    gw[1] = gs + e.hq2 * gy[2];
+    gw[2] = gs + gdif + e.H * gy[2];
+  }
+}
+
+template <typename T, int M>
+HW_HD void back_eigen_adj(const Eigen<T, M>& e, const T* w, const T* gy, EigenAdj<T>& ge) {
+  if constexpr (M == 4) {
+    const T s = w[0] + w[1] + w[3], dif = w[3] - w[0];
     ge.un += s * gy[1] + e.c * dif * gy[3];
     ge.c += dif * gy[1] + e.un * dif * gy[3];
     ge.ut += s * gy[2] + w[2] * gy[3];
@@ -293,11 +309,6 @@ HW_HD void back_vjp(const Eigen<T, M>& e, const T* w, const T* gy, T* gw, EigenA
     ge.hq2 += w[1] * gy[3];
   } else {
     const T s = w[0] + w[1] + w[2], dif = w[2] - w[0];
-    const T gs = gy[0] + e.un * gy[1];
-    const T gdif = e.c * gy[1] + e.un * e.c * gy[2];
-    gw[0] = gs - gdif + e.H * gy[2];
-    gw[1] = gs + e.hq2 * gy[2];
-    gw[2] = gs + gdif + e.H * gy[2];
     ge.un += s * gy[1] + e.c * dif * gy[2];
     ge.c += dif * gy[1] + e.un * dif * gy[2];
     ge.H += (w[0] + w[2]) * gy[2];
@@ -361,8 +372,11 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
 
 // ---------------------------------------------------------------------------
 // VJP of interface_fluxes(): given the adjoints of f-hat, h-hat and the mixed
-// flux (normal frame), emit(s, gU, gDn, gDt) receives the adjoints of the
-// state of stencil point s (called once for each s = 0..3).
+// flux (normal frame), emit(s, gU, gDn, gDt) receives adjoint contributions
+// for the state of stencil point s (additively; a point may be emitted more
+// than once).  The "+" side (points 0..2) and the mirrored "-" side (points
+// 1..3) are differentiated in separate passes, so that only one side's
+// projected data and adjoints are live at a time.
 // ---------------------------------------------------------------------------
 template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Emit>
 HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Consts<T>& k,
@@ -370,18 +384,32 @@ HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Const
   constexpr bool CHARW = (PHYS == PH_EULER);
   const bool proj = CHARW && k.characteristic;
   Eigen<T, M> eg;
-  T U1[M], U2[M];
-  {
-    T dn[M], dt[M];
-    ld(1, U1, dn, dt);
-    ld(2, U2, dn, dt);
-  }
   if constexpr (CHARW) {
-    if (proj) eg.roe(U1, U2, k.gm1);
+    if (proj) {
+      T U1[M], U2[M], dn[M], dt[M];
+      ld(1, U1, dn, dt);
+      ld(2, U2, dn, dt);
+      eg.roe(U1, U2, k.gm1);
+    }
   }
   const T hh2 = T(0.5) * h;
-  auto split = [&](const int s, const T sign, T* x, T* y) {
-    T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
+  constexpr T cF[4] = {T(1), T(-15), T(15), T(-1)};
+  constexpr T cU[4] = {T(1), T(-1), T(-1), T(1)};
+  constexpr T cA[4] = {T(1), T(-7), T(-7), T(1)};
+  constexpr T cD[4] = {T(1), T(3), T(-3), T(-1)};
+  constexpr T cX[4] = {T(-1), T(7), T(7), T(-1)};
+  const T i8 = T(0.125) * ih;
+  EigenAdj<T> ge;
+  T gfc[M];  // adjoint of the characteristic flux f-hat^+ + f-hat^-
+  if (proj) {
+    back_T(eg, gfh, gfc);
+  } else {
+#pragma unroll
+    for (int c = 0; c < M; ++c) gfc[c] = gfh[c];
+  }
+  // split data x = (F +- alpha U)/2, y = dx/2 (A Dn +- alpha Dn) of point s
+  auto split = [&](int s, T sign, T* U, T* Dn, T* Dt, T* x, T* y) {
+    T F[M], A[M], B[M];
     ld(s, U, Dn, Dt);
     point_fluxes<T, PHYS, M, false>(U, Dn, Dt, k, an, F, A, B);
 #pragma unroll
@@ -390,168 +418,94 @@ HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Const
       y[c] = hh2 * (A[c] + sign * alpha * Dn[c]);
     }
   };
-  // ---- forward recomputation of the projected split data ----
-  T fP[3][M], HP[3][M], fM[3][M], HM[3][M];
+  auto side = [&](const bool plus) {
+    const int s0 = plus ? 0 : 1;
+    const T sign = plus ? T(1) : T(-1);
+    T fS[3][M], HS[3][M];
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    if (s <= 2) {
-      T x[M], y[M];
-      split(s, T(1), x, y);
+    for (int j = 0; j < 3; ++j) {
+      T U[M], Dn[M], Dt[M], x[M], y[M];
+      split(s0 + j, sign, U, Dn, Dt, x, y);
       if (proj) {
-        eg.project(x, fP[s]);
-        eg.project(y, HP[s]);
+        eg.project(x, fS[j]);
+        eg.project(y, HS[j]);
       } else {
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-          fP[s][c] = x[c];
-          HP[s][c] = y[c];
+          fS[j][c] = x[c];
+          HS[j][c] = y[c];
         }
       }
     }
-    if (s >= 1) {
-      T x[M], y[M];
-      split(s, T(-1), x, y);
-      if (proj) {
-        eg.project(x, fM[s - 1]);
-        eg.project(y, HM[s - 1]);
-      } else {
+    T gfS[3][M], gHS[3][M], fcs[M];
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-          fM[s - 1][c] = x[c];
-          HM[s - 1][c] = y[c];
-        }
-      }
-    }
-  }
-  EigenAdj<T> ge;
-  // ---- reverse: back projection ----
-  T gfc[M];
-  if (proj) {
-    T fc[M];
+    for (int j = 0; j < 3; ++j)
 #pragma unroll
-    for (int c = 0; c < M; ++c)
-      fc[c] = hw_plus(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw) +
-              hw_plus(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw);
-    back_vjp(eg, fc, gfh, gfc, ge);
-  } else {
-#pragma unroll
-    for (int c = 0; c < M; ++c) gfc[c] = gfh[c];
-  }
-  // ---- reverse: nonlinear reconstructions ----
-  T gfP[3][M], gHP[3][M], gfM[3][M], gHM[3][M];
-#pragma unroll
-  for (int s = 0; s < 3; ++s)
-#pragma unroll
-    for (int c = 0; c < M; ++c) gfP[s][c] = gHP[s][c] = gfM[s][c] = gHM[s][c] = T(0);
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    hw_plus_vjp(fP[0][c], fP[1][c], fP[2][c], HP[0][c], HP[1][c], HP[2][c], k.rw, gfc[c],
-                gfP[0][c], gfP[1][c], gfP[2][c], gHP[0][c], gHP[1][c], gHP[2][c]);
-    T n2 = 0, n1 = 0, n0 = 0;  // adjoints of the negated derivative data
-    hw_plus_vjp(fM[2][c], fM[1][c], fM[0][c], -HM[2][c], -HM[1][c], -HM[0][c], k.rw, gfc[c],
-                gfM[2][c], gfM[1][c], gfM[0][c], n2, n1, n0);
-    gHM[2][c] -= n2;
-    gHM[1][c] -= n1;
-    gHM[0][c] -= n0;
-  }
-  // ---- reverse: split, projection, linear fluxes and point physics ----
-  constexpr T cF[4] = {T(1), T(-15), T(15), T(-1)};
-  constexpr T cU[4] = {T(1), T(-1), T(-1), T(1)};
-  constexpr T cA[4] = {T(1), T(-7), T(-7), T(1)};
-  constexpr T cD[4] = {T(1), T(3), T(-3), T(-1)};
-  constexpr T cX[4] = {T(-1), T(7), T(7), T(-1)};
-  const T i8 = T(0.125) * ih;
-  T gU1[M], gU2[M], gDn1[M], gDn2[M], gDt1[M], gDt2[M];
-  const int order[4] = {0, 3, 1, 2};
-#pragma unroll
-  for (int oi = 0; oi < 4; ++oi) {
-    const int s = order[oi];
-    T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
-    ld(s, U, Dn, Dt);
-    point_fluxes<T, PHYS, M, false>(U, Dn, Dt, k, an, F, A, B);
-    T gF[M], gA[M], gB[M], gUd[M], gDnd[M], gDtd[M];
+      for (int c = 0; c < M; ++c) gfS[j][c] = gHS[j][c] = T(0);
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      gF[c] = cF[s] * i8 * ghh[c];
-      gUd[c] = alpha * cU[s] * i8 * ghh[c];
-      gA[c] = cA[s] * T(1.0 / 24.0) * ghh[c];
-      gDnd[c] = alpha * cD[s] * T(1.0 / 24.0) * ghh[c];
-      gB[c] = MIXED ? cX[s] * T(1.0 / 12.0) * gxh[c] : T(0);
-      gDtd[c] = T(0);
-    }
-    if (s <= 2) {
-      T x[M], y[M], gx[M], gy[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        x[c] = T(0.5) * (F[c] + alpha * U[c]);
-        y[c] = hh2 * (A[c] + alpha * Dn[c]);
+      if (plus) {
+        fcs[c] = hw_plus_vjp(fS[0][c], fS[1][c], fS[2][c], HS[0][c], HS[1][c], HS[2][c], k.rw,
+                             gfc[c], gfS[0][c], gfS[1][c], gfS[2][c], gHS[0][c], gHS[1][c],
+                             gHS[2][c]);
+      } else {
+        // mirrored: i+2, i+1, i with the derivative data negated
+        T n2 = 0, n1 = 0, n0 = 0;
+        fcs[c] = hw_plus_vjp(fS[2][c], fS[1][c], fS[0][c], -HS[2][c], -HS[1][c], -HS[0][c],
+                             k.rw, gfc[c], gfS[2][c], gfS[1][c], gfS[0][c], n2, n1, n0);
+        gHS[2][c] -= n2;
+        gHS[1][c] -= n1;
+        gHS[0][c] -= n0;
       }
+    }
+    // the back projection's eigen-system adjoint is linear in f-hat: add this side's part
+    if (proj) back_eigen_adj(eg, fcs, gfh, ge);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const int s = s0 + j;
+      T U[M], Dn[M], Dt[M], x[M], y[M], gx[M], gy[M];
+      split(s, sign, U, Dn, Dt, x, y);
       if (proj) {
-        project_vjp(eg, x, gfP[s], gx, ge);
-        project_vjp(eg, y, gHP[s], gy, ge);
+        project_vjp(eg, x, gfS[j], gx, ge);
+        project_vjp(eg, y, gHS[j], gy, ge);
       } else {
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-          gx[c] = gfP[s][c];
-          gy[c] = gHP[s][c];
+          gx[c] = gfS[j][c];
+          gy[c] = gHS[j][c];
         }
       }
+      // the linear fluxes of points 0..2 are differentiated in the "+" pass,
+      // point 3's in the "-" pass
+      const bool lin = plus || s == 3;
+      T gF[M], gA[M], gB[M], gUd[M], gDnd[M], gDtd[M];
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        gF[c] += T(0.5) * gx[c];
-        gUd[c] += T(0.5) * alpha * gx[c];
-        gA[c] += hh2 * gy[c];
-        gDnd[c] += hh2 * alpha * gy[c];
+        gF[c] = T(0.5) * gx[c] + (lin ? cF[s] * i8 * ghh[c] : T(0));
+        gUd[c] = sign * T(0.5) * alpha * gx[c] + (lin ? alpha * cU[s] * i8 * ghh[c] : T(0));
+        gA[c] = hh2 * gy[c] + (lin ? cA[s] * T(1.0 / 24.0) * ghh[c] : T(0));
+        gDnd[c] = sign * hh2 * alpha * gy[c] + (lin ? alpha * cD[s] * T(1.0 / 24.0) * ghh[c] : T(0));
+        gB[c] = (MIXED && lin) ? cX[s] * T(1.0 / 12.0) * gxh[c] : T(0);
+        gDtd[c] = T(0);
       }
-    }
-    if (s >= 1) {
-      T x[M], y[M], gx[M], gy[M];
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        x[c] = T(0.5) * (F[c] - alpha * U[c]);
-        y[c] = hh2 * (A[c] - alpha * Dn[c]);
-      }
-      if (proj) {
-        project_vjp(eg, x, gfM[s - 1], gx, ge);
-        project_vjp(eg, y, gHM[s - 1], gy, ge);
-      } else {
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          gx[c] = gfM[s - 1][c];
-          gy[c] = gHM[s - 1][c];
-        }
-      }
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        gF[c] += T(0.5) * gx[c];
-        gUd[c] -= T(0.5) * alpha * gx[c];
-        gA[c] += hh2 * gy[c];
-        gDnd[c] -= hh2 * alpha * gy[c];
-      }
-    }
-    point_fluxes_vjp<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, gF, gA, gB, gUd, gDnd, gDtd);
-    if (s == 0 || s == 3) {
+      point_fluxes_vjp<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, gF, gA, gB, gUd, gDnd, gDtd);
       emit(s, gUd, gDnd, gDtd);
-    } else {
+    }
+  };
+  side(true);
+  side(false);
+  if constexpr (CHARW) {
+    if (proj) {
+      T U1[M], U2[M], dn[M], dt[M], gU1[M], gU2[M], z[M];
+      ld(1, U1, dn, dt);
+      ld(2, U2, dn, dt);
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        if (s == 1) {
-          gU1[c] = gUd[c];
-          gDn1[c] = gDnd[c];
-          gDt1[c] = gDtd[c];
-        } else {
-          gU2[c] = gUd[c];
-          gDn2[c] = gDnd[c];
-          gDt2[c] = gDtd[c];
-        }
-      }
+      for (int c = 0; c < M; ++c) gU1[c] = gU2[c] = z[c] = T(0);
+      roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
+      emit(1, gU1, z, z);
+      emit(2, gU2, z, z);
     }
   }
-  if constexpr (CHARW) {
-    if (proj) roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
-  }
-  emit(1, gU1, gDn1, gDt1);
-  emit(2, gU2, gDn2, gDt2);
 }
 
 }  // namespace hweno

@@ -58,6 +58,19 @@ __device__ __forceinline__ int map_index(int i, int n, int bc) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Loads and stores through the global address space.  Pointers that arrive
+// through memory (the batched instance descriptors) are generic to the
+// compiler, which then cannot rule out aliasing with the LDS tile and
+// serialises every HBM load against the LDS writes around it.
+template <typename T>
+__device__ __forceinline__ T gld(const T* p) {
+  return *(const __attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, T v) {
+  *(__attribute__((address_space(1))) T*)p = v;
+}
+
 __device__ __forceinline__ unsigned long long dbits(double x) {
   return (unsigned long long)__double_as_longlong(x);
 }
@@ -93,11 +106,25 @@ __device__ __forceinline__ void block_fold(double sx, double sy, uint32_t flags,
       by = red[q][1] > by ? red[q][1] : by;
       flags |= redf[q];
     }
+    // global-address-space atomics (see gld): the slot may come from memory.
+    // The slots only grow during a launch, so a value read from them is a
+    // lower bound of the final maximum: a workgroup whose maximum does not
+    // exceed it has nothing to add.  Once the first workgroups have folded
+    // theirs, almost every later one skips its atomic, and tens of thousands
+    // of read-modify-writes no longer queue on one address.
+    using gu64 = __attribute__((address_space(1))) unsigned long long;
     if (do_speeds) {
-      atomicMax((unsigned long long*)slot, bx);
-      atomicMax((unsigned long long*)slot + 1, by);
+      const unsigned long long cx =
+          __hip_atomic_load((gu64*)slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const unsigned long long cy =
+          __hip_atomic_load((gu64*)slot + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (bx > cx) __hip_atomic_fetch_max((gu64*)slot, bx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (by > cy)
+        __hip_atomic_fetch_max((gu64*)slot + 1, by, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    if (flags && status) atomicOr(status, (unsigned long long)flags);
+    if (flags && status)
+      __hip_atomic_fetch_or((gu64*)status, (unsigned long long)flags, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
@@ -112,6 +139,33 @@ __device__ __forceinline__ int xcd_band(int b, int nb) {
   if (b >= per * NXCD) return b;
   return (b % NXCD) * per + (b / NXCD);
 }
+
+// Persistent variant: the tile list is cut into 8 contiguous bands, band x
+// is processed by the workgroups on XCD x (blockIdx % 8 == x), in order.
+// Visits every t in [0, total) exactly once; `it` counts the iterations.
+struct BandIter {
+  int lb, nlb, band_lo, band_hi;
+  __device__ __forceinline__ BandIter(int total) {
+    constexpr int NXCD = 8;
+    const int nb = (int)gridDim.x;
+    if (nb < NXCD) {  // too few workgroups for one band each: plain striding
+      nlb = nb;
+      lb = (int)blockIdx.x;
+      band_lo = 0;
+      band_hi = total;
+      return;
+    }
+    const int x = (int)blockIdx.x % NXCD;
+    // workgroups of XCD x: x, x+8, ... (the last band may get fewer)
+    nlb = nb / NXCD + ((nb % NXCD) > x ? 1 : 0);
+    lb = (int)blockIdx.x / NXCD;
+    const int per = (total + NXCD - 1) / NXCD;
+    band_lo = min(x * per, total);
+    band_hi = min(band_lo + per, total);
+  }
+  __device__ __forceinline__ int tile(int it) const { return band_lo + lb + it * nlb; }
+  __device__ __forceinline__ bool valid(int it) const { return tile(it) < band_hi; }
+};
 
 // time step of stage K and the speeds it splits with (uniform per grid)
 template <int DIM, int K>
@@ -171,13 +225,28 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
   const long long fs = a.fs;
 
   // ---- stage the tile and its halo in LDS ----
-  for (int q = tid; q < W * HR; q += NT) {
-    const int lr = q / W, lc = q - lr * W;
-    const int gi = map_index(i0 - 2 + lc, nx, a.bc_x);
-    const int gj = (DIM == 2) ? map_index(j0 - HY + lr, ny, a.bc_y) : 0;
-    const long long g = (long long)gj * nx + gi;
+  // All rounds' loads are issued before the first LDS write.
+  constexpr int NS = (W * HR + NT - 1) / NT;
+  T v[NS][NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) sm[(f * HR + lr) * W + lc] = a.in[f * fs + g];
+  for (int r = 0; r < NS; ++r) {
+    const int q = tid + r * NT;
+    if (q < W * HR) {
+      const int lr = q / W, lc = q - lr * W;
+      const int gi = map_index(i0 - 2 + lc, nx, a.bc_x);
+      const int gj = (DIM == 2) ? map_index(j0 - HY + lr, ny, a.bc_y) : 0;
+      const long long g = (long long)gj * nx + gi;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) v[r][f] = gld(a.in + f * fs + g);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    const int q = tid + r * NT;
+    if (q < W * HR) {
+#pragma unroll
+      for (int f = 0; f < NF; ++f) sm[f * HR * W + q] = v[r][f];
+    }
   }
   __syncthreads();
 
@@ -275,9 +344,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
   if constexpr (K == 0) {
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      a.out[c * fs + g] = LU[c];
-      a.out[(M + c) * fs + g] = LV[c];
-      if constexpr (DIM == 2) a.out[(2 * M + c) * fs + g] = LW[c];
+      gst(a.out + c * fs + g, LU[c]);
+      gst(a.out + (M + c) * fs + g, LV[c]);
+      if constexpr (DIM == 2) gst(a.out + (2 * M + c) * fs + g, LW[c]);
     }
   } else {
     // S^_k = (U_k, limited derivatives of S_k)
@@ -309,19 +378,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
       for (int f = 0; f < NF; ++f) out[f] = Sh[f] + tdt * L[f];
       if (k.limiter_on) {
 #pragma unroll
-        for (int f = M; f < NF; ++f) a.base[(f - M) * fs + g] = Sh[f];
+        for (int f = M; f < NF; ++f) gst(a.base + (f - M) * fs + g, Sh[f]);
       }
     } else {
       const T w0 = (K == 2) ? T(0.75) : T(1.0 / 3.0);
       const T w1 = (K == 2) ? T(0.25) : T(2.0 / 3.0);
 #pragma unroll
       for (int f = 0; f < NF; ++f) {
-        const T s0 = (f < M || !k.limiter_on) ? a.st0[f * fs + g] : a.base[(f - M) * fs + g];
+        const T s0 = (f < M || !k.limiter_on) ? gld(a.st0 + f * fs + g) : gld(a.base + (f - M) * fs + g);
         out[f] = w0 * s0 + w1 * (Sh[f] + tdt * L[f]);
       }
     }
 #pragma unroll
-    for (int f = 0; f < NF; ++f) a.out[f * fs + g] = out[f];
+    for (int f = 0; f < NF; ++f) gst(a.out + f * fs + g, out[f]);
     point_speeds<T, PHYS, DIM>(out, k, sx, sy, flags);
   }
   (void)alx;
@@ -332,8 +401,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
 // stage / right-hand-side kernel over one grid
 // K = 0: right-hand side only; K = 1, 2, 3: SSP-RK3 stage K.
 // ---------------------------------------------------------------------------
+// FP32 stage kernels are held to three resident waves per SIMD (<= 170
+// VGPRs); FP64 ones need the whole register file at one wave.
+template <typename T>
+struct StageOcc {
+  static constexpr int WAVES = sizeof(T) == 4 ? 3 : 1;
+};
+
 template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_stage(StageArgs<T> a, Consts<T> k) {
+__global__ __launch_bounds__(NT, StageOcc<T>::WAVES) void k_stage(StageArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
   constexpr int HY = (DIM == 2) ? 2 : 0;
@@ -381,15 +457,6 @@ struct BatchTile<1> {  // 231 x- and 256 y-interfaces: one pass each, wider rows
   static constexpr int TX = 32, TY = 7, NT = 256;
 };
 
-__device__ __forceinline__ int find_instance(const hweno_instance* __restrict__ inst, int n,
-                                             int t, int V) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (inst[mid].tile_begin[V] <= t) lo = mid; else hi = mid - 1;
-  }
-  return lo;
-}
 
 template <typename T, int K>
 __device__ __forceinline__ StageArgs<T> instance_args(const hweno_instance& I, double cfl) {
@@ -418,56 +485,103 @@ __device__ __forceinline__ StageArgs<T> instance_args(const hweno_instance& I, d
   return a;
 }
 
+// One tile t of the flattened list; nothing is done when its instance's step
+// is skipped (a decision uniform over the workgroup).
 template <typename T, int V, int K>
-__global__ __launch_bounds__(256) void k_stage_batched(const hweno_instance* __restrict__ inst,
-                                                       int n_inst, int total, double cfl,
-                                                       Consts<T> k) {
+__device__ __forceinline__ void batched_tile(const hweno_instance* __restrict__ inst,
+                                             const int* __restrict__ tile_map, int t, double cfl,
+                                             const Consts<T>& k, T* sm, T* fb) {
   constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY, NT = BatchTile<V>::NT;
+  const hweno_instance& I = inst[tile_map[t]];
+  StageArgs<T> a = instance_args<T, K>(I, cfl);
+  double dt;
+  if (!stage_dt<2, K>(nullptr, a.ctrl, a.dt_fixed, a.t_end, cfl, a.dx, a.dy, 0,
+                      t == I.tile_begin[V] && threadIdx.x == 0, a.status, dt))
+    return;  // this instance's step is skipped
+  const double alx = a.ctrl[2 * (K - 1)], aly = a.ctrl[2 * (K - 1) + 1];
+  const int lt = t - I.tile_begin[V];
+  const int ntx = (I.nx + TX - 1) / TX;
+  const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
+  T sx = T(0), sy = T(0);
+  uint32_t flags = 0;
+  stage_tile<T, PH_EULER, 2, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
+                                            flags);
+  block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status, K < 3);
+}
+
+// ONE: exactly one tile per workgroup (grid = tile count, XCD-banded order).
+// Nothing is written before the descriptor and control words are read, so
+// those reads stay scalar and never queue behind the other workgroups'
+// atomics on the same control line.  Otherwise: persistent, striding over
+// XCD bands of the tile list.
+template <typename T, int V, int K, bool ONE>
+__global__ __launch_bounds__(256, StageOcc<T>::WAVES) void k_stage_batched(
+    const hweno_instance* __restrict__ inst, const int* __restrict__ tile_map, int total,
+    double cfl, Consts<T> k) {
+  constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY;
   __shared__ T sm[12 * (TY + 4) * (TX + 4)];
   __shared__ T fb[12 * (TY + 1) * (TX + 1)];
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const hweno_instance& I = inst[find_instance(inst, n_inst, t, V)];
-    StageArgs<T> a = instance_args<T, K>(I, cfl);
-    double dt;
-    if (!stage_dt<2, K>(nullptr, a.ctrl, a.dt_fixed, a.t_end, cfl, a.dx, a.dy, 0,
-                        t == I.tile_begin[V] && threadIdx.x == 0, a.status, dt))
-      continue;  // uniform over the workgroup: this instance's step is skipped
-    const double alx = a.ctrl[2 * (K - 1)], aly = a.ctrl[2 * (K - 1) + 1];
-    const int lt = t - I.tile_begin[V];
-    const int ntx = (I.nx + TX - 1) / TX;
-    const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
-    T sx = T(0), sy = T(0);
-    uint32_t flags = 0;
-    stage_tile<T, PH_EULER, 2, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx,
-                                              sy, flags);
-    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status, K < 3);
+  if constexpr (ONE) {
+    batched_tile<T, V, K>(inst, tile_map, xcd_band(blockIdx.x, gridDim.x), cfl, k, sm, fb);
+  } else {
+    const BandIter bi(total);
+    for (int it = 0; bi.valid(it); ++it) {
+      batched_tile<T, V, K>(inst, tile_map, bi.tile(it), cfl, k, sm, fb);
+      __syncthreads();  // LDS tile and fold slots are reused by the next tile
+    }
   }
 }
 
-// speeds of every instance's state (slots pre-zeroed by k_begin_batched)
+// speeds of every instance's state (slots pre-zeroed by k_begin_batched).
+// Each workgroup walks one contiguous chunk of the tile list, keeps a running
+// maximum while consecutive tiles belong to the same instance and folds it
+// into that instance's slot only when the instance changes (cells are read
+// once, so no halo locality is at stake here).
 template <typename T, int V>
 __global__ __launch_bounds__(256) void k_alpha_batched(const hweno_instance* __restrict__ inst,
-                                                       int n_inst, int total, Consts<T> k) {
+                                                       const int* __restrict__ tile_map,
+                                                       int total, Consts<T> k) {
   constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY;
-  for (int t = blockIdx.x; t < total; t += gridDim.x) {
-    const hweno_instance& I = inst[find_instance(inst, n_inst, t, V)];
+  const long long nb = gridDim.x;
+  const int t_lo = (int)(total * (long long)blockIdx.x / nb);
+  const int t_hi = (int)(total * ((long long)blockIdx.x + 1) / nb);
+  int cur = -1;
+  T sx = T(0), sy = T(0);
+  uint32_t flags = 0;
+  for (int t = t_lo; t < t_hi; ++t) {
+    const int q = tile_map[t];
+    if (q != cur) {  // uniform over the workgroup
+      if (cur >= 0) {
+        double* ctrl = (double*)inst[cur].ws;
+        block_fold<256>(double(sx), double(sy), flags, ctrl, (unsigned long long*)(ctrl + 8), true);
+        __syncthreads();  // the fold's LDS slots are reused by the next fold
+        sx = sy = T(0);
+        flags = 0;
+      }
+      cur = q;
+    }
+    const hweno_instance& I = inst[q];
     const int lt = t - I.tile_begin[V];
     const int ntx = (I.nx + TX - 1) / TX;
     const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
     const int tx = threadIdx.x % TX, ty = threadIdx.x / TX;
     const int gi = tile_x * TX + tx, gj = tile_y * TY + ty;
-    T sx = T(0), sy = T(0);
-    uint32_t flags = 0;
     if (threadIdx.x < TX * TY && gi < I.nx && gj < I.ny) {
       const long long n = (long long)I.nx * I.ny;
       const long long g = (long long)gj * I.nx + gi;
       const T* S = (const T*)I.state;
       T U[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) U[c] = S[c * n + g];
-      point_speeds<T, PH_EULER, 2>(U, k, sx, sy, flags);
+      for (int c = 0; c < 4; ++c) U[c] = gld(S + c * n + g);
+      T ax, ay;
+      point_speeds<T, PH_EULER, 2>(U, k, ax, ay, flags);
+      // bit-pattern max keeps NaN
+      sx = (dbits(double(ax)) > dbits(double(sx))) ? ax : sx;
+      sy = (dbits(double(ay)) > dbits(double(sy))) ? ay : sy;
     }
-    double* ctrl = (double*)I.ws;
+  }
+  if (cur >= 0) {
+    double* ctrl = (double*)inst[cur].ws;
     block_fold<256>(double(sx), double(sy), flags, ctrl, (unsigned long long*)(ctrl + 8), true);
   }
 }
@@ -513,8 +627,13 @@ struct AdjArgs {
   double dx, dy;
 };
 
+template <typename T>
+struct AdjOcc {
+  static constexpr int WAVES = sizeof(T) == 4 ? 2 : 1;
+};
+
 template <typename T, int PHYS, int DIM, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT) void k_adjoint(AdjArgs<T> a, Consts<T> k) {
+__global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
   constexpr int GX = 2, GY = (DIM == 2) ? 2 : 0;  // ghost width of E
@@ -1118,10 +1237,12 @@ struct RunStep {
   }
 };
 
+// 2D adjoint tile: 15 x 14 cells, so the 18 x 14 x-interfaces and the
+// 15 x 17 y-interfaces touching it each fit one pass of 256 threads
 template <int DIM>
 struct AdjTile {
-  static constexpr int TX = (DIM == 2) ? 16 : 256;
-  static constexpr int TY = (DIM == 2) ? 16 : 1;
+  static constexpr int TX = (DIM == 2) ? 15 : 253;
+  static constexpr int TY = (DIM == 2) ? 14 : 1;
   static constexpr int NT = 256;
 };
 
@@ -1267,16 +1388,31 @@ int tiles_of(int nx, int ny) {
 }
 
 template <typename T, int V>
-hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, int n, int total,
-                         int blocks, hipStream_t s) {
+hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, const int* map, int n,
+                         int total, int blocks, hipStream_t s) {
   const Consts<T> k = make_consts<T>(p);
-  const int grid = blocks > 0 ? std::min(blocks, total) : std::min(total, 8 * device_cus());
+  int grid = blocks;
+  if (grid <= 0) {  // default: exactly the workgroups that can be resident at once
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_batched<T, V, 1, false>, 256, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+      per_cu = 1;
+    grid = per_cu * device_cus();
+  }
+  grid = std::min(grid, total);
   const unsigned small = (unsigned)((n + 255) / 256);
   k_begin_batched<<<small, 256, 0, s>>>(inst, n);
-  k_alpha_batched<T, V><<<grid, 256, 0, s>>>(inst, n, total, k);
-  timed(s, [&] { k_stage_batched<T, V, 1><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
-  timed(s, [&] { k_stage_batched<T, V, 2><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
-  timed(s, [&] { k_stage_batched<T, V, 3><<<grid, 256, 0, s>>>(inst, n, total, p->cfl, k); });
+  k_alpha_batched<T, V><<<std::min(total, 4 * device_cus()), 256, 0, s>>>(inst, map, total, k);
+  if (grid == total) {
+    timed(s, [&] { k_stage_batched<T, V, 1, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 2, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 3, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+  } else {
+    timed(s, [&] { k_stage_batched<T, V, 1, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 2, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 3, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+  }
   k_finish_batched<<<small, 256, 0, s>>>(inst, n);
   return launch_check("rk3_step_batched");
 }
@@ -1437,23 +1573,44 @@ hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* in
   return ok();
 }
 
+hweno_status hweno_batch_tile_map(const hweno_instance* inst, int32_t n_inst, int32_t variant,
+                                  int32_t* map, int32_t total_tiles) {
+  if (!inst || !map || n_inst < 1 || variant < 0 || variant >= HWENO_BATCH_VARIANTS)
+    return fail(HWENO_ERR_INVALID_ARG, "inst, map must be non-NULL, n_inst >= 1, variant valid");
+  long long filled = 0;
+  for (int q = 0; q < n_inst; ++q) {
+    const int b = inst[q].tile_begin[variant], n = inst[q].n_tiles[variant];
+    if (b != filled || n < 1 || (long long)b + n > total_tiles)
+      return fail(HWENO_ERR_INVALID_ARG, "instance %d: descriptors not prepared for %d tiles", q,
+                  total_tiles);
+    for (int t = 0; t < n; ++t) map[b + t] = q;
+    filled += n;
+  }
+  if (filled != total_tiles) return fail(HWENO_ERR_INVALID_ARG, "tile count mismatch");
+  return ok();
+}
+
 hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_instance* inst_dev,
-                                    int32_t n_inst, int32_t total_tiles, int32_t variant,
-                                    int32_t blocks, void* stream) {
+                                    const int32_t* tile_map_dev, int32_t n_inst,
+                                    int32_t total_tiles, int32_t variant, int32_t blocks,
+                                    void* stream) {
   hweno_status st = batch_common_ok(common);
   if (st) return st;
-  if (!inst_dev || n_inst < 1 || total_tiles < n_inst)
-    return fail(HWENO_ERR_INVALID_ARG, "inst_dev must be non-NULL, n_inst >= 1, total_tiles >= n_inst");
+  if (!inst_dev || !tile_map_dev || n_inst < 1 || total_tiles < n_inst)
+    return fail(HWENO_ERR_INVALID_ARG,
+                "inst_dev, tile_map_dev must be non-NULL, n_inst >= 1, total_tiles >= n_inst");
   if (variant < 0 || variant >= HWENO_BATCH_VARIANTS)
     return fail(HWENO_ERR_INVALID_ARG, "variant must be in [0, %d)", HWENO_BATCH_VARIANTS);
   if (blocks < 0) return fail(HWENO_ERR_INVALID_ARG, "blocks must be >= 0");
   hipStream_t s = (hipStream_t)stream;
   if (common->dtype == HWENO_F64) {
-    st = variant == 0 ? run_batched<double, 0>(common, inst_dev, n_inst, total_tiles, blocks, s)
-                      : run_batched<double, 1>(common, inst_dev, n_inst, total_tiles, blocks, s);
+    st = variant == 0
+             ? run_batched<double, 0>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s)
+             : run_batched<double, 1>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s);
   } else {
-    st = variant == 0 ? run_batched<float, 0>(common, inst_dev, n_inst, total_tiles, blocks, s)
-                      : run_batched<float, 1>(common, inst_dev, n_inst, total_tiles, blocks, s);
+    st = variant == 0
+             ? run_batched<float, 0>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s)
+             : run_batched<float, 1>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s);
   }
   if (st) return st;
   return ok();

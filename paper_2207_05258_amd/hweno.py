@@ -87,7 +87,9 @@ def lib() -> ctypes.CDLL:
                                         vp], ctypes.c_int),
             "hweno_batch_prepare": ([P, ctypes.POINTER(_CInstance), ctypes.c_int32,
                                      ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
-            "hweno_rk3_step_batched": ([P, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+            "hweno_batch_tile_map": ([ctypes.POINTER(_CInstance), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32), ctypes.c_int32], ctypes.c_int),
+            "hweno_rk3_step_batched": ([P, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, vp], ctypes.c_int),
             "hweno_timing_begin": ([ctypes.c_int32], ctypes.c_int),
             "hweno_timing_end": ([ctypes.POINTER(ctypes.c_int64), dp], ctypes.c_int),
@@ -347,6 +349,12 @@ class BatchedStepper:
         self._host = arr
         blob = torch.frombuffer(bytearray(bytes(arr)), dtype=torch.uint8)
         self.desc = blob.to(device)
+        self.maps = []
+        for v in range(BATCH_VARIANTS):
+            m = (ctypes.c_int32 * self.total_tiles[v])()
+            _check(lib().hweno_batch_tile_map(arr, n, v, m, self.total_tiles[v]),
+                   "hweno_batch_tile_map")
+            self.maps.append(torch.frombuffer(bytearray(bytes(m)), dtype=torch.int32).to(device))
         self.cells = sum(int(S.shape[1]) * int(S.shape[2]) for S in states)
         self.variant = 0
         self.blocks = 0
@@ -359,7 +367,8 @@ class BatchedStepper:
     def step(self, variant: Optional[int] = None, blocks: Optional[int] = None):
         v = self.variant if variant is None else int(variant)
         b = self.blocks if blocks is None else int(blocks)
-        _check(lib().hweno_rk3_step_batched(ctypes.byref(self._c), self.desc.data_ptr(), self.n,
+        _check(lib().hweno_rk3_step_batched(ctypes.byref(self._c), self.desc.data_ptr(),
+                                            self.maps[v].data_ptr(), self.n,
                                             self.total_tiles[v], v, b, _stream()),
                "hweno_rk3_step_batched")
 
@@ -406,7 +415,9 @@ def autotune_batched(stepper: BatchedStepper, trials: int = 2):
     scratch = BatchedStepper(scratch_states, grids, stepper.common)
     results = {}
     for v in range(BATCH_VARIANTS):
-        for b in (0, 2 * cus, 4 * cus, 16 * cus):
+        # 0 = the resident capacity of the stage kernel (persistent), or one
+        # workgroup per tile, or over-subscribed persistent grids
+        for b in (0, 2 * cus, 4 * cus, scratch.total_tiles[v]):
             scratch.step(v, b)  # warm-up
             torch.cuda.synchronize()
             e0 = torch.cuda.Event(enable_timing=True)

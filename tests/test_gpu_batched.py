@@ -52,15 +52,19 @@ def _individual(ws, dtype, steps=1, **common_kw):
 UNEVEN = [(37, 29), (16, 15), (5, 3), (64, 7), (1, 1), (33, 46), (100, 18)]
 
 
+@pytest.mark.parametrize("blocks", [0, 5, 16], ids=["one_tile_per_wg", "persistent5", "banded16"])
 @pytest.mark.parametrize("variant", [0, 1])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
-def test_batched_equals_individual_bitwise(variant, dtype):
+def test_batched_equals_individual_bitwise(variant, dtype, blocks):
+    """blocks=0 gives one workgroup per tile here (the batch has fewer tiles
+    than resident workgroups); blocks=5 and 16 make every workgroup walk
+    several tiles (plain striding below 8 workgroups, XCD bands from 8 on)."""
     ws = hi.batched_instances(len(UNEVEN), 3, sizes=UNEVEN)
-    announce("batched == individual", variant, dtype)
+    announce("batched == individual", variant, dtype, blocks)
     states, grids, common = _batch(ws, dtype)
     b = h.BatchedStepper(states, grids, common)
     for _ in range(2):
-        b.step(variant=variant)
+        b.step(variant=variant, blocks=blocks)
     ref, ctrls = _individual(ws, dtype, steps=2)
     for q in range(len(ws)):
         assert torch.equal(states[q], ref[q]), (q, ws[q].name)
