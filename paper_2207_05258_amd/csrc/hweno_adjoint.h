@@ -372,12 +372,16 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
 
 // ---------------------------------------------------------------------------
 // VJP of interface_fluxes(): given the adjoints of f-hat, h-hat and the mixed
-// flux (normal frame), emit(s, gU, gDn, gDt) receives adjoint contributions
-// for the state of stencil point s (additively; a point may be emitted more
-// than once).  The "+" side (points 0..2) and the mirrored "-" side (points
-// 1..3) are differentiated in separate passes, so that only one side's
-// projected data and adjoints are live at a time.
+// flux (normal frame), emit(s, mode, gU, gDn, gDt) receives adjoint
+// contributions for the state of stencil point s.  mode EMIT_SET is the first
+// contribution to point s (all fields), EMIT_ADD adds to all fields, EMIT_ADD_U
+// adds to the U fields only (gDn, gDt are zero).  The "+" side (points 0..2)
+// and the mirrored "-" side (points 1..3) are differentiated in separate
+// passes, so that only one side's projected data and adjoints are live at a
+// time; every point receives exactly one EMIT_SET, before any addition.
 // ---------------------------------------------------------------------------
+enum { EMIT_SET = 0, EMIT_ADD = 1, EMIT_ADD_U = 2 };
+
 template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Emit>
 HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Consts<T>& k,
                          const T* gfh, const T* ghh, const T* gxh, const Emit& emit) {
@@ -489,7 +493,7 @@ HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Const
         gDtd[c] = T(0);
       }
       point_fluxes_vjp<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, gF, gA, gB, gUd, gDnd, gDtd);
-      emit(s, gUd, gDnd, gDtd);
+      emit(s, (plus || s == 3) ? EMIT_SET : EMIT_ADD, gUd, gDnd, gDtd);
     }
   };
   side(true);
@@ -502,8 +506,8 @@ HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Const
 #pragma unroll
       for (int c = 0; c < M; ++c) gU1[c] = gU2[c] = z[c] = T(0);
       roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
-      emit(1, gU1, z, z);
-      emit(2, gU2, z, z);
+      emit(1, EMIT_ADD_U, gU1, z, z);
+      emit(2, EMIT_ADD_U, gU2, z, z);
     }
   }
 }

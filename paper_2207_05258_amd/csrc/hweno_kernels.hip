@@ -632,6 +632,15 @@ struct AdjOcc {
   static constexpr int WAVES = sizeof(T) == 4 ? 2 : 1;
 };
 
+constexpr int cmax(int x, int y) { return x > y ? x : y; }
+
+// One output tile of E per workgroup (TX x TY entries, ghost entries
+// included).  Every interface and limiter stencil that touches the tile is
+// differentiated by one lane, which writes its contributions to the stencil's
+// cells into lane-private LDS slots (no atomics); after a barrier the owner
+// of each output entry gathers the slots that point at it.  The state tile is
+// staged cell-interleaved ([row][col][field]) so that one stencil point's
+// fields are read with a few wide LDS loads.
 template <typename T, int PHYS, int DIM, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
@@ -639,14 +648,21 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
   constexpr int GX = 2, GY = (DIM == 2) ? 2 : 0;  // ghost width of E
   constexpr int HX = 3, HY = (DIM == 2) ? 3 : 0;  // state halo around the tile
   constexpr int W = TX + 2 * HX, HR = TY + 2 * HY;
-  __shared__ T sm[NF * HR * W];
+  constexpr int NIX = TY * (TX + 3);                   // x-interfaces touching the tile
+  constexpr int NIY = (DIM == 2) ? TX * (TY + 3) : 0;  // y-interfaces
+  constexpr int NLX = TY * (TX + 2);                   // cells whose x-limiter touches it
+  constexpr int NLY = (DIM == 2) ? TX * (TY + 2) : 0;
+  constexpr int GB = cmax(4 * NF * cmax(NIX, NIY), 5 * M * cmax(NLX, NLY));
+  static_assert(TX * TY <= NT, "one output entry per thread");
+  __shared__ __align__(16) T sm[HR * W * NF];
   __shared__ T acc[NF * TY * TX];
+  __shared__ T gb[GB];
   const int nx = a.nx, ny = a.ny;
   const long long fs = a.fs;
   const int ntx = (a.nxe + TX - 1) / TX;
   const int t = xcd_band(blockIdx.x, gridDim.x);
   const int bty = t / ntx, btx = t - bty * ntx;
-  const int rx0 = btx * TX - GX, ry0 = bty * TY - GY;  // real coordinates of tile cell (0, 0)
+  const int rx0 = btx * TX - GX, ry0 = bty * TY - GY;  // real coordinates of tile entry (0, 0)
   const int tid = threadIdx.x;
   const T cr = T(a.cr * (a.dtp ? *a.dtp : 1.0));
   const T cl = T(a.cl);
@@ -656,147 +672,222 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
     const int gj = (DIM == 2) ? map_index(ry0 - HY + lr, ny, a.bc_y) : 0;
     const long long g = (long long)gj * nx + gi;
 #pragma unroll
-    for (int f = 0; f < NF; ++f) sm[(f * HR + lr) * W + lc] = a.S[f * fs + g];
+    for (int f = 0; f < NF; ++f) sm[q * NF + f] = a.S[f * fs + g];
   }
-  for (int q = tid; q < NF * TY * TX; q += NT) acc[q] = T(0);
   __syncthreads();
 
   auto xl = [&](int f, int i, int j) -> T {
     return (i >= 0 && i < nx && j >= 0 && j < ny) ? a.XL[f * fs + (long long)j * nx + i] : T(0);
   };
-  auto add = [&](int f, int i, int j, T v) {
-    const int lx = i - rx0, ly = j - ry0;
-    if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && v != T(0)) atomicAdd(&acc[(f * TY + ly) * TX + lx], v);
+  // cell (i, j) of the staged state
+  auto cell = [&](int i, int j) -> const T* {
+    return sm + ((j - (ry0 - HY)) * W + (i - (rx0 - HX))) * NF;
   };
+  const bool owner = tid < TX * TY;
+  const int lx = tid % TX, ly = tid / TX;
   const T idx = T(1.0 / a.dx), hx = T(a.dx);
 
   // ---- x-interfaces I (between cells I and I+1) that touch the tile ----
-  for (int q = tid; q < TY * (TX + 3); q += NT) {
+  for (int q = tid; q < NIX; q += NT) {
     const int r = q / (TX + 3), ii = q - r * (TX + 3);
     const int j = ry0 + r, I = rx0 - 2 + ii;
-    if (j < 0 || j >= ny || I < -1 || I > nx - 1) continue;
+    T* slot = gb + q;  // contribution to field f of point s: slot[(s * NF + f) * NIX]
     T gf[M], gh[M], gx[M];
     bool any = false;
-#pragma unroll
-    for (int c = 0; c < M; ++c) {
-      gf[c] = cr * (xl(c, I + 1, j) - xl(c, I, j)) * idx;
-      gh[c] = cr * (xl(M + c, I + 1, j) - xl(M + c, I, j)) * idx;
-      gx[c] = (DIM == 2) ? cr * (xl(2 * M + c, I + 1, j) - xl(2 * M + c, I, j)) * idx : T(0);
-      any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
-    }
-    if (!any) continue;
-    const T* row = sm + (j - (ry0 - HY)) * W + (I - 1 - (rx0 - HX));
-    auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+    if (j >= 0 && j < ny && I >= -1 && I <= nx - 1) {
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        U[c] = row[(c * HR) * W + s];
-        Dn[c] = row[((M + c) * HR) * W + s];
-        Dt[c] = (DIM == 2) ? row[((2 * M + c) * HR) * W + s] : T(0);
+        gf[c] = cr * (xl(c, I + 1, j) - xl(c, I, j)) * idx;
+        gh[c] = cr * (xl(M + c, I + 1, j) - xl(M + c, I, j)) * idx;
+        gx[c] = (DIM == 2) ? cr * (xl(2 * M + c, I + 1, j) - xl(2 * M + c, I, j)) * idx : T(0);
+        any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
+      }
+    }
+    if (!any) {
+#pragma unroll
+      for (int e = 0; e < 4 * NF; ++e) slot[e * NIX] = T(0);
+      continue;
+    }
+    const T* row = cell(I - 1, j);
+    auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+      const T* p = row + s * NF;
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        U[c] = p[c];
+        Dn[c] = p[M + c];
+        Dt[c] = (DIM == 2) ? p[2 * M + c] : T(0);
       }
     };
-    auto emit = [&](int s, const T* gU, const T* gDn, const T* gDt) {
-      const int P = I - 1 + s;
+    auto emit = [&](int s, int mode, const T* gU, const T* gDn, const T* gDt) {
+      auto put = [&](int f, T v) {
+        T& d = slot[(s * NF + f) * NIX];
+        d = (mode == EMIT_SET) ? v : d + v;
+      };
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        add(c, P, j, gU[c]);
-        add(M + c, P, j, gDn[c]);
-        if constexpr (DIM == 2) add(2 * M + c, P, j, gDt[c]);
+        put(c, gU[c]);
+        if (mode != EMIT_ADD_U) {
+          put(M + c, gDn[c]);
+          if constexpr (DIM == 2) put(2 * M + c, gDt[c]);
+        }
       }
     };
     interface_vjp<T, PHYS, M, DIM == 2>(ld, T(a.alpha[0]), hx, idx, k.ax, k, gf, gh, gx, emit);
   }
+  __syncthreads();
+  if (owner) {
+    // entry (lx, ly) is point s of interface ii = lx + 3 - s in its row
+    const T* b = gb + ly * (TX + 3) + lx + 3;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      T v = T(0);
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2) v += b[(s2 * NF + f) * NIX - s2];
+      acc[(f * TY + ly) * TX + lx] = v;
+    }
+  }
 
   if constexpr (DIM == 2) {
     const T idy = T(1.0 / a.dy), hy = T(a.dy);
+    __syncthreads();
     // ---- y-interfaces J (between rows J and J+1) that touch the tile ----
-    for (int q = tid; q < TX * (TY + 3); q += NT) {
+    for (int q = tid; q < NIY; q += NT) {
       const int jj = q / TX, cc = q - jj * TX;
       const int i = rx0 + cc, J = ry0 - 2 + jj;
-      if (i < 0 || i >= nx || J < -1 || J > ny - 1) continue;
+      T* slot = gb + q;
       T gf[M], gh[M], gx[M];
       bool any = false;
-#pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-        gf[c] = cr * (xl(cs, i, J + 1) - xl(cs, i, J)) * idy;
-        gh[c] = cr * (xl(2 * M + cs, i, J + 1) - xl(2 * M + cs, i, J)) * idy;  // theta-hat
-        gx[c] = cr * (xl(M + cs, i, J + 1) - xl(M + cs, i, J)) * idy;          // xi-hat
-        any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
-      }
-      if (!any) continue;
-      const T* col = sm + (J - 1 - (ry0 - HY)) * W + (i - (rx0 - HX));
-      auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+      if (i >= 0 && i < nx && J >= -1 && J <= ny - 1) {
 #pragma unroll
         for (int c = 0; c < M; ++c) {
           const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-          U[c] = col[(cs * HR + s) * W];
-          Dn[c] = col[((2 * M + cs) * HR + s) * W];
-          Dt[c] = col[((M + cs) * HR + s) * W];
+          gf[c] = cr * (xl(cs, i, J + 1) - xl(cs, i, J)) * idy;
+          gh[c] = cr * (xl(2 * M + cs, i, J + 1) - xl(2 * M + cs, i, J)) * idy;  // theta-hat
+          gx[c] = cr * (xl(M + cs, i, J + 1) - xl(M + cs, i, J)) * idy;          // xi-hat
+          any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
+        }
+      }
+      if (!any) {
+#pragma unroll
+        for (int e = 0; e < 4 * NF; ++e) slot[e * NIY] = T(0);
+        continue;
+      }
+      const T* col = cell(i, J - 1);
+      auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+        const T* p = col + s * (W * NF);
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          // normal frame: swap the two momenta; Dn = U_y, Dt = U_x
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          U[c] = p[cs];
+          Dn[c] = p[2 * M + cs];
+          Dt[c] = p[M + cs];
         }
       };
-      auto emit = [&](int s, const T* gU, const T* gDn, const T* gDt) {
-        const int P = J - 1 + s;
+      auto emit = [&](int s, int mode, const T* gU, const T* gDn, const T* gDt) {
+        auto put = [&](int f, T v) {
+          T& d = slot[(s * NF + f) * NIY];
+          d = (mode == EMIT_SET) ? v : d + v;
+        };
 #pragma unroll
         for (int c = 0; c < M; ++c) {
           const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-          add(cs, i, P, gU[c]);
-          add(2 * M + cs, i, P, gDn[c]);
-          add(M + cs, i, P, gDt[c]);
+          put(cs, gU[c]);
+          if (mode != EMIT_ADD_U) {
+            put(2 * M + cs, gDn[c]);
+            put(M + cs, gDt[c]);
+          }
         }
       };
       interface_vjp<T, PHYS, M, true>(ld, T(a.alpha[1]), hy, idy, k.ay, k, gf, gh, gx, emit);
     }
+    __syncthreads();
+    if (owner) {
+      // entry (lx, ly) is point s of interface jj = ly + 3 - s in its column
+      const T* b = gb + (ly + 3) * TX + lx;
+#pragma unroll
+      for (int f = 0; f < NF; ++f) {
+        T v = T(0);
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2) v += b[(s2 * NF + f) * NIY - s2 * TX];
+        acc[(f * TY + ly) * TX + lx] += v;
+      }
+    }
   }
 
   // ---- limiter: U_x along x (and U_y along y) of cells near the tile ----
+  // contributions of the limiter at cell C, component c, slot k:
+  //   0: U at C-1, 1: U at C, 2: U at C+1, 3: derivative at C-1, 4: derivative at C+1
   if (a.XM) {
-    for (int q = tid; q < TY * (TX + 2); q += NT) {
+    __syncthreads();
+    for (int q = tid; q < NLX; q += NT) {
       const int r = q / (TX + 2), ii = q - r * (TX + 2);
       const int j = ry0 + r, C = rx0 - 1 + ii;
-      if (j < 0 || j >= ny || C < 0 || C >= nx) continue;
-      const T* p = sm + (j - (ry0 - HY)) * W + (C - (rx0 - HX));
+      const bool live = j >= 0 && j < ny && C >= 0 && C < nx;
+      const T* p = live ? cell(C, j) : sm;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        const T mu = cl * a.XM[c * fs + (long long)j * nx + C];
-        if (mu == T(0)) continue;
-        const T* u = p + (c * HR) * W;
-        const T* v = p + ((M + c) * HR) * W;
-        T gum = 0, gu0 = 0, gup = 0, gvm = 0, gvp = 0;
-        limit1_vjp(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw, mu, gum, gu0, gup, gvm, gvp);
-        add(c, C - 1, j, gum);
-        add(c, C, j, gu0);
-        add(c, C + 1, j, gup);
-        add(M + c, C - 1, j, gvm);
-        add(M + c, C + 1, j, gvp);
+        const T mu = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
+        T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
+        if (mu != T(0))
+          limit1_vjp(p[-NF + c], p[c], p[NF + c], p[-NF + M + c], p[NF + M + c], hx, idx, k.lw,
+                     mu, g0, g1, g2, g3, g4);
+        gb[(0 * M + c) * NLX + q] = g0;
+        gb[(1 * M + c) * NLX + q] = g1;
+        gb[(2 * M + c) * NLX + q] = g2;
+        gb[(3 * M + c) * NLX + q] = g3;
+        gb[(4 * M + c) * NLX + q] = g4;
+      }
+    }
+    __syncthreads();
+    if (owner) {
+      // entry P = rx0 + lx: the limiter of cell C sits at ii = C - rx0 + 1
+      const T* b = gb + ly * (TX + 2) + lx + 1;  // ii of C = P
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        acc[(c * TY + ly) * TX + lx] += b[(0 * M + c) * NLX + 1] + b[(1 * M + c) * NLX] +
+                                        b[(2 * M + c) * NLX - 1];
+        acc[((M + c) * TY + ly) * TX + lx] += b[(3 * M + c) * NLX + 1] + b[(4 * M + c) * NLX - 1];
       }
     }
     if constexpr (DIM == 2) {
       const T idy = T(1.0 / a.dy), hy = T(a.dy);
-      for (int q = tid; q < TX * (TY + 2); q += NT) {
+      __syncthreads();
+      for (int q = tid; q < NLY; q += NT) {
         const int jj = q / TX, cc = q - jj * TX;
         const int i = rx0 + cc, C = ry0 - 1 + jj;
-        if (i < 0 || i >= nx || C < 0 || C >= ny) continue;
-        const T* p = sm + (C - (ry0 - HY)) * W + (i - (rx0 - HX));
+        const bool live = i >= 0 && i < nx && C >= 0 && C < ny;
+        const T* p = live ? cell(i, C) : sm;
+        constexpr int S = W * NF;
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-          const T mu = cl * a.XM[(M + c) * fs + (long long)C * nx + i];
-          if (mu == T(0)) continue;
-          const T* u = p + (c * HR) * W;
-          const T* w = p + ((2 * M + c) * HR) * W;
-          T gum = 0, gu0 = 0, gup = 0, gwm = 0, gwp = 0;
-          limit1_vjp(u[-W], u[0], u[W], w[-W], w[W], hy, idy, k.lw, mu, gum, gu0, gup, gwm, gwp);
-          add(c, i, C - 1, gum);
-          add(c, i, C, gu0);
-          add(c, i, C + 1, gup);
-          add(2 * M + c, i, C - 1, gwm);
-          add(2 * M + c, i, C + 1, gwp);
+          const T mu = live ? cl * a.XM[(M + c) * fs + (long long)C * nx + i] : T(0);
+          T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
+          if (mu != T(0))
+            limit1_vjp(p[-S + c], p[c], p[S + c], p[-S + 2 * M + c], p[S + 2 * M + c], hy, idy,
+                       k.lw, mu, g0, g1, g2, g3, g4);
+          gb[(0 * M + c) * NLY + q] = g0;
+          gb[(1 * M + c) * NLY + q] = g1;
+          gb[(2 * M + c) * NLY + q] = g2;
+          gb[(3 * M + c) * NLY + q] = g3;
+          gb[(4 * M + c) * NLY + q] = g4;
+        }
+      }
+      __syncthreads();
+      if (owner) {
+        const T* b = gb + (ly + 1) * TX + lx;  // jj of C = P
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          acc[(c * TY + ly) * TX + lx] += b[(0 * M + c) * NLY + TX] + b[(1 * M + c) * NLY] +
+                                          b[(2 * M + c) * NLY - TX];
+          acc[((2 * M + c) * TY + ly) * TX + lx] +=
+              b[(3 * M + c) * NLY + TX] + b[(4 * M + c) * NLY - TX];
         }
       }
     }
   }
-  __syncthreads();
-  for (int q = tid; q < TX * TY; q += NT) {
-    const int lx = q % TX, ly = q / TX;
+  // each owner wrote and reads only its own acc entries: no barrier needed
+  if (owner) {
     const int ex = btx * TX + lx, ey = bty * TY + ly;
     if (ex < a.nxe && ey < a.nye) {
 #pragma unroll
