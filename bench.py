@@ -42,8 +42,9 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the SHA-256 of the
 # kernel sources it was measured on (stale entries are reported as null).
 MEASURED_TRAFFIC = {
-    # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md
-    ("0e5a8766b90ecd97", "f64", 4096): 6.2651e9,
+    # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
+    ("e402757e4e1d90d2", "f64", 4096): 5.0826e+09,
+    ("e402757e4e1d90d2", "f32", 4096): 2.5406e+09,
 }
 
 
