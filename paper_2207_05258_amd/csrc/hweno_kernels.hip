@@ -268,14 +268,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
         if constexpr (DIM == 2) Dt[c] = row[((2 * M + c) * HR) * W + s];
       }
     };
-    T fh[M], hh[M], xh[M];
-    interface_fluxes<T, PHYS, M, DIM == 2>(ld, T(alx), hx, idx, k.ax, k, fh, hh, xh);
+    // linear fluxes accumulate in their flux-buffer slots (owned by this lane)
+    auto lin = [&](int s, int c, T dh, T dx) {
+      T& h1 = fb[((M + c) * FR + r) * FW + ix];
+      h1 = (s == 0) ? dh : h1 + dh;
+      if constexpr (DIM == 2) {
+        T& x1 = fb[((2 * M + c) * FR + r) * FW + ix];
+        x1 = (s == 0) ? dx : x1 + dx;
+      }
+    };
+    T fh[M];
+    interface_fluxes<T, PHYS, M, DIM == 2>(ld, lin, T(alx), hx, idx, k.ax, k, fh);
 #pragma unroll
-    for (int c = 0; c < M; ++c) {
-      fb[(c * FR + r) * FW + ix] = fh[c];
-      fb[((M + c) * FR + r) * FW + ix] = hh[c];
-      if constexpr (DIM == 2) fb[((2 * M + c) * FR + r) * FW + ix] = xh[c];
-    }
+    for (int c = 0; c < M; ++c) fb[(c * FR + r) * FW + ix] = fh[c];
   }
   __syncthreads();
   if (owner) {
@@ -310,14 +315,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
           Dt[c] = col[((M + cs) * HR + s) * W];
         }
       };
-      T fh[M], hh[M], xh[M];
-      interface_fluxes<T, PHYS, M, true>(ld, T(aly), hy, idy, k.ay, k, fh, hh, xh);
+      auto lin = [&](int s, int c, T dh, T dx) {
+        const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        T& h1 = fb[((M + cs) * FR + iy) * FW + cc];      // theta-hat -> L_W
+        h1 = (s == 0) ? dh : h1 + dh;
+        T& x1 = fb[((2 * M + cs) * FR + iy) * FW + cc];  // xi-hat -> L_V
+        x1 = (s == 0) ? dx : x1 + dx;
+      };
+      T fh[M];
+      interface_fluxes<T, PHYS, M, true>(ld, lin, T(aly), hy, idy, k.ay, k, fh);
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
         fb[(cs * FR + iy) * FW + cc] = fh[c];
-        fb[((M + cs) * FR + iy) * FW + cc] = hh[c];      // theta-hat -> L_W
-        fb[((2 * M + cs) * FR + iy) * FW + cc] = xh[c];  // xi-hat -> L_V
       }
     }
     __syncthreads();
@@ -401,15 +411,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
 // stage / right-hand-side kernel over one grid
 // K = 0: right-hand side only; K = 1, 2, 3: SSP-RK3 stage K.
 // ---------------------------------------------------------------------------
-// FP32 stage kernels are held to three resident waves per SIMD (<= 170
-// VGPRs); FP64 ones need the whole register file at one wave.
-template <typename T>
+// Resident waves per SIMD the stage kernels are compiled for (the register
+// budget is 512 / WAVES per lane).  Runge-Kutta stages fit four waves in FP32
+// (<= 128 VGPRs) and two in FP64; the right-hand-side-only kernels (K = 0)
+// keep one wave more of registers (they would spill at the stage bounds).
+template <typename T, int K>
 struct StageOcc {
-  static constexpr int WAVES = sizeof(T) == 4 ? 3 : 1;
+  static constexpr int WAVES = sizeof(T) == 4 ? (K == 0 ? 3 : 4) : (K == 0 ? 1 : 2);
 };
 
 template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
-__global__ __launch_bounds__(NT, StageOcc<T>::WAVES) void k_stage(StageArgs<T> a, Consts<T> k) {
+__global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
   constexpr int HY = (DIM == 2) ? 2 : 0;
@@ -515,7 +527,7 @@ __device__ __forceinline__ void batched_tile(const hweno_instance* __restrict__ 
 // atomics on the same control line.  Otherwise: persistent, striding over
 // XCD bands of the tile list.
 template <typename T, int V, int K, bool ONE>
-__global__ __launch_bounds__(256, StageOcc<T>::WAVES) void k_stage_batched(
+__global__ __launch_bounds__(256, (StageOcc<T, K>::WAVES)) void k_stage_batched(
     const hweno_instance* __restrict__ inst, const int* __restrict__ tile_map, int total,
     double cfl, Consts<T> k) {
   constexpr int TX = BatchTile<V>::TX, TY = BatchTile<V>::TY;

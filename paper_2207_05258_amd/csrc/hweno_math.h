@@ -259,14 +259,17 @@ struct Eigen {
 // Stencil points s = 0..3 are x_{i-1}, x_i, x_{i+1}, x_{i+2};
 // ld(s, U, Dn, Dt) loads the state of point s in the normal frame.
 // Outputs (normal frame): fh = f-hat (nonlinear, Section 2.1 with Remarks
-// 2.1/2.2), hh = h-hat (linear p0'^+ + p0'^-, component-wise), xh = the
-// mixed flux of eq. (mixed) (only when MIXED).
+// 2.1/2.2).  The two linear fluxes, h-hat (p0'^+ + p0'^-, component-wise)
+// and the mixed flux of eq. (mixed) (only when MIXED), are sums of one term
+// per stencil point; point s hands its terms to lin(s, c, dh, dx) as soon as
+// they are formed (s = 0 first, then 1, 2, 3), so the caller can accumulate
+// them where it stores them instead of keeping twelve partial sums live in
+// registers across the nonlinear reconstructions.
 //   alpha: global LF speed of this direction; h: cell size; ih = 1/h.
 // ---------------------------------------------------------------------------
-template <typename T, int PHYS, int M, bool MIXED, typename Loader>
-HW_HD void interface_fluxes(const Loader& ld, T alpha, T h,
-                                                 T ih, T an, const Consts<T>& k,
-                                                 T* fh, T* hh, T* xh) {
+template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Lin>
+HW_HD void interface_fluxes(const Loader& ld, const Lin& lin, T alpha, T h, T ih, T an,
+                            const Consts<T>& k, T* fh) {
   constexpr bool CHARW = (PHYS == PH_EULER);
   Eigen<T, M> eg;
   const bool proj = CHARW && k.characteristic;
@@ -290,14 +293,8 @@ HW_HD void interface_fluxes(const Loader& ld, T alpha, T h,
   constexpr T cA[4] = {T(1), T(-7), T(-7), T(1)};
   constexpr T cD[4] = {T(1), T(3), T(-3), T(-1)};
   constexpr T cX[4] = {T(-1), T(7), T(7), T(-1)};
-  T sF[M], sA[M];
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    sF[c] = T(0);
-    sA[c] = T(0);
-    if constexpr (MIXED) xh[c] = T(0);
-  }
   const T hh2 = T(0.5) * h;
+  const T i8 = T(0.125) * ih;
   // one stencil point: physics, linear-flux accumulation, split and projected data
   auto point = [&](const int s) {
     T U[M], Dn[M], Dt[M], F[M], A[M], B[M];
@@ -305,9 +302,10 @@ HW_HD void interface_fluxes(const Loader& ld, T alpha, T h,
     point_fluxes<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, F, A, B);
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      sF[c] += cF[s] * F[c] + alpha * cU[s] * U[c];
-      sA[c] += cA[s] * A[c] + alpha * cD[s] * Dn[c];
-      if constexpr (MIXED) xh[c] += cX[s] * B[c];
+      const T dh = (cF[s] * F[c] + alpha * cU[s] * U[c]) * i8 +
+                   (cA[s] * A[c] + alpha * cD[s] * Dn[c]) * T(1.0 / 24.0);
+      const T dx = MIXED ? cX[s] * B[c] * T(1.0 / 12.0) : T(0);
+      lin(s, c, dh, dx);
     }
     if (s <= 2) {
       T x[M], y[M];
@@ -365,12 +363,6 @@ HW_HD void interface_fluxes(const Loader& ld, T alpha, T h,
   } else {
 #pragma unroll
     for (int c = 0; c < M; ++c) fh[c] = fc[c];
-  }
-  const T i8 = T(0.125) * ih;
-#pragma unroll
-  for (int c = 0; c < M; ++c) {
-    hh[c] = sF[c] * i8 + sA[c] * T(1.0 / 24.0);
-    if constexpr (MIXED) xh[c] *= T(1.0 / 12.0);
   }
 }
 
