@@ -378,7 +378,10 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
 // adds to the U fields only (gDn, gDt are zero).  The "+" side (points 0..2)
 // and the mirrored "-" side (points 1..3) are differentiated in separate
 // passes, so that only one side's projected data and adjoints are live at a
-// time; every point receives exactly one EMIT_SET, before any addition.
+// time; every point receives exactly one EMIT_SET, before any addition.  The
+// eigen-system adjoint (through the Roe average) is linear in the per-side
+// accumulations, so each side applies its share at its end: the accumulators
+// never stay live across the two passes.
 // ---------------------------------------------------------------------------
 enum { EMIT_SET = 0, EMIT_ADD = 1, EMIT_ADD_U = 2 };
 
@@ -495,21 +498,22 @@ HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Const
       point_fluxes_vjp<T, PHYS, M, MIXED>(U, Dn, Dt, k, an, gF, gA, gB, gUd, gDnd, gDtd);
       emit(s, (plus || s == 3) ? EMIT_SET : EMIT_ADD, gUd, gDnd, gDtd);
     }
+    if constexpr (CHARW) {
+      if (proj) {
+        T U1[M], U2[M], dn[M], dt[M], gU1[M], gU2[M], z[M];
+        ld(1, U1, dn, dt);
+        ld(2, U2, dn, dt);
+#pragma unroll
+        for (int c = 0; c < M; ++c) gU1[c] = gU2[c] = z[c] = T(0);
+        roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
+        emit(1, EMIT_ADD_U, gU1, z, z);
+        emit(2, EMIT_ADD_U, gU2, z, z);
+        ge = EigenAdj<T>();
+      }
+    }
   };
   side(true);
   side(false);
-  if constexpr (CHARW) {
-    if (proj) {
-      T U1[M], U2[M], dn[M], dt[M], gU1[M], gU2[M], z[M];
-      ld(1, U1, dn, dt);
-      ld(2, U2, dn, dt);
-#pragma unroll
-      for (int c = 0; c < M; ++c) gU1[c] = gU2[c] = z[c] = T(0);
-      roe_vjp<T, M>(U1, U2, k.gm1, ge, gU1, gU2);
-      emit(1, EMIT_ADD_U, gU1, z, z);
-      emit(2, EMIT_ADD_U, gU2, z, z);
-    }
-  }
 }
 
 }  // namespace hweno
