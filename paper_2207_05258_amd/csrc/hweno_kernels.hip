@@ -618,6 +618,121 @@ __global__ void k_finish_batched(const hweno_instance* __restrict__ inst, int n_
   }
 }
 
+// Fold the ghost-padded adjoint onto the grid and apply the pointwise
+// Runge-Kutta transposes:
+//   out  = [out] + fold(E) + cu * XU   (XU on U only, or on all fields when
+//                                       identity_all; nothing when XU is NULL)
+//   L0   = ca * A + cb * B + out       (when L0 is non-NULL)
+template <typename T>
+struct FoldArgs {
+  const T* E;
+  int nxe, nye;
+  int nx, ny, bc_x, bc_y, dim, nf, m;
+  long long fs;
+  T* out;
+  int accumulate;
+  const T* XU;
+  double cu;
+  int identity_all;
+  T* L0;
+  const T* A;
+  const T* B;
+  double ca, cb;
+};
+
+// The Runge-Kutta transposes of the NF fields of cell index q, given their
+// folded adjoints v[].  Every load is issued before the first store: the
+// output may not be proven distinct from the inputs, and interleaving them
+// would serialise one memory round trip per field.
+template <typename T, int NF>
+__device__ __forceinline__ void fold_finish(const FoldArgs<T>& a, long long q, const T* v) {
+  T r[NF], av[NF], bv[NF];
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const long long o = (long long)f * a.fs + q;
+    r[f] = v[f];
+    if (a.accumulate) r[f] += a.out[o];
+    if (a.XU && (f < a.m || a.identity_all)) r[f] += T(a.cu) * a.XU[o];
+    if (a.L0) {
+      av[f] = a.A[o];
+      bv[f] = a.B[o];
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < NF; ++f) {
+    const long long o = (long long)f * a.fs + q;
+    a.out[o] = r[f];
+    if (a.L0) a.L0[o] = T(a.ca) * av[f] + T(a.cb) * bv[f] + r[f];
+  }
+}
+
+// field f of cell (i, j): its own entry of E plus every ghost entry the
+// boundary maps read from it, then the Runge-Kutta transposes
+template <typename T>
+__device__ __forceinline__ void fold_cell_field(const FoldArgs<T>& a, int i, int j, int f) {
+  const int GX = 2, GY = (a.dim == 2) ? 2 : 0;
+  const int gx[4] = {-2, -1, a.nx, a.nx + 1};
+  const int gy[4] = {-2, -1, a.ny, a.ny + 1};
+  const long long q = (long long)j * a.nx + i;
+  const T* Ef = a.E + (long long)f * a.nye * a.nxe;
+  T v = Ef[(long long)(j + GY) * a.nxe + (i + GX)];
+#pragma unroll
+  for (int g = 0; g < 4; ++g)
+    if (map_index(gx[g], a.nx, a.bc_x) == i) v += Ef[(long long)(j + GY) * a.nxe + (gx[g] + GX)];
+  if (a.dim == 2) {
+#pragma unroll
+    for (int g = 0; g < 4; ++g)
+      if (map_index(gy[g], a.ny, a.bc_y) == j) v += Ef[(long long)(gy[g] + GY) * a.nxe + (i + GX)];
+  }
+  const long long o = (long long)f * a.fs + q;
+  T r = v;
+  if (a.accumulate) r += a.out[o];
+  if (a.XU && (f < a.m || a.identity_all)) r += T(a.cu) * a.XU[o];
+  T av = T(0), bv = T(0);
+  if (a.L0) {
+    av = a.A[o];
+    bv = a.B[o];
+  }
+  a.out[o] = r;
+  if (a.L0) a.L0[o] = T(a.ca) * av + T(a.cb) * bv + r;
+}
+
+// one thread per (field, cell)
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold(FoldArgs<T> a) {
+  const long long t = blockIdx.x * 256ll + threadIdx.x;
+  if (t >= a.fs * a.nf) return;
+  const int f = (int)(t / a.fs);
+  const long long q = t - (long long)f * a.fs;
+  const int j = (int)(q / a.nx), i = (int)(q - (long long)j * a.nx);
+  fold_cell_field(a, i, j, f);
+}
+
+// 2D grids with nx, ny >= 4 after a fused adjoint: only the cells within two of
+// a boundary (the only ones the boundary maps read ghost entries from) are
+// folded here; every other cell was finished by the adjoint kernel itself.
+// Band cells are enumerated as the four columns 0, 1, nx-2, nx-1 (4*ny cells)
+// and then the four rows 0, 1, ny-2, ny-1 of the columns 2..nx-3; one thread
+// per (field, band cell).
+template <typename T>
+__global__ __launch_bounds__(256) void k_fold_band(FoldArgs<T> a) {
+  const int nxb = 4 * a.ny, nb = nxb + 4 * (a.nx - 4);
+  const int t = blockIdx.x * 256 + threadIdx.x;
+  if (t >= nb * a.nf) return;
+  const int f = t / nb, q = t - f * nb;
+  int i, j;
+  if (q < nxb) {
+    const int r = q & 3;
+    j = q >> 2;
+    i = r < 2 ? r : a.nx - 4 + r;
+  } else {
+    const int r = (q - nxb) & 3;
+    i = 2 + ((q - nxb) >> 2);
+    j = r < 2 ? r : a.ny - 4 + r;
+  }
+  fold_cell_field(a, i, j, f);
+}
+
 // ---------------------------------------------------------------------------
 // Discrete adjoint.  The forward operator reads ghost cells through the
 // boundary index maps; its adjoint scatters into a ghost-padded buffer E
@@ -637,6 +752,10 @@ struct AdjArgs {
   long long fs;
   int nxe, nye;
   double dx, dy;
+  // fused: entries of real cells at least two away from every boundary are
+  // folded and finished (fo's transposes) here instead of being stored in E
+  int fused;
+  FoldArgs<T> fo;
 };
 
 template <typename T>
@@ -902,60 +1021,19 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
   if (owner) {
     const int ex = btx * TX + lx, ey = bty * TY + ly;
     if (ex < a.nxe && ey < a.nye) {
+      const int i = ex - GX, j = ey - GY;
+      const bool inner = i >= 2 && i < nx - 2 && (DIM == 1 || (j >= 2 && j < ny - 2));
+      if (a.fused && inner) {
+        T v[NF];
 #pragma unroll
-      for (int f = 0; f < NF; ++f)
-        a.E[((long long)f * a.nye + ey) * a.nxe + ex] = acc[(f * TY + ly) * TX + lx];
+        for (int f = 0; f < NF; ++f) v[f] = acc[(f * TY + ly) * TX + lx];
+        fold_finish<T, NF>(a.fo, (long long)j * nx + i, v);
+      } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f)
+          a.E[((long long)f * a.nye + ey) * a.nxe + ex] = acc[(f * TY + ly) * TX + lx];
+      }
     }
-  }
-}
-
-// Fold the ghost-padded adjoint onto the grid and apply the pointwise
-// Runge-Kutta transposes:
-//   out  = [out] + fold(E) + cu * XU   (XU on U only, or on all fields when
-//                                       identity_all; nothing when XU is NULL)
-//   L0   = ca * A + cb * B + out       (when L0 is non-NULL)
-template <typename T>
-struct FoldArgs {
-  const T* E;
-  int nxe, nye;
-  int nx, ny, bc_x, bc_y, dim, nf, m;
-  long long fs;
-  T* out;
-  int accumulate;
-  const T* XU;
-  double cu;
-  int identity_all;
-  T* L0;
-  const T* A;
-  const T* B;
-  double ca, cb;
-};
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_fold(FoldArgs<T> a) {
-  const long long n = a.fs;
-  const long long q = blockIdx.x * 256ll + threadIdx.x;
-  if (q >= n) return;
-  const int j = (int)(q / a.nx), i = (int)(q - (long long)j * a.nx);
-  const int GX = 2, GY = (a.dim == 2) ? 2 : 0;
-  const int gx[4] = {-2, -1, a.nx, a.nx + 1};
-  const int gy[4] = {-2, -1, a.ny, a.ny + 1};
-  for (int f = 0; f < a.nf; ++f) {
-    const T* Ef = a.E + (long long)f * a.nye * a.nxe;
-    T v = Ef[(long long)(j + GY) * a.nxe + (i + GX)];
-#pragma unroll
-    for (int g = 0; g < 4; ++g)
-      if (map_index(gx[g], a.nx, a.bc_x) == i) v += Ef[(long long)(j + GY) * a.nxe + (gx[g] + GX)];
-    if (a.dim == 2) {
-#pragma unroll
-      for (int g = 0; g < 4; ++g)
-        if (map_index(gy[g], a.ny, a.bc_y) == j) v += Ef[(long long)(gy[g] + GY) * a.nxe + (i + GX)];
-    }
-    const long long o = (long long)f * n + q;
-    T r = a.accumulate ? a.out[o] + v : v;
-    if (a.XU && (f < a.m || a.identity_all)) r += T(a.cu) * a.XU[o];
-    a.out[o] = r;
-    if (a.L0) a.L0[o] = T(a.ca) * a.A[o] + T(a.cb) * a.B[o] + r;
   }
 }
 
@@ -1371,9 +1449,11 @@ AdjLayout adj_layout(const hweno_problem* p) {
 // one adjoint evaluation into E followed by one fold
 struct RunAdj {
   template <typename T, int PHYS, int DIM>
+  // fuse: finish interior cells inside the adjoint kernel (the fold's output
+  // buffers must then not alias S, XL or XM)
   static hweno_status run(const hweno_problem* p, const void* S, const void* XL, double cr,
                           const double* dtp, const void* XM, double cl, const double* alpha,
-                          void* ws, FoldArgs<T> fo, hipStream_t s) {
+                          void* ws, FoldArgs<T> fo, bool fuse, hipStream_t s) {
     const AdjLayout L = adj_layout(p);
     AdjArgs<T> a;
     a.S = (const T*)S;
@@ -1393,9 +1473,6 @@ struct RunAdj {
     a.nye = L.nye;
     a.dx = p->dx;
     a.dy = DIM == 2 ? p->dy : 1.0;
-    constexpr int TX = AdjTile<DIM>::TX, TY = AdjTile<DIM>::TY, NT = AdjTile<DIM>::NT;
-    const unsigned tiles = (unsigned)(((L.nxe + TX - 1) / TX) * ((L.nye + TY - 1) / TY));
-    timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
     fo.E = a.E;
     fo.nxe = L.nxe;
     fo.nye = L.nye;
@@ -1407,7 +1484,17 @@ struct RunAdj {
     fo.nf = Comps<PHYS, DIM>::NF;
     fo.m = Comps<PHYS, DIM>::M;
     fo.fs = a.fs;
-    k_fold<T><<<(unsigned)((a.fs + 255) / 256), 256, 0, s>>>(fo);
+    a.fused = (fuse && DIM == 2 && a.nx >= 4 && a.ny >= 4) ? 1 : 0;
+    a.fo = fo;
+    constexpr int TX = AdjTile<DIM>::TX, TY = AdjTile<DIM>::TY, NT = AdjTile<DIM>::NT;
+    const unsigned tiles = (unsigned)(((L.nxe + TX - 1) / TX) * ((L.nye + TY - 1) / TY));
+    timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+    if (a.fused) {
+      const long long nb = (4ll * a.ny + 4ll * (a.nx - 4)) * fo.nf;
+      k_fold_band<T><<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(fo);
+    } else {
+      k_fold<T><<<(unsigned)((a.fs * fo.nf + 255) / 256), 256, 0, s>>>(fo);
+    }
     return launch_check("adjoint");
   }
 };
@@ -1429,8 +1516,9 @@ struct RunRhsAdj {
   static hweno_status run(const hweno_problem* p, const void* state, const double* alpha,
                           const void* lam_rhs, const void* lam_lim, void* lam_state, void* ws,
                           hipStream_t s) {
+    // the caller's buffers may alias: fold in a separate pass
     return RunAdj::run<T, PHYS, DIM>(p, state, lam_rhs, 1.0, nullptr, lam_lim, 1.0, alpha, ws,
-                                     fold_args<T>(lam_state, 1, nullptr, 0.0, 0), s);
+                                     fold_args<T>(lam_state, 1, nullptr, 0.0, 0), false, s);
   }
 };
 
@@ -1452,9 +1540,10 @@ struct RunStepAdj {
     const int ida = lim ? 0 : 1;
     hweno_status st;
     // stage 3: S^{n+1} = 1/3 S^0 + 2/3 (S^2 + dt L(S2)),  S^ = (U, Lim(S))
+    // (each stage's fold writes a buffer its adjoint kernel does not read: fused)
     st = RunAdj::run<T, PHYS, DIM>(p, S2, lam, 2.0 / 3.0, tape + 6,
                                    lim ? (const T*)lam + mN : nullptr, 2.0 / 3.0, tape + 4, ws,
-                                   fold_args<T>(Y2, 0, lam, 2.0 / 3.0, ida), s);
+                                   fold_args<T>(Y2, 0, lam, 2.0 / 3.0, ida), true, s);
     if (st) return st;
     // stage 2: S2 = 3/4 S^0 + 1/4 (S^1 + dt L(S1));  L0 = lam/3 + 3/4 Y2 + Y1
     FoldArgs<T> f2 = fold_args<T>(Y1, 0, Y2, 0.25, ida);
@@ -1464,11 +1553,11 @@ struct RunStepAdj {
     f2.ca = 1.0 / 3.0;
     f2.cb = 0.75;
     st = RunAdj::run<T, PHYS, DIM>(p, S1, Y2, 0.25, tape + 6, lim ? Y2 + mN : nullptr, 0.25,
-                                   tape + 2, ws, f2, s);
+                                   tape + 2, ws, f2, true, s);
     if (st) return st;
     // stage 1: S1 = S^0 + dt L(S0); the base S^0 collects L0
     return RunAdj::run<T, PHYS, DIM>(p, state0, Y1, 1.0, tape + 6, lim ? L0 + mN : nullptr, 1.0,
-                                     tape + 0, ws, fold_args<T>(lam, 0, L0, 1.0, ida), s);
+                                     tape + 0, ws, fold_args<T>(lam, 0, L0, 1.0, ida), true, s);
   }
 };
 
