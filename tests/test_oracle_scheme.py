@@ -14,6 +14,7 @@ import pytest
 import torch
 
 import hweno_inputs as hi
+from tests import exact_solutions as ex
 from oracle import hweno_ref as o
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -298,14 +299,6 @@ def test_table2_euler1d_density_wave():
     assert min(_orders([e[0] for e in errs])) > 4.8
 
 
-def _burgers_exact(x, t):
-    u = 0.5 + np.sin(np.pi * x)
-    for _ in range(60):
-        g = u - (0.5 + np.sin(np.pi * (x - u * t)))
-        u = u - g / (1 + np.pi * np.cos(np.pi * (x - u * t)) * t)
-    return u
-
-
 def test_table1_burgers1d():
     """Example 3.1, Table 1 (L-HWENO columns), N = 10..80."""
     table = _load_table("table1_burgers1d.txt")
@@ -315,7 +308,7 @@ def test_table1_burgers1d():
         w = hi.scalar_sine_1d(n, "burgers")
         prob = _prob(w)
         S, _ = o.run(_S(w), prob, T, _accuracy_dt(prob))
-        e = np.abs(S[0, 0].numpy() - _burgers_exact(hi.centers(n, 0.0, 2.0), T))
+        e = np.abs(S[0, 0].numpy() - ex.burgers_1d(hi.centers(n, 0.0, 2.0), T))
         errs.append((e.mean(), e.max()))
     _check_against_table(table, errs[1:], ns[1:], 0.4, 2.5)
     _check_against_table(table, errs[2:], ns[2:], 0.8, 1.25)
