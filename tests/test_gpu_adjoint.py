@@ -111,12 +111,23 @@ def test_rhs_adjoint_fp32():
     assert rel_err(got, ref) < 2e-4
 
 
+# tiny 2D grids: the step adjoint folds only the two-cell boundary bands in a
+# separate pass; at nx or ny = 4 the bands cover the whole grid
+TINY = {
+    "euler2d_rough_periodic_4x4": lambda: hi.euler2d_rough(4, 4, 12, bc=hi.PERIODIC),
+    "euler2d_rough_outflow_5x4": lambda: hi.euler2d_rough(5, 4, 13),
+    "euler2d_rough_periodic_4x7": lambda: hi.euler2d_rough(4, 7, 14, bc=hi.PERIODIC),
+    "euler2d_rough_outflow_6x5": lambda: hi.euler2d_rough(6, 5, 15),
+    "burgers2d_sine_5x6": lambda: hi.scalar_sine_2d(5, 6, "burgers"),
+}
+
+
 @pytest.mark.parametrize("limiter_on", [True, False], ids=["lim", "nolim"])
 @pytest.mark.parametrize("case", ["euler2d_rough_outflow_33x21", "euler2d_rsmooth_32x32",
                                   "euler1d_piecewise_301", "burgers2d_sine_19x23",
-                                  "linadv1d_random_270"])
+                                  "linadv1d_random_270"] + sorted(TINY))
 def test_step_adjoint_matches_oracle_autograd(case, limiter_on):
-    w = CASES[case]()
+    w = (CASES.get(case) or TINY[case])()
     announce("step adjoint", case, limiter_on)
     Sg = P.to_gpu(w, torch.float64)
     S0 = Sg.clone()
