@@ -43,8 +43,8 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # kernel sources it was measured on (stale entries are reported as null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("2e0e1af611ef4cd5", "f64", 4096): 5.0832e+09,
-    ("2e0e1af611ef4cd5", "f32", 4096): 2.5421e+09,
+    ("369c34169397c713", "f64", 4096): 5.0828e+09,
+    ("369c34169397c713", "f32", 4096): 2.5420e+09,
 }
 
 
