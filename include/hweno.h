@@ -169,7 +169,8 @@ size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob);
  * boundary index maps (periodic wrap, outflow copy).
  * alpha: device double[2], the speeds of the forward evaluation (replayed).
  * lam_rhs: nf fields; lam_lim: m * dim fields (limited-derivative layout of
- * hweno_limit) or NULL; lam_state: nf fields, accumulated into.
+ * hweno_limit) or NULL; lam_state: nf fields, accumulated into.  lam_state
+ * may overlap lam_rhs or lam_lim (the result is folded in a separate pass).
  * ws: device workspace of >= hweno_adjoint_workspace_bytes(prob) bytes. */
 hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
                                const double* alpha, const void* lam_rhs,
@@ -182,7 +183,9 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
  * state0: S^n, the step's input; step_ws: the workspace of a forward step
  * from state0 taken with that tape (it holds the stage states S1, S2 until
  * the next step on it); tape: device double[HWENO_CTRL_LEN] (as written by
- * hweno_rk3_step); ws: >= hweno_adjoint_workspace_bytes(prob) bytes. */
+ * hweno_rk3_step); ws: >= hweno_adjoint_workspace_bytes(prob) bytes.
+ * lam, state0, step_ws and ws must not overlap (2D grids finish most cells
+ * of each stage's adjoint in the kernel that reads the stage's inputs). */
 hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state0,
                                     const void* step_ws, size_t step_ws_bytes,
                                     const double* tape, void* lam, void* ws,

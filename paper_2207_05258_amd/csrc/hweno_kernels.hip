@@ -1722,6 +1722,18 @@ hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state
                 adj_layout(prob).total);
   if (((uintptr_t)ws & 255u) != 0 || ((uintptr_t)step_ws & 255u) != 0)
     return fail(HWENO_ERR_WORKSPACE, "workspaces must be 256-byte aligned");
+  {
+    // the stage adjoints read state0 / step_ws / lam while writing lam and ws
+    const size_t sb = (size_t)cells_of(prob) * elem_size(prob) * n_fields(prob);
+    auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
+      const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+      return x < y + nb && y < x + na;
+    };
+    if (overlap(lam, sb, state0, sb) || overlap(lam, sb, step_ws, step_ws_bytes) ||
+        overlap(lam, sb, ws, ws_bytes) || overlap(ws, ws_bytes, state0, sb) ||
+        overlap(ws, ws_bytes, step_ws, step_ws_bytes))
+      return fail(HWENO_ERR_INVALID_ARG, "lam, state0, step_ws and ws must not overlap");
+  }
   st = dispatch<RunStepAdj>(prob, state0, step_ws, tape, lam, ws, (hipStream_t)stream);
   if (st) return st;
   return ok();

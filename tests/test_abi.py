@@ -108,6 +108,33 @@ def test_null_pointers_and_small_workspace_are_rejected_on_host():
                             float("inf"), 0.0, None, None, None) == 1
 
 
+def test_step_adjoint_rejects_overlapping_buffers_on_host():
+    """The step adjoint writes lam and its workspace while reading state0 and the
+    forward step's workspace: overlapping ranges are refused before any HIP call
+    (the addresses below are never dereferenced)."""
+    L = _lib_or_skip()
+    c = _prob().c()
+    P = ctypes.byref(c)
+    swb = L.hweno_workspace_bytes(P)
+    awb = L.hweno_adjoint_workspace_bytes(P)
+    state_bytes = 64 * 48 * 12 * 8
+    base = 1 << 40
+    state0, step_ws = base, base + (1 << 34)
+    ws, lam = base + (2 << 34), base + (3 << 34)
+    tape = base + (4 << 34)
+    vp = ctypes.c_void_p
+
+    def call(lam_, ws_):
+        return L.hweno_rk3_step_adjoint(P, vp(state0), vp(step_ws), swb, vp(tape), vp(lam_),
+                                        vp(ws_), awb, None)
+
+    assert call(state0, ws) == 1                     # lam is state0
+    assert "overlap" in L.hweno_last_error().decode()
+    assert call(step_ws + 256, ws) == 1              # lam inside the step workspace
+    assert call(lam, lam + 256 * ((state_bytes // 2) // 256)) == 1   # ws inside lam
+    assert call(lam, step_ws) == 1                   # ws is the step workspace
+
+
 def test_empty_grid_is_a_noop_without_device_calls():
     L = _lib_or_skip()
     for kw in (dict(nx=0), dict(ny=0), dict(dim=1, nx=0, ny=1)):
