@@ -189,14 +189,14 @@ def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 20, dtype_name: str 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--dtype", choices=["f64", "f32"], default="f64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the secondary run in the other precision")
-    ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--cpu-n", type=int, default=2048)
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
     ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
