@@ -43,17 +43,28 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # kernel sources it was measured on (stale entries are reported as null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("369c34169397c713", "f64", 4096): 5.0828e+09,
-    ("369c34169397c713", "f32", 4096): 2.5420e+09,
+    ("d71891ebd22a083a", "f64", 4096): 5.0828e+09,
+    ("d71891ebd22a083a", "f32", 4096): 2.5420e+09,
 }
 
 
 def kernel_sha() -> str:
-    hsh = hashlib.sha256()
-    for f in ("paper_2207_05258_amd/csrc/hweno_kernels.hip", "paper_2207_05258_amd/csrc/hweno_math.h"):
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            hsh.update(fh.read())
-    return hsh.hexdigest()[:16]
+    """sha256[:16] of the device code embedded in the built library (its .hip_fatbin
+    section): it changes with the kernels, not with host-side code, so a traffic
+    figure measured for one build stays attached to exactly that device code."""
+    import struct
+    from paper_2207_05258_amd import hweno as hw
+    with open(hw.LIB_PATH, "rb") as fh:
+        b = fh.read()
+    shoff = struct.unpack_from("<Q", b, 0x28)[0]
+    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
+    secs = [struct.unpack_from("<IIQQQQ", b, shoff + i * shentsize) for i in range(shnum)]
+    names = secs[shstrndx]
+    strtab = b[names[4]:names[4] + names[5]]
+    for name, _typ, _flags, _addr, off, size in secs:
+        if strtab[name:strtab.index(b"\0", name)] == b".hip_fatbin":
+            return hashlib.sha256(b[off:off + size]).hexdigest()[:16]
+    return "unknown"
 
 
 def cpu_baseline(n: int = 1024):

@@ -1723,7 +1723,7 @@ hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state
   if (((uintptr_t)ws & 255u) != 0 || ((uintptr_t)step_ws & 255u) != 0)
     return fail(HWENO_ERR_WORKSPACE, "workspaces must be 256-byte aligned");
   {
-    // the stage adjoints read state0 / step_ws / lam while writing lam and ws
+    // the stage adjoints read state0, step_ws and lam while writing lam and ws
     const size_t sb = (size_t)cells_of(prob) * elem_size(prob) * n_fields(prob);
     auto overlap = [](const void* a, size_t na, const void* b, size_t nb) {
       const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
