@@ -26,6 +26,7 @@ GAMMA_GAS = 1.4
 
 PERIODIC = 0
 OUTFLOW = 1
+REFLECT = 2
 
 
 @dataclass
@@ -168,6 +169,49 @@ def euler1d_piecewise(n: int, seed: int, lo=0.0, hi=2.0) -> Workload:
     return Workload(S, 1, "euler", (hi - lo) / n, 1.0, PERIODIC, PERIODIC,
                     (lo, 0.0), (hi, 1.0), name=f"euler1d_piecewise_{n}_s{seed}",
                     info={"jumps": k})
+
+
+def _riemann_1d(n, lo, hi, cuts, states, bc, name):
+    """Piecewise-constant (rho, u, p) states separated at ``cuts``; zero derivatives."""
+    x = centers(n, lo, hi)
+    piece = np.searchsorted(np.asarray(cuts), x)
+    st = np.asarray(states, dtype=np.float64)
+    U = conserved_1d(st[piece, 0], st[piece, 1], st[piece, 2])
+    S = np.concatenate([U, np.zeros_like(U)])[:, None, :]
+    return Workload(S, 1, "euler", (hi - lo) / n, 1.0, bc, bc, (lo, 0.0), (hi, 1.0), name=name)
+
+
+def lax_1d(n: int) -> Workload:
+    """Lax shock tube (Example 3.5): (0.445, 0.698, 3.528) for x < 0, (0.5, 0, 0.571)
+    for x > 0 on [-0.5, 0.5] with outflow boundaries; the paper runs it to T = 0.16."""
+    return _riemann_1d(n, -0.5, 0.5, [0.0], [(0.445, 0.698, 3.528), (0.5, 0.0, 0.571)],
+                       OUTFLOW, f"lax_{n}")
+
+
+def blast_waves_1d(n: int) -> Workload:
+    """Two interacting blast waves (Example 3.7): rho = 1, u = 0, p = 1000 / 0.01 / 100
+    on (0, 0.1) / (0.1, 0.9) / (0.9, 1), reflecting walls at both ends; T = 0.038."""
+    return _riemann_1d(n, 0.0, 1.0, [0.1, 0.9], [(1.0, 0.0, 1e3), (1.0, 0.0, 1e-2), (1.0, 0.0, 1e2)],
+                       REFLECT, f"blast_waves_{n}")
+
+
+def shu_osher_1d(n: int) -> Workload:
+    """Shock / entropy-wave interaction (Example 3.6): (3.857143, 2.629369, 10.333333)
+    for x < -4, (1 + 0.2 sin 5x, 0, 1) for x >= -4, on [-5, 5] with outflow
+    boundaries; T = 1.8.  Derivatives: those of the smooth piece, zero elsewhere."""
+    lo, hi = -5.0, 5.0
+    x = centers(n, lo, hi)
+    left = x < -4.0
+    rho = np.where(left, 3.857143, 1.0 + 0.2 * np.sin(5.0 * x))
+    u = np.where(left, 2.629369, 0.0)
+    p = np.where(left, 10.333333, 1.0)
+    U = conserved_1d(rho, u, p)
+    # right piece: u = 0, p = 1, so m_x = E_x = 0 and only rho_x = cos(5x) is nonzero
+    D = np.zeros_like(U)
+    D[0] = np.where(left, 0.0, np.cos(5.0 * x))
+    S = np.concatenate([U, D])[:, None, :]
+    return Workload(S, 1, "euler", (hi - lo) / n, 1.0, OUTFLOW, OUTFLOW, (lo, 0.0), (hi, 1.0),
+                    name=f"shu_osher_{n}")
 
 
 # ---------------------------------------------------------------------------

@@ -44,6 +44,7 @@ DTYPE = torch.float64
 
 PERIODIC = 0
 OUTFLOW = 1
+REFLECT = 2   # solid wall: mirror image, wall-normal momentum and normal derivatives odd
 
 
 @dataclass
@@ -346,14 +347,38 @@ def physics_of(prob: Problem):
 # Grid helpers
 # ===========================================================================
 
-def _pad(A, axis, bc, width=2):
-    """Ghost cells along ``axis``: periodic wrap or copy of the nearest interior value."""
+def _pad(A, axis, bc, width=2, parity=None):
+    """Ghost cells along ``axis`` of A = [components, ny, nx]: periodic wrap, copy
+    of the nearest interior value, or (REFLECT) the mirror image across the wall,
+    ghost k taking interior cell k (k = 1, 2 counted from the wall) times the
+    component's parity (+1 even, -1 odd) under the reflection."""
     n = A.shape[axis]
+    k = torch.arange(-width, n + width)
     if bc == PERIODIC:
-        idx = torch.arange(-width, n + width) % n
-    else:
-        idx = torch.clamp(torch.arange(-width, n + width), 0, n - 1)
-    return A.index_select(axis, idx)
+        return A.index_select(axis, k % n)
+    if bc == OUTFLOW:
+        return A.index_select(axis, torch.clamp(k, 0, n - 1))
+    if n < width:
+        raise ValueError("a reflecting wall needs at least as many cells as ghost cells")
+    mirror = torch.where(k < 0, -1 - k, torch.where(k >= n, 2 * n - 1 - k, k))
+    out = A.index_select(axis, mirror)
+    ghost = ((k < 0) | (k >= n)).to(A.dtype)
+    shape = [1] * A.dim()
+    shape[axis] = k.numel()
+    p = torch.as_tensor(parity, dtype=A.dtype).view([-1] + [1] * (A.dim() - 1))
+    # interior points keep their values; ghosts are multiplied by the parity
+    return out * (1 - ghost.view(shape) + ghost.view(shape) * p)
+
+
+def _parities(prob, d):
+    """Parities of (U, derivative along d, derivative across d) under reflection
+    across a wall normal to direction d: the momentum component normal to the
+    wall is odd, a derivative along d flips the parity of its component."""
+    if prob.physics != "euler":
+        raise ValueError("reflecting walls are defined for the Euler equations only")
+    pu = [1.0] * prob.m
+    pu[1 + d] = -1.0
+    return pu, [-q for q in pu], pu
 
 
 def _split(S, prob):
@@ -388,8 +413,9 @@ def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
     bc = prob.bc_x if d == 0 else prob.bc_y
     dd = prob.dx if d == 0 else prob.dy
     n = U.shape[axis]
-    Up = _pad(U, axis, bc).movedim(0, -1)
-    Dnp = _pad(Dn, axis, bc).movedim(0, -1)
+    pu, pn, pt = _parities(prob, d) if bc == REFLECT else (None, None, None)
+    Up = _pad(U, axis, bc, parity=pu).movedim(0, -1)
+    Dnp = _pad(Dn, axis, bc, parity=pn).movedim(0, -1)
     cax = axis - 1   # grid axis once the component axis has moved last
 
     def at(A, k):    # stencil point i-1+k of the interfaces i+1/2, i = -1..n-1
@@ -431,7 +457,7 @@ def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
 
     mixed = None
     if Dt is not None:
-        Dtp = _pad(Dt, axis, bc).movedim(0, -1)
+        Dtp = _pad(Dt, axis, bc, parity=pt).movedim(0, -1)
         AT = phys.jvp(Up, Dtp, d)
         # eq. (mixed): central four-point value, no splitting
         mixed = (-at(AT, 0) + 7.0 * at(AT, 1) + 7.0 * at(AT, 2) - at(AT, 3)) / 12.0
@@ -469,8 +495,9 @@ def limited_derivatives(S, prob: Problem):
 
     def along(D, axis, bc, h):
         n = U.shape[axis]
-        Up = _pad(U, axis, bc, 1)
-        Dp = _pad(D, axis, bc, 1)
+        pu, pn, _ = _parities(prob, 0 if axis == 2 else 1) if bc == REFLECT else (None, None, None)
+        Up = _pad(U, axis, bc, 1, parity=pu)
+        Dp = _pad(D, axis, bc, 1, parity=pn)
         return limit_derivative(Up.narrow(axis, 0, n), Up.narrow(axis, 1, n),
                                 Up.narrow(axis, 2, n), Dp.narrow(axis, 0, n),
                                 Dp.narrow(axis, 2, n), h, d, eps, lin)

@@ -6,6 +6,7 @@ Jacobian, invariants (constant states, conservation, reflection and
 transposition symmetry, 1D/2D reduction), fifth-order truncation error on
 smooth data, and the L-HWENO error tables printed in Section 3.
 """
+import dataclasses
 import math
 import os
 
@@ -353,3 +354,147 @@ def test_linear_advection_sits_on_rk3_floor():
     amp = G(dt) ** full * (G(last) if last > 1e-12 else 1.0)
     floor = abs(amp - np.exp(-1j * np.pi * 2.0))
     assert 0.9 < err / floor < 1.1, (err, floor)
+
+
+# ---------------------------------------------------------------------------
+# reflective walls
+# ---------------------------------------------------------------------------
+
+def _mirror_double(S, prob, axis, d):
+    """The state on the domain doubled across its low wall along grid ``axis``
+    (direction d): the mirror image, fields multiplied by their reflection
+    parity (wall-normal momentum odd, derivative along d odd, parities
+    multiply), followed by the original."""
+    m = prob.m
+    par = torch.ones(S.shape[0], dtype=S.dtype)
+    for f in range(S.shape[0]):
+        c, g = f % m, f // m
+        sgn = -1.0 if (prob.physics == "euler" and c == 1 + d) else 1.0
+        if g == 1 + d:
+            sgn = -sgn
+        par[f] = sgn
+    mir = S.flip(axis) * par.view(-1, *([1] * (S.dim() - 1)))
+    return torch.cat([mir, S], dim=axis)
+
+
+REFLECT_CASES = {
+    "euler1d_x": (lambda: hi.euler1d_piecewise(37, 3), 0),
+    "euler2d_x": (lambda: hi.euler2d_rough(19, 14, 4), 0),
+    "euler2d_y": (lambda: hi.euler2d_rough(13, 21, 5), 1),
+}
+
+
+@pytest.mark.parametrize("case", sorted(REFLECT_CASES))
+def test_reflective_wall_equals_mirror_doubled_periodic_domain(case):
+    """A reflective wall is the symmetry plane of the mirror-doubled periodic
+    problem: RHS, limiter and one RK3 step on [0, L] with walls at both ends
+    equal the periodic computation on [-L, L] restricted to [0, L]."""
+    make, d = REFLECT_CASES[case]
+    w = make()
+    axis = 2 if d == 0 else 1
+    kw = dict(bc_x=o.REFLECT) if d == 0 else dict(bc_y=o.REFLECT)
+    kw2 = dict(bc_x=o.PERIODIC) if d == 0 else dict(bc_y=o.PERIODIC)
+    pr = dataclasses.replace(_prob(w), **kw)
+    pd = dataclasses.replace(_prob(w), **kw2)
+    S = _S(w)
+    Sd = _mirror_double(S, pr, axis, d)
+    n = S.shape[axis]
+    assert o.max_speeds(S, pr) == o.max_speeds(Sd, pd)
+
+    def half(A):
+        return A.narrow(axis, n, n)
+
+    scale = float(S.abs().max())
+    for got, ref in ((o.rhs(S, pr), half(o.rhs(Sd, pd))),
+                     (o.limited_derivatives(S, pr), half(o.limited_derivatives(Sd, pd))),
+                     (o.rk3_step(S, pr)[0], half(o.rk3_step(Sd, pd)[0]))):
+        assert float((got - ref).abs().max()) <= 1e-13 * max(scale, float(ref.abs().max())), case
+
+
+def test_reflective_wall_is_refused_for_scalar_laws():
+    w = hi.scalar_random_2d(9, 8, 6, "burgers")
+    with pytest.raises(ValueError):
+        o.rhs(_S(w), dataclasses.replace(_prob(w), bc_x=o.REFLECT))
+
+
+def test_reflective_wall_conserves_mass_and_energy():
+    """Walls exchange no mass or energy: sum(rho) and sum(E) are constant over a
+    step with reflecting walls on both sides (momentum is not: the wall pushes)."""
+    w = hi.euler2d_rough(16, 12, 7)
+    pr = dataclasses.replace(_prob(w), bc_x=o.REFLECT, bc_y=o.REFLECT)
+    S = _S(w)
+    S1, _, _ = o.rk3_step(S, pr)
+    for c in (0, 3):
+        a, b = float(S[c].sum()), float(S1[c].sum())
+        assert abs(a - b) <= 1e-12 * abs(a), (c, a, b)
+
+
+# ---------------------------------------------------------------------------
+# the paper's discontinuous 1D problems (Examples 3.5-3.7)
+# ---------------------------------------------------------------------------
+
+LAX_L, LAX_R = (0.445, 0.698, 3.528), (0.5, 0.0, 0.571)
+
+
+def test_exact_riemann_solver_reproduces_sod_star_state_and_conserves():
+    """The exact solver used as reference: Sod's problem has the well-known star state
+    p* = 0.30313, u* = 0.92745; and the integral of U over [-1, 1] grows by
+    t (F(W_L) - F(W_R)) while no wave has reached the ends (midpoint-rule error only)."""
+    W = ex.riemann_euler((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), np.array([0.5]))
+    assert abs(W[2, 0] - 0.30313) < 1e-5 and abs(W[1, 0] - 0.92745) < 1e-5
+    g, t = 1.4, 0.16
+
+    def U(w):
+        r, u, p = w
+        return np.array([r, r * u, p / (g - 1) + 0.5 * r * u * u])
+
+    def F(w):
+        r, u, p = w
+        return np.array([r * u, r * u * u + p, u * (U(w)[2] + p)])
+
+    A = ex.riemann_cell_averages(LAX_L, LAX_R, 0.0, -1.0, 1.0, 400, t, sub=256)
+    want = U(LAX_L) + U(LAX_R) + t * (F(LAX_L) - F(LAX_R))
+    # midpoint error at each jump is at most jump x sub-cell width (~6e-5 here)
+    assert np.abs(A.sum(axis=1) * 2.0 / 400 - want).max() < 2e-4
+
+
+def test_lax_shock_tube_converges_to_exact_riemann_solution():
+    """Example 3.5 to T = 0.16 against the exact Riemann solution (cell averages): the
+    density L1 error is small and falls with refinement at the first-order rate that
+    a solution with a contact and a shock allows."""
+    err = {}
+    for n in (200, 400):
+        w = hi.lax_1d(n)
+        S, _ = o.run(_S(w), _prob(w), 0.16)
+        ref = ex.riemann_cell_averages(LAX_L, LAX_R, 0.0, -0.5, 0.5, n, 0.16)
+        err[n] = float(np.abs(S[0, 0].numpy() - ref[0]).mean())
+    assert err[200] < 1.2e-2, err
+    assert err[400] < 0.6 * err[200], err
+
+
+def test_shu_osher_shock_moves_at_rankine_hugoniot_speed():
+    """Example 3.6: the left state is the post-shock state of a Mach 3 shock running into
+    (rho, u, p) = (1, 0, 1), so the shock leaves x = -4 at speed 3 sqrt(gamma); the
+    entropy wave ahead of it only perturbs the density, so at T = 1.8 the steepest
+    density drop sits within two cells of -4 + 5.4 sqrt(1.4)."""
+    w = hi.shu_osher_1d(400)
+    S, _ = o.run(_S(w), _prob(w), 1.8)
+    x = hi.centers(w.nx, w.lo[0], w.hi[0])
+    rho = S[0, 0].numpy()
+    j = int(np.argmin(np.diff(rho)))
+    shock = 0.5 * (x[j] + x[j + 1])
+    assert abs(shock - (-4.0 + 5.4 * math.sqrt(1.4))) < 2 * w.dx, shock
+    assert rho.min() > 0.79 and rho.max() < 4.6
+
+
+def test_blast_waves_conserve_mass_and_energy_between_walls():
+    """Example 3.7 to T = 0.038 with reflecting walls: total mass and energy stay at their
+    initial values (1 and 275.02) and density and pressure stay positive through the
+    collision of the two blast waves."""
+    w = hi.blast_waves_1d(200)
+    S, _ = o.run(_S(w), _prob(w), 0.038)
+    rho, m, E = (S[c, 0].numpy() for c in range(3))
+    p = (w.gamma_gas - 1.0) * (E - 0.5 * m * m / rho)
+    assert abs(rho.sum() * w.dx - 1.0) < 1e-12
+    assert abs(E.sum() * w.dx - 275.02) < 1e-10
+    assert rho.min() > 0 and p.min() > 0
