@@ -65,6 +65,9 @@ class Problem:
     cfl: float = 0.6
     characteristic: bool = True
     limiter_on: bool = True
+    # Euler only: apply the limiter to local characteristic fields of each cell
+    # instead of component by component (a variant; the paper does not say)
+    limiter_characteristic: bool = False
     # test-only switches: force the nonlinear weights to the linear ones
     linear_recon: bool = False
     linear_limiter: bool = False
@@ -493,14 +496,30 @@ def limited_derivatives(S, prob: Problem):
     U, V, W = _split(S, prob)
     d, eps, lin = prob.lim_w, prob.eps, prob.linear_limiter
 
+    char = prob.limiter_characteristic and prob.physics == "euler"
+    phys = physics_of(prob) if char else None
+
     def along(D, axis, bc, h):
         n = U.shape[axis]
-        pu, pn, _ = _parities(prob, 0 if axis == 2 else 1) if bc == REFLECT else (None, None, None)
+        dr = 0 if axis == 2 else 1
+        pu, pn, _ = _parities(prob, dr) if bc == REFLECT else (None, None, None)
         Up = _pad(U, axis, bc, 1, parity=pu)
         Dp = _pad(D, axis, bc, 1, parity=pn)
-        return limit_derivative(Up.narrow(axis, 0, n), Up.narrow(axis, 1, n),
-                                Up.narrow(axis, 2, n), Dp.narrow(axis, 0, n),
-                                Dp.narrow(axis, 2, n), h, d, eps, lin)
+        um, u0, up = (Up.narrow(axis, k, n) for k in range(3))
+        vm, vp = Dp.narrow(axis, 0, n), Dp.narrow(axis, 2, n)
+        if not char:
+            return limit_derivative(um, u0, up, vm, vp, h, d, eps, lin)
+        # characteristic variant: every stencil value is projected with the left
+        # eigenvectors of dF_d/dU at the cell's own state, the scalar limiter acts
+        # on each characteristic field, and the right eigenvectors map back
+        R = phys.right_eigenvectors(u0.movedim(0, -1), u0.movedim(0, -1), dr)
+        Li = torch.linalg.inv(R)
+
+        def proj(A):
+            return (Li @ A.movedim(0, -1).unsqueeze(-1)).squeeze(-1).movedim(-1, 0)
+
+        z = limit_derivative(proj(um), proj(u0), proj(up), proj(vm), proj(vp), h, d, eps, lin)
+        return (R @ z.movedim(0, -1).unsqueeze(-1)).squeeze(-1).movedim(-1, 0)
 
     out = [along(V, 2, prob.bc_x, prob.dx)]
     if prob.dim == 2:

@@ -213,6 +213,56 @@ def test_characteristic_equals_componentwise_with_linear_weights():
     assert not torch.allclose(o.rhs(S, _prob(w)), o.rhs(S, pc), rtol=1e-6)
 
 
+@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.REFLECT])
+def test_characteristic_limiter_equals_componentwise_with_linear_weights(bc):
+    """With the limiter's weights forced to d the limiter is linear in (U, U_x), so the
+    projection L and the map back R = L^-1 cancel (both directions of a 2D grid)."""
+    w = hi.euler2d_rough(10, 8, 12, bc=hi.PERIODIC)
+    S = _S(w)
+
+    def pr(**kw):
+        return dataclasses.replace(_prob(w, **kw), bc_x=bc, bc_y=bc)
+
+    a = o.limited_derivatives(S, pr(linear_limiter=True, limiter_characteristic=True))
+    b = o.limited_derivatives(S, pr(linear_limiter=True))
+    assert torch.allclose(a, b, rtol=1e-11, atol=1e-9 * float(b.abs().max()))
+    # the nonlinear weights do see the projection
+    assert not torch.allclose(o.limited_derivatives(S, pr(limiter_characteristic=True)),
+                              o.limited_derivatives(S, pr()), rtol=1e-6)
+
+
+@pytest.mark.parametrize("dim,d,k", [(1, 0, 0), (1, 0, 2), (2, 0, 1), (2, 1, 3), (2, 1, 0)])
+def test_characteristic_limiter_reduces_to_scalar_along_one_eigenvector(dim, d, k):
+    """Neighbours that differ from the middle cell's state only along its k-th right
+    eigenvector r_k (values and derivatives) form one scalar characteristic field: the
+    middle cell's limited derivative is r_k times the scalar limiter of those amplitudes."""
+    g = torch.Generator().manual_seed(10 * dim + k)
+    m = 3 if dim == 1 else 4
+    ub = torch.tensor([1.2, 0.3, -0.2, 2.9] if m == 4 else [1.2, 0.3, 2.9], dtype=torch.float64)
+    pr = o.Problem(dim=dim, physics="euler", dx=0.1, dy=0.07, bc_x=o.OUTFLOW, bc_y=o.OUTFLOW,
+                   limiter_characteristic=True)
+    rk = o.Euler(pr).right_eigenvectors(ub, ub, d)[:, k]
+    s_m, s_p, v_m, v_0, v_p = (0.01 * torch.randn((), generator=g, dtype=torch.float64)
+                               for _ in range(5))
+    amp, vel = (s_m, 0.0 * s_m, s_p), (v_m, v_0, v_p)
+    # three cells along direction d, one across it
+    S = torch.zeros(m * (1 + dim), 3 if d == 1 else 1, 1 if d == 1 else 3, dtype=torch.float64)
+    line = S[:, :, 0] if d == 1 else S[:, 0, :]
+    for q in range(3):
+        line[:m, q] = ub + amp[q] * rk
+        line[m * (1 + d):m * (2 + d), q] = vel[q] * rk
+    out = o.limited_derivatives(S, pr)
+    got = (out[:, :, 0] if d == 1 else out[:, 0, :])[m * d:m * (d + 1), 1]
+    h = pr.dy if d == 1 else pr.dx
+    want = o.limit_derivative(s_m, 0.0 * s_m, s_p, v_m, v_p, h, pr.lim_w, pr.eps) * rk
+    assert torch.allclose(got, want, rtol=1e-10, atol=1e-15), (got, want)
+    # a component-wise limiter does not keep the data on r_k in general
+    pc = dataclasses.replace(pr, limiter_characteristic=False)
+    comp = o.limited_derivatives(S, pc)
+    comp = (comp[:, :, 0] if d == 1 else comp[:, 0, :])[m * d:m * (d + 1), 1]
+    assert not torch.allclose(comp, want, rtol=1e-6, atol=0.0)
+
+
 def test_limiter_off_is_plain_rk3():
     w = hi.euler1d_piecewise(30, 1)
     prob = _prob(w, limiter_on=False)
