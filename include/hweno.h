@@ -49,7 +49,7 @@ typedef enum {
 
 typedef enum { HWENO_F32 = 0, HWENO_F64 = 1 } hweno_dtype;
 typedef enum { HWENO_LINADV = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_physics;
-typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1 } hweno_bc;
+typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1, HWENO_BC_REFLECT = 2 } hweno_bc;
 
 /* Problem description (host memory, read during the call only).
  *  dim            1 or 2.
@@ -58,13 +58,28 @@ typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1 } hweno_bc;
  *                 f = a_x u, g = a_y u (LINADV), f = g = u^2/2 (BURGERS), or
  *                 the Euler equations with E = p/(gamma-1) + rho|vel|^2/2.
  *  dtype          hweno_dtype of every array (FP32 or FP64).
- *  bc_x, bc_y     hweno_bc: periodic wrap, or outflow = copy of the nearest
- *                 interior value of every field into the two ghost cells.
+ *  bc_x, bc_y     hweno_bc: periodic wrap; outflow = copy of the nearest
+ *                 interior value of every field into the two ghost cells;
+ *                 reflect = solid wall: ghost k mirrors interior cell k
+ *                 (k = 1, 2 from the wall) with the wall-normal momentum and
+ *                 every derivative across the wall negated (signs multiply:
+ *                 the normal derivative of the normal momentum is kept).
+ *                 Euler only (HWENO_ERR_UNSUPPORTED for scalar laws, which
+ *                 have no mirror symmetry with the same flux); at least 2
+ *                 cells across the wall's direction.
  *  characteristic Euler only: 1 = nonlinear flux reconstruction in local
  *                 characteristic fields (Remarks 2.1/2.2; Roe average),
  *                 0 = component by component.  Ignored for scalars.
  *  limiter_on     1 = HWENO limiter on the derivatives in the time update
  *                 (Section 2.2), 0 = no limiter (ablation of Table 5).
+ *  limiter_characteristic
+ *                 Euler only, 0 or 1: 0 = the limiter acts component by
+ *                 component on the conserved variables; 1 = a variant (the
+ *                 paper does not say how its limiter treats systems): the
+ *                 stencil of each cell is projected on the characteristic
+ *                 fields of the cell's own state, limited field by field and
+ *                 mapped back.  The adjoint entry points return
+ *                 HWENO_ERR_UNSUPPORTED for it.  Ignored for scalars.
  *  dx, dy         cell sizes (> 0; dy ignored in 1D).
  *  gamma_gas      ratio of specific heats (> 1; Euler only).
  *  adv_speed      (a_x, a_y) for LINADV.
@@ -77,7 +92,7 @@ typedef struct {
   int32_t dim, nx, ny;
   int32_t physics, dtype, bc_x, bc_y;
   int32_t characteristic, limiter_on;
-  int32_t reserved;
+  int32_t limiter_characteristic;
   double dx, dy;
   double gamma_gas;
   double adv_speed[2];

@@ -4,6 +4,7 @@ Zhang & Zhao, "A fifth-order finite difference HWENO scheme combined with
 limiter for hyperbolic conservation laws" (arXiv 2207.05258).
 """
 from .hweno import (BatchedStepper, Rollout, adjoint_workspace, autotune_batched, rhs_adjoint,
-                    rollout_replay, step_adjoint, CTRL_LEN, OUTFLOW, PERIODIC, HwenoError, Problem, Stepper,  # noqa: F401
+                    rollout_bytes_kept,
+                    rollout_replay, step_adjoint, CTRL_LEN, OUTFLOW, PERIODIC, REFLECT, HwenoError, Problem, Stepper,  # noqa: F401
                     alpha, lib, limit, problem_for, rhs, rk3_step_, timing_begin, timing_end, validate,
                     workspace_bytes)

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -55,7 +56,43 @@ __device__ __forceinline__ int map_index(int i, int n, int bc) {
     i %= n;
     return i < 0 ? i + n : i;
   }
+  if (bc == HWENO_BC_REFLECT) {
+    // mirror images repeat with period 2n; reducing first keeps every index
+    // in range (halo loads deeper than n are never used in a result)
+    i %= 2 * n;
+    if (i < 0) i += 2 * n;
+    return i < n ? i : 2 * n - 1 - i;
+  }
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// map_index for the stage kernels, whose results use halos at most 2 deep: a
+// reflecting wall has n >= 2 cells across, so one mirror step is exact for
+// -2 <= i <= n + 1.  A partial tile also stages cells further out that no
+// result uses; the clamp keeps those loads inside the grid.
+__device__ __forceinline__ int map_index2(int i, int n, int bc) {
+  if (bc == HWENO_BC_PERIODIC) {
+    i %= n;
+    return i < 0 ? i + n : i;
+  }
+  if (bc == HWENO_BC_REFLECT) i = i < 0 ? -1 - i : (i >= n ? 2 * n - 1 - i : i);
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// true when index i is a ghost that a reflecting boundary fills with signs
+__device__ __forceinline__ bool mirrored(int i, int n, int bc) {
+  return bc == HWENO_BC_REFLECT && (i < 0 || i >= n);
+}
+
+// Sign of field f (layout U[0..m), U_x[0..m), U_y[0..m)) in a ghost mirrored
+// across a wall normal to direction d (0 = x, 1 = y): the wall-normal momentum
+// (Euler component 1 + d) is odd, and so is every derivative along d; the
+// two parities multiply.
+__host__ __device__ __forceinline__ int mirror_sign(int f, int m, bool euler, int d) {
+  const int c = f % m, g = f / m;
+  int s = (euler && c == 1 + d) ? -1 : 1;
+  if (g == 1 + d) s = -s;
+  return s;
 }
 
 // Loads and stores through the global address space.  Pointers that arrive
@@ -204,7 +241,9 @@ __device__ __forceinline__ bool stage_dt(const StageArgs<double>* unused, double
 // NT threads; TX x TY cells (TX*TY <= NT); sm, fb: LDS staging buffers.
 // Returns this thread's contribution to the next stage's speeds.
 // ---------------------------------------------------------------------------
-template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
+// CL: the characteristic variant of the limiter (Euler; a separate
+// instantiation so the default kernels carry none of its code).
+template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT, bool CL>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T>& k,
                                            int tile_x, int tile_y, double dt, double alx,
                                            double aly, T* __restrict__ sm, T* __restrict__ fb,
@@ -233,8 +272,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
     const int q = tid + r * NT;
     if (q < W * HR) {
       const int lr = q / W, lc = q - lr * W;
-      const int gi = map_index(i0 - 2 + lc, nx, a.bc_x);
-      const int gj = (DIM == 2) ? map_index(j0 - HY + lr, ny, a.bc_y) : 0;
+      const int ii = i0 - 2 + lc, jj = j0 - HY + lr;
+      const int gi = map_index2(ii, nx, a.bc_x);
+      const int gj = (DIM == 2) ? map_index2(jj, ny, a.bc_y) : 0;
       const long long g = (long long)gj * nx + gi;
 #pragma unroll
       for (int f = 0; f < NF; ++f) v[r][f] = gld(a.in + f * fs + g);
@@ -246,6 +286,27 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
     if (q < W * HR) {
 #pragma unroll
       for (int f = 0; f < NF; ++f) sm[f * HR * W + q] = v[r][f];
+    }
+  }
+  if constexpr (PHYS == PH_EULER) {
+    // Reflecting walls: a ghost cell holds the mirror image of an interior
+    // cell with its odd fields negated.  Only tiles whose halo crosses such a
+    // wall (a uniform decision) fix their LDS entries, each thread the ones it
+    // stored itself, so the staging above stays the same for every tile.
+    const bool wx = a.bc_x == HWENO_BC_REFLECT && (i0 - 2 < 0 || i0 - 2 + W > nx);
+    const bool wy = DIM == 2 && a.bc_y == HWENO_BC_REFLECT && (j0 - HY < 0 || j0 - HY + HR > ny);
+    if (wx || wy) {
+      for (int q = tid; q < W * HR; q += NT) {
+        const int lr = q / W, lc = q - lr * W;
+        const int ii = i0 - 2 + lc, jj = j0 - HY + lr;
+        const bool mx = wx && (ii < 0 || ii >= nx), my = wy && (jj < 0 || jj >= ny);
+        if (!(mx || my)) continue;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+          const int sg = (mx ? mirror_sign(f, M, true, 0) : 1) * (my ? mirror_sign(f, M, true, 1) : 1);
+          if (sg < 0) sm[f * HR * W + q] = -sm[f * HR * W + q];
+        }
+      }
     }
   }
   __syncthreads();
@@ -361,17 +422,47 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
   } else {
     // S^_k = (U_k, limited derivatives of S_k)
     T Sh[NF];
+    constexpr bool charlim = CL && PHYS == PH_EULER;
+    const bool complim = k.limiter_on && !charlim;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       const T* u = own + (c * HR) * W;
       const T* v = own + ((M + c) * HR) * W;
       Sh[c] = u[0];
-      Sh[M + c] = k.limiter_on ? limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw) : v[0];
+      Sh[M + c] = complim ? limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw) : v[0];
       if constexpr (DIM == 2) {
         const T* w = own + ((2 * M + c) * HR) * W;
-        Sh[2 * M + c] = k.limiter_on ? limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
-                                              T(1.0 / a.dy), k.lw)
-                                     : w[0];
+        Sh[2 * M + c] = complim ? limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
+                                         T(1.0 / a.dy), k.lw)
+                                : w[0];
+      }
+    }
+    if constexpr (charlim) {
+      if (k.limiter_on) {
+        // characteristic variant of the limiter, x then y (normal frame:
+        // the two momenta swap places for y)
+        T um[M], u0[M], up[M], vm[M], vp[M], r[M];
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const T* u = own + (c * HR) * W;
+          const T* v = own + ((M + c) * HR) * W;
+          um[c] = u[-1], u0[c] = u[0], up[c] = u[1], vm[c] = v[-1], vp[c] = v[1];
+        }
+        limit_char<T, M>(um, u0, up, vm, vp, hx, idx, k.lw, k.gm1, r);
+#pragma unroll
+        for (int c = 0; c < M; ++c) Sh[M + c] = r[c];
+        if constexpr (DIM == 2) {
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            const int q = (c == 1) ? 2 : (c == 2) ? 1 : c;
+            const T* u = own + (q * HR) * W;
+            const T* w = own + ((2 * M + q) * HR) * W;
+            um[c] = u[-W], u0[c] = u[0], up[c] = u[W], vm[c] = w[-W], vp[c] = w[W];
+          }
+          limit_char<T, M>(um, u0, up, vm, vp, T(a.dy), T(1.0 / a.dy), k.lw, k.gm1, r);
+#pragma unroll
+          for (int c = 0; c < M; ++c) Sh[2 * M + ((c == 1) ? 2 : (c == 2) ? 1 : c)] = r[c];
+        }
       }
     }
     T L[NF];
@@ -420,7 +511,7 @@ struct StageOcc {
   static constexpr int WAVES = sizeof(T) == 4 ? (K == 0 ? 3 : 4) : (K == 0 ? 1 : 2);
 };
 
-template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT>
+template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT, bool CL>
 __global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
@@ -445,8 +536,8 @@ __global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs
   const int tile_y = t / ntx, tile_x = t - tile_y * ntx;
   T sx = T(0), sy = T(0);
   uint32_t flags = 0;
-  stage_tile<T, PHYS, DIM, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
-                                          flags);
+  stage_tile<T, PHYS, DIM, K, TX, TY, NT, CL>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
+                                              flags);
   if constexpr (K > 0) {
     // speeds of the new stage state feed the next stage's splitting
     block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status,
@@ -499,7 +590,7 @@ __device__ __forceinline__ StageArgs<T> instance_args(const hweno_instance& I, d
 
 // One tile t of the flattened list; nothing is done when its instance's step
 // is skipped (a decision uniform over the workgroup).
-template <typename T, int V, int K>
+template <typename T, int V, int K, bool CL>
 __device__ __forceinline__ void batched_tile(const hweno_instance* __restrict__ inst,
                                              const int* __restrict__ tile_map, int t, double cfl,
                                              const Consts<T>& k, T* sm, T* fb) {
@@ -516,8 +607,8 @@ __device__ __forceinline__ void batched_tile(const hweno_instance* __restrict__ 
   const int tile_y = lt / ntx, tile_x = lt - tile_y * ntx;
   T sx = T(0), sy = T(0);
   uint32_t flags = 0;
-  stage_tile<T, PH_EULER, 2, K, TX, TY, NT>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
-                                            flags);
+  stage_tile<T, PH_EULER, 2, K, TX, TY, NT, CL>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx,
+                                                sy, flags);
   block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status, K < 3);
 }
 
@@ -526,7 +617,7 @@ __device__ __forceinline__ void batched_tile(const hweno_instance* __restrict__ 
 // those reads stay scalar and never queue behind the other workgroups'
 // atomics on the same control line.  Otherwise: persistent, striding over
 // XCD bands of the tile list.
-template <typename T, int V, int K, bool ONE>
+template <typename T, int V, int K, bool ONE, bool CL>
 __global__ __launch_bounds__(256, (StageOcc<T, K>::WAVES)) void k_stage_batched(
     const hweno_instance* __restrict__ inst, const int* __restrict__ tile_map, int total,
     double cfl, Consts<T> k) {
@@ -534,11 +625,11 @@ __global__ __launch_bounds__(256, (StageOcc<T, K>::WAVES)) void k_stage_batched(
   __shared__ T sm[12 * (TY + 4) * (TX + 4)];
   __shared__ T fb[12 * (TY + 1) * (TX + 1)];
   if constexpr (ONE) {
-    batched_tile<T, V, K>(inst, tile_map, xcd_band(blockIdx.x, gridDim.x), cfl, k, sm, fb);
+    batched_tile<T, V, K, CL>(inst, tile_map, xcd_band(blockIdx.x, gridDim.x), cfl, k, sm, fb);
   } else {
     const BandIter bi(total);
     for (int it = 0; bi.valid(it); ++it) {
-      batched_tile<T, V, K>(inst, tile_map, bi.tile(it), cfl, k, sm, fb);
+      batched_tile<T, V, K, CL>(inst, tile_map, bi.tile(it), cfl, k, sm, fb);
       __syncthreads();  // LDS tile and fold slots are reused by the next tile
     }
   }
@@ -627,7 +718,7 @@ template <typename T>
 struct FoldArgs {
   const T* E;
   int nxe, nye;
-  int nx, ny, bc_x, bc_y, dim, nf, m;
+  int nx, ny, bc_x, bc_y, dim, nf, m, euler;
   long long fs;
   T* out;
   int accumulate;
@@ -676,13 +767,16 @@ __device__ __forceinline__ void fold_cell_field(const FoldArgs<T>& a, int i, int
   const long long q = (long long)j * a.nx + i;
   const T* Ef = a.E + (long long)f * a.nye * a.nxe;
   T v = Ef[(long long)(j + GY) * a.nxe + (i + GX)];
+  // ghosts copied from this cell; a reflecting wall copied them with a sign
+  const T sx = (a.bc_x == HWENO_BC_REFLECT) ? T(mirror_sign(f, a.m, a.euler, 0)) : T(1);
 #pragma unroll
   for (int g = 0; g < 4; ++g)
-    if (map_index(gx[g], a.nx, a.bc_x) == i) v += Ef[(long long)(j + GY) * a.nxe + (gx[g] + GX)];
+    if (map_index(gx[g], a.nx, a.bc_x) == i) v += sx * Ef[(long long)(j + GY) * a.nxe + (gx[g] + GX)];
   if (a.dim == 2) {
+    const T sy = (a.bc_y == HWENO_BC_REFLECT) ? T(mirror_sign(f, a.m, a.euler, 1)) : T(1);
 #pragma unroll
     for (int g = 0; g < 4; ++g)
-      if (map_index(gy[g], a.ny, a.bc_y) == j) v += Ef[(long long)(gy[g] + GY) * a.nxe + (i + GX)];
+      if (map_index(gy[g], a.ny, a.bc_y) == j) v += sy * Ef[(long long)(gy[g] + GY) * a.nxe + (i + GX)];
   }
   const long long o = (long long)f * a.fs + q;
   T r = v;
@@ -799,11 +893,18 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
   const T cl = T(a.cl);
   for (int q = tid; q < W * HR; q += NT) {
     const int lr = q / W, lc = q - lr * W;
-    const int gi = map_index(rx0 - HX + lc, nx, a.bc_x);
-    const int gj = (DIM == 2) ? map_index(ry0 - HY + lr, ny, a.bc_y) : 0;
+    const int ii = rx0 - HX + lc, jj = ry0 - HY + lr;
+    const int gi = map_index(ii, nx, a.bc_x);
+    const int gj = (DIM == 2) ? map_index(jj, ny, a.bc_y) : 0;
     const long long g = (long long)gj * nx + gi;
+    const bool mx = mirrored(ii, nx, a.bc_x), my = DIM == 2 && mirrored(jj, ny, a.bc_y);
 #pragma unroll
-    for (int f = 0; f < NF; ++f) sm[q * NF + f] = a.S[f * fs + g];
+    for (int f = 0; f < NF; ++f) {
+      const T x = a.S[f * fs + g];
+      const int sg = (mx ? mirror_sign(f, M, PHYS == PH_EULER, 0) : 1) *
+                     (my ? mirror_sign(f, M, PHYS == PH_EULER, 1) : 1);
+      sm[q * NF + f] = sg < 0 ? -x : x;
+    }
   }
   __syncthreads();
 
@@ -1093,22 +1194,57 @@ __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __res
   const long long i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= n) return;
   const int gj = (int)(i / nx), gi = (int)(i - (long long)gj * nx);
+  constexpr bool EU = PHYS == PH_EULER;
   const long long xm = (long long)gj * nx + map_index(gi - 1, nx, bc_x);
   const long long xp = (long long)gj * nx + map_index(gi + 1, nx, bc_x);
+  const bool mxm = mirrored(gi - 1, nx, bc_x), mxp = mirrored(gi + 1, nx, bc_x);
+  // value of field f at a neighbour, with the wall signs when it is a mirrored ghost
+  auto nb = [&](int f, long long at, bool mir, int d) {
+    const T x = S[f * n + at];
+    return (mir && mirror_sign(f, M, EU, d) < 0) ? -x : x;
+  };
+  if (EU && k.limiter_char) {
+    // characteristic variant (normal frame: the momenta swap places for y)
+    T um[M], u0[M], up[M], vm[M], vp[M], r[M];
+#pragma unroll
+    for (int c = 0; c < M; ++c) {
+      um[c] = nb(c, xm, mxm, 0), u0[c] = S[c * n + i], up[c] = nb(c, xp, mxp, 0);
+      vm[c] = nb(M + c, xm, mxm, 0), vp[c] = nb(M + c, xp, mxp, 0);
+    }
+    limit_char<T, M>(um, u0, up, vm, vp, T(dx), T(1.0 / dx), k.lw, k.gm1, r);
+#pragma unroll
+    for (int c = 0; c < M; ++c) out[c * n + i] = r[c];
+    if constexpr (DIM == 2) {
+      const long long ym = (long long)map_index(gj - 1, ny, bc_y) * nx + gi;
+      const long long yp = (long long)map_index(gj + 1, ny, bc_y) * nx + gi;
+      const bool mym = mirrored(gj - 1, ny, bc_y), myp = mirrored(gj + 1, ny, bc_y);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        const int q = (c == 1) ? 2 : (c == 2) ? 1 : c;
+        um[c] = nb(q, ym, mym, 1), u0[c] = S[q * n + i], up[c] = nb(q, yp, myp, 1);
+        vm[c] = nb(2 * M + q, ym, mym, 1), vp[c] = nb(2 * M + q, yp, myp, 1);
+      }
+      limit_char<T, M>(um, u0, up, vm, vp, T(dy), T(1.0 / dy), k.lw, k.gm1, r);
+#pragma unroll
+      for (int c = 0; c < M; ++c) out[(M + ((c == 1) ? 2 : (c == 2) ? 1 : c)) * n + i] = r[c];
+    }
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    const T* u = S + c * n;
-    const T* v = S + (M + c) * n;
-    out[c * n + i] = limit1(u[xm], u[i], u[xp], v[xm], v[xp], T(dx), T(1.0 / dx), k.lw);
+    out[c * n + i] = limit1(nb(c, xm, mxm, 0), S[c * n + i], nb(c, xp, mxp, 0),
+                            nb(M + c, xm, mxm, 0), nb(M + c, xp, mxp, 0), T(dx), T(1.0 / dx),
+                            k.lw);
   }
   if constexpr (DIM == 2) {
     const long long ym = (long long)map_index(gj - 1, ny, bc_y) * nx + gi;
     const long long yp = (long long)map_index(gj + 1, ny, bc_y) * nx + gi;
+    const bool mym = mirrored(gj - 1, ny, bc_y), myp = mirrored(gj + 1, ny, bc_y);
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      const T* u = S + c * n;
-      const T* w = S + (2 * M + c) * n;
-      out[(M + c) * n + i] = limit1(u[ym], u[i], u[yp], w[ym], w[yp], T(dy), T(1.0 / dy), k.lw);
+      out[(M + c) * n + i] = limit1(nb(c, ym, mym, 1), S[c * n + i], nb(c, yp, myp, 1),
+                                    nb(2 * M + c, ym, mym, 1), nb(2 * M + c, yp, myp, 1), T(dy),
+                                    T(1.0 / dy), k.lw);
     }
   }
 }
@@ -1206,9 +1342,20 @@ hweno_status validate(const hweno_problem* p) {
     return fail(HWENO_ERR_INVALID_ARG, "unknown physics %d", p->physics);
   if (p->dtype != HWENO_F32 && p->dtype != HWENO_F64)
     return fail(HWENO_ERR_INVALID_ARG, "unknown dtype %d", p->dtype);
-  if ((p->bc_x != HWENO_BC_PERIODIC && p->bc_x != HWENO_BC_OUTFLOW) ||
-      (p->dim == 2 && p->bc_y != HWENO_BC_PERIODIC && p->bc_y != HWENO_BC_OUTFLOW))
+  auto bc_ok = [](int b) {
+    return b == HWENO_BC_PERIODIC || b == HWENO_BC_OUTFLOW || b == HWENO_BC_REFLECT;
+  };
+  if (!bc_ok(p->bc_x) || (p->dim == 2 && !bc_ok(p->bc_y)))
     return fail(HWENO_ERR_INVALID_ARG, "unknown boundary condition");
+  if (p->physics != HWENO_EULER &&
+      (p->bc_x == HWENO_BC_REFLECT || (p->dim == 2 && p->bc_y == HWENO_BC_REFLECT)))
+    return fail(HWENO_ERR_UNSUPPORTED, "reflecting walls are defined for the Euler equations only");
+  // the two ghost cells mirror two distinct interior cells
+  if ((p->bc_x == HWENO_BC_REFLECT && p->nx == 1) ||
+      (p->dim == 2 && p->bc_y == HWENO_BC_REFLECT && p->ny == 1))
+    return fail(HWENO_ERR_INVALID_ARG, "a reflecting wall needs at least 2 cells across");
+  if (p->limiter_characteristic != 0 && p->limiter_characteristic != 1)
+    return fail(HWENO_ERR_INVALID_ARG, "limiter_characteristic must be 0 or 1");
   if (!(p->dx > 0.0) || !std::isfinite(p->dx)) return fail(HWENO_ERR_INVALID_ARG, "dx must be > 0");
   if (p->dim == 2 && (!(p->dy > 0.0) || !std::isfinite(p->dy)))
     return fail(HWENO_ERR_INVALID_ARG, "dy must be > 0");
@@ -1265,7 +1412,13 @@ Consts<T> make_consts(const hweno_problem* p) {
   k.ay = T(p->adv_speed[1]);
   k.characteristic = p->characteristic ? 1 : 0;
   k.limiter_on = p->limiter_on ? 1 : 0;
+  k.limiter_char = p->limiter_characteristic ? 1 : 0;
   return k;
+}
+
+// the characteristic limiter variant is in force (Euler with the limiter on)
+bool char_limiter(const hweno_problem* p) {
+  return p->physics == HWENO_EULER && p->limiter_on && p->limiter_characteristic;
 }
 
 hweno_status launch_check(const char* what) {
@@ -1359,7 +1512,7 @@ struct RunRhs {
     a.out = (T*)rhs;
     a.alpha = alpha;
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
-    k_stage<T, PHYS, DIM, 0, TX, TY, NT><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
+    k_stage<T, PHYS, DIM, 0, TX, TY, NT, false><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
         a, make_consts<T>(p));
     return launch_check("rhs");
   }
@@ -1404,15 +1557,26 @@ struct RunStep {
     T* s2 = (T*)(w + L.s2);
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
     const dim3 grid = stage_grid(DIM, a.nx, a.ny);
-    a.in = (const T*)state;
-    a.out = s1;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 1, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
-    a.in = s1;
-    a.out = s2;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 2, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
-    a.in = s2;
-    a.out = (T*)state;
-    timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY, NT><<<grid, NT, 0, s>>>(a, k); });
+    auto stages = [&](auto cl) {
+      constexpr bool CL = decltype(cl)::value;
+      a.in = (const T*)state;
+      a.out = s1;
+      timed(s, [&] { k_stage<T, PHYS, DIM, 1, TX, TY, NT, CL><<<grid, NT, 0, s>>>(a, k); });
+      a.in = s1;
+      a.out = s2;
+      timed(s, [&] { k_stage<T, PHYS, DIM, 2, TX, TY, NT, CL><<<grid, NT, 0, s>>>(a, k); });
+      a.in = s2;
+      a.out = (T*)state;
+      timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY, NT, CL><<<grid, NT, 0, s>>>(a, k); });
+    };
+    if constexpr (PHYS == PH_EULER) {
+      if (char_limiter(p))
+        stages(std::true_type{});
+      else
+        stages(std::false_type{});
+    } else {
+      stages(std::false_type{});
+    }
     k_finish<<<1, 64, 0, s>>>(ctrl, tape);
     return launch_check("rk3_step");
   }
@@ -1483,6 +1647,7 @@ struct RunAdj {
     fo.dim = DIM;
     fo.nf = Comps<PHYS, DIM>::NF;
     fo.m = Comps<PHYS, DIM>::M;
+    fo.euler = PHYS == PH_EULER;
     fo.fs = a.fs;
     a.fused = (fuse && DIM == 2 && a.nx >= 4 && a.ny >= 4) ? 1 : 0;
     a.fo = fo;
@@ -1586,7 +1751,7 @@ hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, con
   int grid = blocks;
   if (grid <= 0) {  // default: exactly the workgroups that can be resident at once
     int per_cu = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_batched<T, V, 1, false>, 256, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_batched<T, V, 1, false, false>, 256, 0) !=
             hipSuccess ||
         per_cu < 1)
       per_cu = 1;
@@ -1596,14 +1761,23 @@ hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, con
   const unsigned small = (unsigned)((n + 255) / 256);
   k_begin_batched<<<small, 256, 0, s>>>(inst, n);
   k_alpha_batched<T, V><<<std::min(total, 4 * device_cus()), 256, 0, s>>>(inst, map, total, k);
+  auto stages = [&](auto one, auto cl) {
+    constexpr bool ONE = decltype(one)::value, CL = decltype(cl)::value;
+    timed(s, [&] { k_stage_batched<T, V, 1, ONE, CL><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 2, ONE, CL><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    timed(s, [&] { k_stage_batched<T, V, 3, ONE, CL><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+  };
+  const bool cl = char_limiter(p);
   if (grid == total) {
-    timed(s, [&] { k_stage_batched<T, V, 1, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
-    timed(s, [&] { k_stage_batched<T, V, 2, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
-    timed(s, [&] { k_stage_batched<T, V, 3, true><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    if (cl)
+      stages(std::true_type{}, std::true_type{});
+    else
+      stages(std::true_type{}, std::false_type{});
   } else {
-    timed(s, [&] { k_stage_batched<T, V, 1, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
-    timed(s, [&] { k_stage_batched<T, V, 2, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
-    timed(s, [&] { k_stage_batched<T, V, 3, false><<<grid, 256, 0, s>>>(inst, map, total, p->cfl, k); });
+    if (cl)
+      stages(std::false_type{}, std::true_type{});
+    else
+      stages(std::false_type{}, std::false_type{});
   }
   k_finish_batched<<<small, 256, 0, s>>>(inst, n);
   return launch_check("rk3_step_batched");
@@ -1695,6 +1869,8 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, con
                                size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
+  if (prob->physics == HWENO_EULER && prob->limiter_on && prob->limiter_characteristic)
+    return fail(HWENO_ERR_UNSUPPORTED, "the adjoint of the characteristic limiter is not implemented");
   if (empty(prob)) return ok();
   if (!state || !alpha || !lam_rhs || !lam_state || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state, alpha, lam_rhs, lam_state and ws must be non-NULL");
@@ -1712,6 +1888,8 @@ hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state
                                     void* lam, void* ws, size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
+  if (prob->physics == HWENO_EULER && prob->limiter_on && prob->limiter_characteristic)
+    return fail(HWENO_ERR_UNSUPPORTED, "the adjoint of the characteristic limiter is not implemented");
   if (empty(prob)) return ok();
   if (!state0 || !step_ws || !tape || !lam || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state0, step_ws, tape, lam and ws must be non-NULL");

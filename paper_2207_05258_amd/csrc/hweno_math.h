@@ -44,6 +44,7 @@ struct Consts {
   T ax, ay;       // advection speeds (linear advection)
   int characteristic;
   int limiter_on;
+  int limiter_char;  // Euler: limiter on characteristic fields of each cell
 };
 
 // Reciprocal, quotient and reciprocal square root of finite, positive,
@@ -273,6 +274,21 @@ struct Eigen {
     b2 = b1 * hq2;
   }
 
+  // eigen-system at one state (what the Roe average of a state with itself gives)
+  HW_HD void cell(const T* U, T gm1) {
+    const T ir = fast_rcp(U[0]);
+    un = U[1] * ir;
+    ut = (M == 4) ? U[2] * ir : T(0);
+    hq2 = T(0.5) * (un * un + ut * ut);
+    const T p = gm1 * (U[M - 1] - U[0] * hq2);
+    H = (U[M - 1] + p) * ir;
+    const T c2 = gm1 * (H - hq2);
+    ic = fast_rsq(c2);
+    c = c2 * ic;
+    b1 = gm1 * ic * ic;
+    b2 = b1 * hq2;
+  }
+
   // w = L x
   HW_HD void project(const T* x, T* w) const {
     if constexpr (M == 4) {
@@ -307,6 +323,27 @@ struct Eigen {
     }
   }
 };
+
+// Characteristic variant of the limiter (a choice the paper leaves open for
+// systems): the five stencil vectors u_{i-1}, u_i, u_{i+1}, v_{i-1}, v_{i+1}
+// (normal frame) are projected with the left eigenvectors of the cell's own
+// state, each characteristic field is limited as a scalar, and the right
+// eigenvectors map the result back.
+template <typename T, int M>
+HW_HD void limit_char(const T* um, const T* u0, const T* up, const T* vm, const T* vp, T h, T ih,
+                      const Weights<T>& w, T gm1, T* out) {
+  Eigen<T, M> e;
+  e.cell(u0, gm1);
+  T a[M], b[M], c[M], dm[M], dp[M], z[M];
+  e.project(um, a);
+  e.project(u0, b);
+  e.project(up, c);
+  e.project(vm, dm);
+  e.project(vp, dp);
+#pragma unroll
+  for (int q = 0; q < M; ++q) z[q] = limit1(a[q], b[q], c[q], dm[q], dp[q], h, ih, w);
+  e.back(z, out);
+}
 
 // ---------------------------------------------------------------------------
 // All fluxes of one interface x_{i+1/2} along the normal direction.

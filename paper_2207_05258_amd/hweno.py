@@ -8,6 +8,7 @@ the calls raise.
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 from dataclasses import dataclass, field
 from typing import Optional, Tuple
@@ -23,7 +24,7 @@ ST_NONFINITE, ST_RHO, ST_PRESSURE, ST_SKIPPED = 1, 2, 4, 8
 
 PHYSICS = {"linadv": 0, "burgers": 1, "euler": 2}
 DTYPES = {torch.float32: 0, torch.float64: 1}
-PERIODIC, OUTFLOW = 0, 1
+PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
 
 
 class HwenoError(RuntimeError):
@@ -38,7 +39,7 @@ class _CProblem(ctypes.Structure):
         ("physics", ctypes.c_int32), ("dtype", ctypes.c_int32),
         ("bc_x", ctypes.c_int32), ("bc_y", ctypes.c_int32),
         ("characteristic", ctypes.c_int32), ("limiter_on", ctypes.c_int32),
-        ("reserved", ctypes.c_int32),
+        ("limiter_characteristic", ctypes.c_int32),
         ("dx", ctypes.c_double), ("dy", ctypes.c_double),
         ("gamma_gas", ctypes.c_double), ("adv_speed", ctypes.c_double * 2),
         ("lin_w", ctypes.c_double * 3), ("lim_w", ctypes.c_double * 3),
@@ -128,6 +129,7 @@ class Problem:
     bc_y: int = PERIODIC
     characteristic: bool = True
     limiter_on: bool = True
+    limiter_characteristic: bool = False
     gamma_gas: float = 1.4
     adv_speed: Tuple[float, float] = (1.0, 1.0)
     lin_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)
@@ -156,6 +158,7 @@ class Problem:
         p.bc_x, p.bc_y = int(self.bc_x), int(self.bc_y)
         p.characteristic = int(bool(self.characteristic))
         p.limiter_on = int(bool(self.limiter_on))
+        p.limiter_characteristic = int(bool(self.limiter_characteristic))
         p.dx, p.dy = float(self.dx), float(self.dy)
         p.gamma_gas = float(self.gamma_gas)
         p.adv_speed[:] = [float(x) for x in self.adv_speed]
@@ -254,10 +257,13 @@ class Stepper:
         self.prob = prob
         self._c = prob.c()
         self.nbytes = max(workspace_bytes(prob), 256)
-        self.ws = torch.zeros(self.nbytes + 256, dtype=torch.uint8, device=device)
+        # Only the control block must start at zero: every step writes the stage
+        # states before reading them.
+        self.ws = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
         off = (-self.ws.data_ptr()) % 256
         self.ws = self.ws[off:off + self.nbytes]
         self.ctrl = self.ws[:CTRL_LEN * 8].view(torch.float64)
+        self.ctrl.zero_()
         self.ctrl[7] = t0
 
     def step(self, S: torch.Tensor, dt: Optional[float] = None, t_end: Optional[float] = None,
@@ -271,6 +277,15 @@ class Stepper:
                                     float(dt or 0.0), float(t_end or 0.0), _ptr(tape),
                                     _ptr(replay), _stream()), "hweno_rk3_step")
         return S
+
+    @classmethod
+    def _over(cls, prob: Problem, c: _CProblem, ws: torch.Tensor, nbytes: int) -> "Stepper":
+        """A stepper over a caller-provided, 256-byte aligned workspace whose control
+        block the caller has initialised (no checks, no allocation)."""
+        self = cls.__new__(cls)
+        self.prob, self._c, self.nbytes, self.ws = prob, c, nbytes, ws
+        self.ctrl = ws[:CTRL_LEN * 8].view(torch.float64)
+        return self
 
     @property
     def t(self) -> float:
@@ -487,15 +502,31 @@ def rollout_replay(S0: torch.Tensor, prob: Problem, tapes: torch.Tensor) -> torc
     return S
 
 
+def _ws_stride(prob: Problem) -> int:
+    return (max(workspace_bytes(prob), 256) + 255) // 256 * 256
+
+
+def rollout_bytes_kept(prob: Problem, n_steps: int) -> int:
+    """Device bytes that a rollout keeping every step's states holds until its backward
+    (one step workspace, 256-byte aligned, and one input state per step)."""
+    state = prob.nf * prob.shape()[1] * prob.nx * (8 if prob.dtype == torch.float64 else 4)
+    return n_steps * (_ws_stride(prob) + state)
+
+
 class Rollout(torch.autograd.Function):
     """n_steps SSP-RK3 steps as a differentiable function of the initial state.
 
     Forward: device-side CFL time steps (or ``dt``), one tape record per step
-    (speeds of the three stages and dt), a checkpoint every ``ckpt`` steps.
-    Backward: for each segment, newest first, recompute its steps from the
-    checkpoint with the tape replayed (keeping each step's stage states), then
-    apply the hand-written step adjoints in reverse.  Speeds and time steps
-    are held fixed (replay semantics), so the gradient is that of the taped
+    (speeds of the three stages and dt).  What the backward needs of each step
+    (its input state and its two intermediate stage states) is either kept in
+    device memory for every step (``ckpt=0``), or kept as a checkpoint every
+    ``ckpt`` steps and recomputed segment by segment, newest first, with the
+    tape replayed; the replay of the next older segment runs on a side stream,
+    overlapped with the adjoints of the current one.  ``ckpt=None`` keeps every
+    step when that takes at most half of the free device memory, else
+    checkpoints every ~sqrt(n_steps) steps.  The backward applies the
+    hand-written step adjoints in reverse.  Speeds and time steps are held
+    fixed (replay semantics), so the gradient is that of the taped
     computation.  Returns the final state; ``Rollout.last_tapes`` keeps the
     tape of the most recent forward call.
     """
@@ -503,17 +534,45 @@ class Rollout(torch.autograd.Function):
     last_tapes = None
 
     @staticmethod
-    def forward(ctx, S0, prob: Problem, n_steps: int, ckpt: int = 20, dt: Optional[float] = None):
+    def forward(ctx, S0, prob: Problem, n_steps: int, ckpt: Optional[int] = None,
+                dt: Optional[float] = None):
         S = S0.detach().clone().contiguous()
-        st = Stepper(prob, device=S.device)
+        if ckpt is None:
+            free, _ = torch.cuda.mem_get_info(S.device)
+            if rollout_bytes_kept(prob, n_steps) <= free // 2:
+                ckpt = 0
+            else:
+                ckpt = max(1, int(math.isqrt(max(n_steps, 1))))
+        if ckpt < 0:
+            raise ValueError("ckpt must be >= 0")
         tapes = torch.zeros(n_steps, CTRL_LEN, dtype=torch.float64, device=S.device)
-        ckpts = []
-        for n in range(n_steps):
-            if n % ckpt == 0:
-                ckpts.append(S.clone())
-            st.step(S, dt=dt, tape=tapes[n])
+        ckpts, kept = [], None
+        if ckpt == 0:
+            # two allocations for the whole rollout: the input state of every step
+            # and every step's workspace (its stage states), control blocks zeroed
+            # by one fill
+            validate(prob)
+            stride = _ws_stride(prob)
+            rows = max(n_steps, 1)
+            raw = torch.empty(rows * stride + 256, dtype=torch.uint8, device=S.device)
+            off = (-raw.data_ptr()) % 256
+            wsall = raw[off:off + rows * stride].view(rows, stride)
+            wsall[:, :CTRL_LEN * 8].zero_()
+            states = torch.empty((n_steps,) + tuple(S.shape), dtype=S.dtype, device=S.device)
+            c = prob.c()
+            steppers = [Stepper._over(prob, c, wsall[n], stride) for n in range(n_steps)]
+            for n in range(n_steps):
+                states[n].copy_(S)
+                steppers[n].step(S, dt=dt, tape=tapes[n])
+            kept = ([states[n] for n in range(n_steps)], steppers)
+        else:
+            st = Stepper(prob, device=S.device)
+            for n in range(n_steps):
+                if n % ckpt == 0:
+                    ckpts.append(S.clone())
+                st.step(S, dt=dt, tape=tapes[n])
         ctx.prob, ctx.n_steps, ctx.ckpt = prob, n_steps, ckpt
-        ctx.ckpts, ctx.tapes = ckpts, tapes
+        ctx.ckpts, ctx.tapes, ctx.kept = ckpts, tapes, kept
         Rollout.last_tapes = tapes
         return S
 
@@ -521,16 +580,52 @@ class Rollout(torch.autograd.Function):
     def backward(ctx, g):
         prob, n_steps, ckpt = ctx.prob, ctx.n_steps, ctx.ckpt
         lam = g.detach().contiguous().clone()
-        ws = adjoint_workspace(prob, lam.device)
-        steppers = [Stepper(prob, device=lam.device) for _ in range(min(ckpt, n_steps))]
+        dev = lam.device
+        ws = adjoint_workspace(prob, dev)
+        if ckpt == 0:
+            inputs, steppers = ctx.kept
+            for n in reversed(range(n_steps)):
+                step_adjoint(prob, inputs[n], steppers[n], ctx.tapes[n], lam, ws)
+                inputs[n] = steppers[n] = None   # give the memory back as the sweep goes
+            ctx.kept = None
+            return lam, None, None, None, None
         nseg = (n_steps + ckpt - 1) // ckpt
-        for seg in reversed(range(nseg)):
+        per = min(ckpt, n_steps)
+        # Two buffer sets of replayed segments: while the adjoints of one segment
+        # run on the caller's stream, the next older segment is replayed on a
+        # side stream (it depends only on its checkpoint), so the replay's
+        # partly filled waves of workgroups overlap the adjoint kernels.
+        main = torch.cuda.current_stream(dev)
+        side = torch.cuda.Stream(device=dev)
+        steppers = [[Stepper(prob, device=dev) for _ in range(per)] for _ in range(2)]
+        inputs = [[None] * per, [None] * per]
+        free = [None, None]  # event: the adjoints that last read buffer set b are done
+        side.wait_stream(main)
+
+        def replay(seg, b):
             n0, n1 = seg * ckpt, min((seg + 1) * ckpt, n_steps)
-            S = ctx.ckpts[seg].clone()
-            inputs = []
-            for n in range(n0, n1):
-                inputs.append(S.clone())
-                steppers[n - n0].step(S, replay=ctx.tapes[n])
+            with torch.cuda.stream(side):
+                if free[b] is not None:
+                    side.wait_event(free[b])
+                S = ctx.ckpts[seg].clone()
+                for n in range(n0, n1):
+                    x = S.clone()
+                    x.record_stream(main)
+                    inputs[b][n - n0] = x
+                    steppers[b][n - n0].step(S, replay=ctx.tapes[n])
+                done = torch.cuda.Event()
+                done.record(side)
+            return done
+
+        ready = replay(nseg - 1, (nseg - 1) % 2)
+        for seg in reversed(range(nseg)):
+            b = seg % 2
+            main.wait_event(ready)
+            if seg > 0:
+                ready = replay(seg - 1, (seg - 1) % 2)
+            n0, n1 = seg * ckpt, min((seg + 1) * ckpt, n_steps)
             for n in reversed(range(n0, n1)):
-                step_adjoint(prob, inputs[n - n0], steppers[n - n0], ctx.tapes[n], lam, ws)
+                step_adjoint(prob, inputs[b][n - n0], steppers[b][n - n0], ctx.tapes[n], lam, ws)
+            free[b] = torch.cuda.Event()
+            free[b].record(main)
         return lam, None, None, None, None

@@ -63,7 +63,14 @@ CASES = {
     "burgers2d_sine_19x23": lambda: hi.scalar_sine_2d(19, 23, "burgers"),
     "linadv1d_random_270": lambda: hi.scalar_random_1d(270, 6, "linadv", a=-0.8),
     "linadv2d_random_17x40": lambda: hi.scalar_random_2d(17, 40, 7, "linadv", a=(0.6, -1.1)),
+    "euler2d_rough_reflect_26x19": lambda: hi.euler2d_rough(26, 19, 16, bc=hi.REFLECT),
+    "euler1d_piecewise_reflect_150": lambda: _reflect(hi.euler1d_piecewise(150, 17)),
 }
+
+
+def _reflect(w):
+    w.bc_x = hi.REFLECT
+    return w
 
 
 def _mus(w, seed, dtype=torch.float64):
@@ -119,13 +126,15 @@ TINY = {
     "euler2d_rough_periodic_4x7": lambda: hi.euler2d_rough(4, 7, 14, bc=hi.PERIODIC),
     "euler2d_rough_outflow_6x5": lambda: hi.euler2d_rough(6, 5, 15),
     "burgers2d_sine_5x6": lambda: hi.scalar_sine_2d(5, 6, "burgers"),
+    "euler2d_rough_reflect_4x6": lambda: hi.euler2d_rough(4, 6, 18, bc=hi.REFLECT),
 }
 
 
 @pytest.mark.parametrize("limiter_on", [True, False], ids=["lim", "nolim"])
 @pytest.mark.parametrize("case", ["euler2d_rough_outflow_33x21", "euler2d_rsmooth_32x32",
                                   "euler1d_piecewise_301", "burgers2d_sine_19x23",
-                                  "linadv1d_random_270"] + sorted(TINY))
+                                  "linadv1d_random_270", "euler2d_rough_reflect_26x19",
+                                  "euler1d_piecewise_reflect_150"] + sorted(TINY))
 def test_step_adjoint_matches_oracle_autograd(case, limiter_on):
     w = (CASES.get(case) or TINY[case])()
     announce("step adjoint", case, limiter_on)
@@ -171,6 +180,26 @@ def test_rollout_gradient_matches_oracle_across_checkpoints():
                                                    (float(t[4]), float(t[5]))])
     _loss(S, P.exact_input(tgt), base.dx, base.dy).backward()
     assert rel_err(U0.grad, X.grad) < 1e-10, rel_err(U0.grad, X.grad)
+
+
+def test_rollout_keep_all_equals_checkpointed_replay():
+    """Keeping every step's states (ckpt=0), checkpointing with overlapped replay and the
+    automatic choice give bitwise the same gradient: the step adjoints see the same inputs."""
+    base, target = hi.adjoint_pair(40, 3)
+    announce("rollout keep-all vs checkpointed")
+    prob = P.gpu_problem(base, torch.float64)
+    tgt = P.to_gpu(target, torch.float64)
+    grads, finals = {}, {}
+    for ck in (0, 4, 1, None):
+        X = P.to_gpu(base, torch.float64).requires_grad_(True)
+        SN = h.Rollout.apply(X, prob, 11, ck, None)
+        _loss(SN, tgt, base.dx, base.dy).backward()
+        grads[ck], finals[ck] = X.grad.clone(), SN.detach().clone()
+    for ck in (4, 1, None):
+        assert torch.equal(finals[ck], finals[0]), ck
+        assert torch.equal(grads[ck], grads[0]), (ck, rel_err(grads[ck], grads[0]))
+    stride = (h.workspace_bytes(prob) + 255) // 256 * 256
+    assert h.rollout_bytes_kept(prob, 11) == 11 * (stride + 12 * 40 * 40 * 8)
 
 
 def test_rollout_gradient_matches_finite_differences():

@@ -71,6 +71,36 @@ def test_batched_equals_individual_bitwise(variant, dtype, blocks):
         assert torch.equal(b.ctrl(q)[:10], ctrls[q][:10]), q
 
 
+def test_batched_mixed_boundaries_equal_individual():
+    """Instances with periodic, outflow and reflecting walls in one batch."""
+    ws = hi.batched_instances(4, 21, sizes=[(30, 17), (17, 30), (24, 24), (9, 40)])
+    bcs = [(hi.REFLECT, hi.REFLECT), (hi.REFLECT, hi.PERIODIC), (hi.OUTFLOW, hi.REFLECT),
+           (hi.PERIODIC, hi.OUTFLOW)]
+    for w, (bx, by) in zip(ws, bcs):
+        w.bc_x, w.bc_y = bx, by
+    announce("batched mixed walls")
+    states, grids, common = _batch(ws, torch.float64)
+    b = h.BatchedStepper(states, grids, common)
+    b.step()
+    ref, _ = _individual(ws, torch.float64)
+    for q in range(len(ws)):
+        assert torch.equal(states[q], ref[q]), q
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_batched_characteristic_limiter_equals_individual(variant):
+    """The characteristic limiter variant, set on the common problem, in both tile variants."""
+    ws = hi.batched_instances(3, 23, sizes=[(30, 17), (9, 40), (24, 24)])
+    ws[1].bc_x = ws[1].bc_y = hi.REFLECT
+    announce("batched characteristic limiter", variant)
+    states, grids, common = _batch(ws, torch.float64, limiter_characteristic=True)
+    b = h.BatchedStepper(states, grids, common)
+    b.step(variant=variant, blocks=4)
+    ref, _ = _individual(ws, torch.float64, limiter_characteristic=True)
+    for q in range(len(ws)):
+        assert torch.equal(states[q], ref[q]), q
+
+
 def test_batched_against_oracle():
     ws = hi.batched_instances(4, 11, sizes=[(40, 23), (18, 35), (64, 16), (9, 9)])
     announce("batched vs oracle")

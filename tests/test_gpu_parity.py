@@ -38,6 +38,13 @@ def _gpu():
 # --------------------------------------------------------------------------
 # workloads: sizes span several tiles (32x8 in 2D, 256 in 1D) and ragged tails
 # --------------------------------------------------------------------------
+def _with_bc(w, bc_x, bc_y=None):
+    w.bc_x = bc_x
+    if bc_y is not None:
+        w.bc_y = bc_y
+    return w
+
+
 CASES = {
     "linadv1d_sine_200": lambda: hi.scalar_sine_1d(200, "linadv"),
     "linadv1d_neg_random_301": lambda: hi.scalar_random_1d(301, 3, "linadv", a=-0.7),
@@ -52,6 +59,13 @@ CASES = {
     "euler2d_wave_48x48": lambda: hi.euler2d_wave(48, 48),
     "burgers2d_sine_40x33": lambda: hi.scalar_sine_2d(40, 33, "burgers"),
     "linadv2d_random_33x17": lambda: hi.scalar_random_2d(33, 17, 6, "linadv", a=(1.0, -0.5)),
+    # reflecting walls (Euler): both sides, and mixed with periodic / outflow
+    "euler1d_piecewise_reflect_333": lambda: _with_bc(hi.euler1d_piecewise(333, 7), hi.REFLECT),
+    "euler2d_rough_reflect_47x29": lambda: hi.euler2d_rough(47, 29, 8, bc=hi.REFLECT),
+    "euler2d_quadrants_reflectx_periodicy_40x36":
+        lambda: _with_bc(hi.euler2d_quadrants(40, 36, 9), hi.REFLECT, hi.PERIODIC),
+    "euler2d_rsmooth_outflowx_reflecty_31x44":
+        lambda: _with_bc(hi.euler2d_random_smooth(31, 44, 10), hi.OUTFLOW, hi.REFLECT),
 }
 
 
@@ -112,6 +126,32 @@ def test_limit(case, dtype):
     D = h.limit(Sg, P.gpu_problem(w, dtype))
     Dref = o.limited_derivatives(S, P.oracle_problem(w))
     P.assert_within(P.limit_errors(D, Dref, S, w), P.TOL[dtype], f"limit {case}")
+
+
+CHAR_LIMITER_CASES = ["euler1d_piecewise_777_s5", "euler1d_piecewise_reflect_333",
+                      "euler2d_quadrants_70x45", "euler2d_rough_50x37",
+                      "euler2d_rough_reflect_47x29", "euler2d_rsmooth_outflowx_reflecty_31x44"]
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", CHAR_LIMITER_CASES)
+def test_limit_characteristic_variant(case, dtype):
+    w = CASES[case]()
+    announce("limit characteristic", case, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    D = h.limit(Sg, P.gpu_problem(w, dtype, limiter_characteristic=True))
+    Dref = o.limited_derivatives(S, P.oracle_problem(w, limiter_characteristic=True))
+    P.assert_within(P.limit_errors(D, Dref, S, w), P.TOL[dtype], f"char limit {case}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", CHAR_LIMITER_CASES)
+def test_rk3_step_characteristic_limiter(case, dtype):
+    w = CASES[case]()
+    announce("rk3_step characteristic limiter", case, dtype)
+    out, ref, *_ = _step_case(w, dtype, limiter_characteristic=True)
+    P.assert_within(P.step_errors(out, ref, w), P.TOL[dtype], f"step char limiter {case}")
 
 
 @pytest.mark.parametrize("weights", [((1 / 3, 1 / 3, 1 / 3), (0.01, 0.495, 0.495)),
@@ -211,12 +251,18 @@ def test_several_steps_euler2d(dtype):
 
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5])
-@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.OUTFLOW])
+@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.OUTFLOW, hi.REFLECT])
 def test_tiny_grids(n, bc):
     announce("tiny", n, bc)
     w1 = hi.euler1d_piecewise(n, 2)
     w1.bc_x = bc
     w2 = hi.euler2d_rough(n, n + 1, 5, bc=bc)
+    if bc == hi.REFLECT and n == 1:
+        # a wall needs two cells to mirror: refused on the host, no launch
+        for w in (w1, w2):
+            with pytest.raises(h.HwenoError, match="at least 2 cells"):
+                h.validate(P.gpu_problem(w, torch.float64))
+        return
     for w in (w1, w2):
         out, ref, *_ = _step_case(w, torch.float64)
         P.assert_within(P.step_errors(out, ref, w), 1e-12, f"tiny {w.name}")
