@@ -43,8 +43,8 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # kernel sources it was measured on (stale entries are reported as null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("2d62a9b658a00296", "f64", 4096): 5.0834e+09,
-    ("2d62a9b658a00296", "f32", 4096): 2.5424e+09,
+    ("e58f4b5e38ab2ec6", "f64", 4096): 5.0823e+09,
+    ("e58f4b5e38ab2ec6", "f32", 4096): 2.6242e+09,
 }
 
 

@@ -508,7 +508,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
 // keep one wave more of registers (they would spill at the stage bounds).
 template <typename T, int K>
 struct StageOcc {
-  static constexpr int WAVES = sizeof(T) == 4 ? (K == 0 ? 3 : 4) : (K == 0 ? 1 : 2);
+  static constexpr int WAVES = sizeof(T) == 4 ? (K == 0 ? 3 : 5) : (K == 0 ? 1 : 2);
 };
 
 template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT, bool CL>
