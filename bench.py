@@ -47,6 +47,17 @@ MEASURED_TRAFFIC = {
     ("e58f4b5e38ab2ec6", "f32", 4096): 2.6242e+09,
 }
 
+# VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
+# SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
+MEASURED_VALU_WAVE_INSTR = {
+    # profiles/k_stage_euler2d_4096_sq_counters.md
+    ("e58f4b5e38ab2ec6", "f64", 4096): 1.040e9,
+    ("e58f4b5e38ab2ec6", "f32", 4096): 9.209e8,
+}
+# VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
+# lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
+PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+
 
 def kernel_sha() -> str:
     """sha256[:16] of the device code embedded in the built library (its .hip_fatbin
@@ -67,22 +78,38 @@ def kernel_sha() -> str:
     return "unknown"
 
 
-def cpu_baseline(n: int = 1024):
-    """The CPU oracle, as it stands, on one SSP-RK3 step of an n x n grid."""
+def cpu_baseline(n: int = 1024, n1: int = 768):
+    """The CPU oracle, as it stands, on one SSP-RK3 step of an n x n grid with all
+    host threads, and of an n1 x n1 grid with one thread."""
     import torch
 
     import hweno_inputs as hi
     from oracle import hweno_ref as o
-    w = hi.euler2d_quadrants(n, n, 0)
-    prob = o.problem_from_workload(w)
-    S = o.as_tensor(w.S)
-    t0 = time.perf_counter()
-    o.rk3_step(S, prob)
-    dt = time.perf_counter() - t0
+
+    def one_step(m):
+        w = hi.euler2d_quadrants(m, m, 0)
+        prob = o.problem_from_workload(w)
+        S = o.as_tensor(w.S)
+        t0 = time.perf_counter()
+        o.rk3_step(S, prob)
+        return time.perf_counter() - t0
+
+    cores = torch.get_num_threads()
+    dt = one_step(n)
+    single = None
+    if n1 > 0:
+        torch.set_num_threads(1)
+        try:
+            dt1 = one_step(n1)
+        finally:
+            torch.set_num_threads(cores)
+        single = {"value": n1 * n1 * 3 / dt1, "cores": 1,
+                  "sample": f"one step at {n1}x{n1}, {dt1:.1f} s"}
     return {"value": n * n * 3 / dt, "unit": "cell-stage updates/s",
-            "cores": torch.get_num_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"one SSP-RK3 step (3 cell-stages per cell) of the four-quadrant 2D Euler "
-                      f"workload at {n}x{n} in float64 (torch CPU), {dt:.1f} s"}
+                      f"workload at {n}x{n} in float64 (torch CPU), {dt:.1f} s",
+            "single_thread": single}
 
 
 def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
@@ -214,6 +241,8 @@ def main():
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the secondary run in the other precision")
     ap.add_argument("--cpu-n", type=int, default=2048)
+    ap.add_argument("--cpu-n1", type=int, default=768,
+                    help="grid side of the one-thread oracle sample (0 = skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
     ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
@@ -284,6 +313,13 @@ def main():
 
     sha = kernel_sha()
     traffic = MEASURED_TRAFFIC.get((sha, args.dtype, args.n))
+    wave_instr = MEASURED_VALU_WAVE_INSTR.get((sha, args.dtype, args.n))
+    valu = None
+    if wave_instr is not None:
+        rate = wave_instr * 64 / (main_run["stage_ms_avg"] * 1e-3)
+        valu = {"lane_instr_per_s": float(f"{rate:.4g}"), "peak": PEAK_VALU_LANE_INSTR,
+                "frac": round(rate / PEAK_VALU_LANE_INSTR, 4),
+                "source": "SQ_INSTS_VALU per launch (rocprofv3) over the live launch time"}
     roofline = {
         "bound": "alu",
         "achieved": round(main_run["achieved_tflops"], 3),
@@ -296,8 +332,9 @@ def main():
         "algorithmic_hbm_GBps": round(main_run["algorithmic_hbm_gbs"], 1),
         "hbm_frac": round(main_run["algorithmic_hbm_gbs"] / PEAK_HBM_GBS, 4),
         "stage_launch_ms": round(main_run["stage_ms_avg"], 4),
+        "valu_issue": valu,
     }
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n, args.cpu_n1)
     out = {
         "metric": "2D Euler HWENO cell-stage updates/s",
         "value": main_run["rate"],
