@@ -586,7 +586,8 @@ class Rollout(torch.autograd.Function):
             inputs, steppers = ctx.kept
             for n in reversed(range(n_steps)):
                 step_adjoint(prob, inputs[n], steppers[n], ctx.tapes[n], lam, ws)
-                inputs[n] = steppers[n] = None   # give the memory back as the sweep goes
+            # the kept states are two allocations, released together here (the
+            # caching allocator reuses them in the next rollout of this size)
             ctx.kept = None
             return lam, None, None, None, None
         nseg = (n_steps + ckpt - 1) // ckpt
