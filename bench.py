@@ -189,6 +189,40 @@ def run_batched(steps: int, warmup: int, n_inst: int = 256, seed: int = 0):
             "graph": "one hipGraph per step (speeds, 3 persistent stages, time update)"}
 
 
+def run_small(n: int = 4000, steps: int = 200):
+    """A 1D Euler grid of n cells (piecewise-constant data, periodic, FP64), where a step
+    is a few microseconds of GPU work: eager steps against the same steps captured in
+    one graph and replayed."""
+    import torch
+
+    import hweno_inputs as hi
+    import paper_2207_05258_amd as h
+    w = hi.euler1d_piecewise(n, 0)
+    prob = h.Problem(dim=1, nx=n, ny=1, physics="euler", dtype=torch.float64, dx=w.dx,
+                     bc_x=w.bc_x)
+    S = torch.as_tensor(w.S).cuda().contiguous()
+    st = h.Stepper(prob)
+    for _ in range(5):
+        st.step(S)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        st.step(S)
+    torch.cuda.synchronize()
+    eager = time.perf_counter() - t0
+    st.capture(S, steps=steps)
+    st.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.replay()
+    torch.cuda.synchronize()
+    graph = time.perf_counter() - t0
+    return {"workload": f"1D Euler, {n} cells, FP64", "steps": steps,
+            "eager_us_per_step": eager * 1e6 / steps, "graph_us_per_step": graph * 1e6 / steps,
+            "graph_value": n * 3 * steps / graph, "unit": "cell-stage updates/s",
+            "status": st.status}
+
+
 def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 0, dtype_name: str = "f32"):
     """Differentiable rollout on a smooth periodic 2D Euler state, loss = 1/2 sum dx dy
     (rho_N - rho_target)^2.  ckpt = 0: the forward keeps every step's states in device
@@ -245,6 +279,8 @@ def main():
                     help="grid side of the one-thread oracle sample (0 = skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the small-grid eager-versus-graph run")
     ap.add_argument("--only", choices=["batched", "adjoint"], default=None,
                     help="run only this part and print its JSON object (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
@@ -311,6 +347,11 @@ def main():
               f"{adjoint['checkpointed']['backward_over_forward']:.2f} (checkpoint every 20)",
               file=sys.stderr, flush=True)
 
+    small = None if args.no_small else run_small()
+    if small is not None:
+        print(f"# small grid: {small['eager_us_per_step']:.1f} us/step eager, "
+              f"{small['graph_us_per_step']:.1f} us/step as one graph", file=sys.stderr, flush=True)
+
     sha = kernel_sha()
     traffic = MEASURED_TRAFFIC.get((sha, args.dtype, args.n))
     wave_instr = MEASURED_VALU_WAVE_INSTR.get((sha, args.dtype, args.n))
@@ -356,6 +397,7 @@ def main():
         "variant": variant,
         "batched": batched,
         "adjoint": adjoint,
+        "small_grid": small,
         "status_word": main_run["status"],
         "kernel_sha": sha,
     }

@@ -278,6 +278,27 @@ class Stepper:
                                     _ptr(replay), _stream()), "hweno_rk3_step")
         return S
 
+    def capture(self, S: torch.Tensor, steps: int = 1, dt: Optional[float] = None,
+                t_end: Optional[float] = None) -> "torch.cuda.CUDAGraph":
+        """Capture ``steps`` steps of S (in place, device-side dt unless ``dt``) in one
+        graph; ``replay()`` then advances S by that many steps with one launch from
+        the host.  S and this stepper's workspace must stay alive while the graph is
+        used.  For small grids, where a step is a few microseconds of GPU work, the
+        per-step host launch cost is what the graph removes."""
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                for _ in range(steps):
+                    self.step(S, dt=dt, t_end=t_end)
+        torch.cuda.current_stream().wait_stream(s)
+        self.graph = g
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
     @classmethod
     def _over(cls, prob: Problem, c: _CProblem, ws: torch.Tensor, nbytes: int) -> "Stepper":
         """A stepper over a caller-provided, 256-byte aligned workspace whose control

@@ -303,6 +303,32 @@ def test_periodic_conservation_and_determinism():
     assert torch.allclose(Sg[:4].sum(dim=(1, 2)), tot0, rtol=1e-13, atol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["euler1d_piecewise_4000", "linadv1d_sine_200",
+                                  "euler2d_quadrants_70x45", "euler2d_rough_reflect_47x29"])
+def test_graph_captured_steps_equal_eager_steps(case):
+    """Steps captured once into a graph and replayed (device-side dt and time) give
+    bitwise the eager steps, replay after replay, with other GPU work in between."""
+    w = CASES[case]()
+    announce("graph capture", case)
+    prob = P.gpu_problem(w, torch.float64)
+    Sg, Se = P.to_gpu(w, torch.float64), P.to_gpu(w, torch.float64)
+    sg, se = h.Stepper(prob), h.Stepper(prob)
+    sg.capture(Sg, steps=3)
+    torch.cuda.synchronize()
+    assert torch.equal(Sg, Se)            # capturing runs nothing
+    for r in range(4):
+        sg.replay()
+        for _ in range(3):
+            se.step(Se)
+        torch.cuda.synchronize()
+        junk = torch.randn(4096, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Se), r
+        assert torch.equal(sg.ctrl[:10], se.ctrl[:10]), r
+        del junk
+    assert float(sg.ctrl[9]) == 12.0
+
+
 def test_tape_and_replay_reproduce_the_step():
     w = hi.euler2d_rough(45, 38, 12)
     announce("tape/replay")
