@@ -118,8 +118,9 @@ typedef struct {
 #define HWENO_ST_PRESSURE 4u
 #define HWENO_ST_SKIPPED 8u
 
-/* Host-side validation of a problem (no HIP call).  Returns HWENO_OK or
- * HWENO_ERR_INVALID_ARG with hweno_last_error() set. */
+/* Host-side validation of a problem (no HIP call).  Returns HWENO_OK, or
+ * HWENO_ERR_INVALID_ARG / HWENO_ERR_UNSUPPORTED (reflecting walls for a scalar
+ * law) with hweno_last_error() set. */
 hweno_status hweno_validate(const hweno_problem* prob);
 
 /* Bytes of device workspace hweno_rk3_step needs for `prob`
@@ -143,7 +144,9 @@ hweno_status hweno_alpha(const hweno_problem* prob, const void* state,
 hweno_status hweno_rhs(const hweno_problem* prob, const void* state, void* rhs,
                        double* alpha, int32_t compute_alpha, void* stream);
 
-/* HWENO limiter (Section 2.2) applied component by component:
+/* HWENO limiter (Section 2.2), component by component on the conserved
+ * variables, or on the characteristic fields of each cell when the problem's
+ * limiter_characteristic is set (Euler):
  *   dlim = (U_x limited along x [, U_y limited along y]), m * dim fields in
  *   the state layout.  The centre derivative is not an input of the limiter. */
 hweno_status hweno_limit(const hweno_problem* prob, const void* state,
@@ -181,7 +184,9 @@ size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob);
  *   lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim
  * evaluated at `state`.  The absolute values in tau are differentiated as
  * sign(x) with sign(0) = 0; ghost cells are differentiated through the
- * boundary index maps (periodic wrap, outflow copy).
+ * boundary index maps (periodic wrap, outflow copy, reflection with the
+ * wall's sign flips).  HWENO_ERR_UNSUPPORTED for the characteristic limiter
+ * variant with the limiter on.
  * alpha: device double[2], the speeds of the forward evaluation (replayed).
  * lam_rhs: nf fields; lam_lim: m * dim fields (limited-derivative layout of
  * hweno_limit) or NULL; lam_state: nf fields, accumulated into.  lam_state
@@ -200,7 +205,9 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
  * the next step on it); tape: device double[HWENO_CTRL_LEN] (as written by
  * hweno_rk3_step); ws: >= hweno_adjoint_workspace_bytes(prob) bytes.
  * lam, state0, step_ws and ws must not overlap (2D grids finish most cells
- * of each stage's adjoint in the kernel that reads the stage's inputs). */
+ * of each stage's adjoint in the kernel that reads the stage's inputs).
+ * HWENO_ERR_UNSUPPORTED for the characteristic limiter variant with the
+ * limiter on. */
 hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state0,
                                     const void* step_ws, size_t step_ws_bytes,
                                     const double* tape, void* lam, void* ws,
