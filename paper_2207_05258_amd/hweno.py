@@ -212,7 +212,8 @@ def workspace_bytes(prob: Problem) -> int:
 
 
 def alpha(S: torch.Tensor, prob: Problem, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Global Lax-Friedrichs speeds (alpha_x, alpha_y) as a float64 device tensor."""
+    """Global Lax-Friedrichs speeds (alpha_x, alpha_y) of the splitting in Section 2.1,
+    as a float64 device tensor."""
     _require(S, prob, prob.nf, "state")
     a = out if out is not None else torch.zeros(2, dtype=torch.float64, device=S.device)
     _check(lib().hweno_alpha(ctypes.byref(prob.c()), _ptr(S), _ptr(a), _stream()), "hweno_alpha")
@@ -221,7 +222,9 @@ def alpha(S: torch.Tensor, prob: Problem, out: Optional[torch.Tensor] = None) ->
 
 def rhs(S: torch.Tensor, prob: Problem, alpha_: Optional[torch.Tensor] = None,
         out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Semi-discrete right-hand side L(S); speeds computed from S unless given."""
+    """Semi-discrete right-hand side L(S) of eqs. (odeH) / (ode2H): flux differences of the
+    nonlinear HWENO flux (Section 2.1, characteristic-wise for Euler per Remarks 2.1-2.2)
+    and of the linear derivative and mixed fluxes; speeds computed from S unless given."""
     _require(S, prob, prob.nf, "state")
     L = out if out is not None else torch.empty_like(S)
     if alpha_ is None:
@@ -236,7 +239,8 @@ def rhs(S: torch.Tensor, prob: Problem, alpha_: Optional[torch.Tensor] = None,
 
 
 def limit(S: torch.Tensor, prob: Problem, out: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """Limited derivatives (U_x along x [, U_y along y]): m * dim fields."""
+    """Limited derivatives of the HWENO limiter (Section 2.2): U_x along x [, U_y along y],
+    m * dim fields."""
     _require(S, prob, prob.nf, "state")
     ny = prob.ny if prob.dim == 2 else 1
     D = out if out is not None else torch.empty((prob.m * prob.dim, ny, prob.nx),
@@ -268,7 +272,8 @@ class Stepper:
 
     def step(self, S: torch.Tensor, dt: Optional[float] = None, t_end: Optional[float] = None,
              tape: Optional[torch.Tensor] = None, replay: Optional[torch.Tensor] = None):
-        """One SSP-RK3 step of S in place (device-side dt unless ``dt`` is given)."""
+        """One SSP-RK3 step of S in place (Section 2.2: the limited derivatives enter the
+        stage combinations only); device-side CFL dt unless ``dt`` is given."""
         _require(S, self.prob, self.prob.nf, "state")
         for t, name in ((tape, "tape"), (replay, "replay")):
             if t is not None and (t.dtype != torch.float64 or t.numel() < CTRL_LEN or not t.is_cuda):
@@ -488,7 +493,8 @@ def adjoint_workspace(prob: Problem, device="cuda") -> torch.Tensor:
 def rhs_adjoint(S: torch.Tensor, prob: Problem, alpha_: torch.Tensor, lam_rhs: torch.Tensor,
                 lam_lim: Optional[torch.Tensor] = None, lam_state: Optional[torch.Tensor] = None,
                 ws: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim with the speeds frozen."""
+    """lam_state += (dL/dS)^T lam_rhs + (dLim/dS)^T lam_lim with the speeds frozen: the
+    transpose of the operator of eqs. (odeH) / (ode2H) and of the Section 2.2 limiter."""
     _require(S, prob, prob.nf, "state")
     _require(lam_rhs, prob, prob.nf, "lam_rhs")
     if lam_lim is not None:
