@@ -408,3 +408,39 @@ def test_full_size_quadrants_sampled(n, dtype):
     S1 = S0.clone()
     h.Stepper(prob).step(S1)
     assert torch.equal(S1, Sg)
+
+
+def test_state_beyond_32_bit_element_indices():
+    """16384^2 FP32 2D Euler: 12 fields of 2^28 cells are 3.2e9 elements (12.9 GB per
+    state), so field offsets pass 2^31; windows at the domain's far corner, in the
+    last field, are checked against the oracle like the smaller full-size cases.
+    The state is built on the device from the four quadrant states of the same
+    generator (its 2 x 2 version), which avoids a 26 GB host array."""
+    n = 16384
+    small = hi.euler2d_quadrants(2, 2, 0)
+    announce("beyond 32-bit indices", n)
+    idx = (torch.arange(n, device="cuda") >= n // 2).long()
+    S0 = torch.as_tensor(small.S, dtype=torch.float32).cuda()[:, idx][:, :, idx].contiguous()
+    assert S0.numel() > 2 ** 31
+    Sg = S0.clone()
+    prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=torch.float32, dx=1.0 / n,
+                     dy=1.0 / n, bc_x=h.OUTFLOW, bc_y=h.OUTFLOW)
+    st = h.Stepper(prob)
+    st.step(Sg)
+    ctrl = st.ctrl.cpu()
+    assert int(ctrl[8:9].view(torch.int64)) == 0
+    alphas = [(float(ctrl[2 * q]), float(ctrl[2 * q + 1])) for q in range(3)]
+    dt = float(ctrl[6])
+    w = hi.Workload(small.S, 2, "euler", 1.0 / n, 1.0 / n, hi.OUTFLOW, hi.OUTFLOW)
+    half, m, k = n // 2, 8, 24
+    for (j, i) in [(half - k // 2, half - k // 2), (n - k, n - k), (0, n - k), (n - k, 0)]:
+        j0, j1 = max(j - m, 0), min(j + k + m, n)
+        i0, i1 = max(i - m, 0), min(i + k + m, n)
+        Sw = P.exact_input(P.window(S0, j0, j1, i0, i1))
+        ref = P.oracle_window_step(Sw, w, alphas, dt)
+        got = P.window(Sg, j0, j1, i0, i1).cpu()
+        sj, si = j - j0, i - i0
+        errs = P.step_errors(got[:, sj:sj + k, si:si + k], ref[:, sj:sj + k, si:si + k], w)
+        P.assert_within(errs, P.TOL[torch.float32], f"window {(j, i)} of {n}^2")
+    del S0, Sg, st
+    torch.cuda.empty_cache()
