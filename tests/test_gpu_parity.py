@@ -329,6 +329,57 @@ def test_graph_captured_steps_equal_eager_steps(case):
     assert float(sg.ctrl[9]) == 12.0
 
 
+def _transpose_euler(S):
+    """Swap x and y: transpose the grids, swap the two momenta and the U_x / U_y blocks."""
+    perm = [0, 2, 1, 3]
+    return torch.cat([S[0:4][perm], S[8:12][perm], S[4:8][perm]]).transpose(1, 2).contiguous()
+
+
+@pytest.mark.parametrize("bc", [hi.PERIODIC, hi.OUTFLOW, hi.REFLECT])
+def test_transpose_symmetry_on_the_gpu(bc):
+    """Swapping x and y (grids, momenta, derivative blocks, dx <-> dy) transposes the GPU's
+    right-hand side and its step; the x and y passes run in a fixed order, so agreement
+    is to rounding, not bitwise."""
+    w = hi.euler2d_rough(45, 31, 12, bc=bc)
+    announce("transpose", bc)
+    S = P.to_gpu(w, torch.float64)
+    ST = _transpose_euler(S)
+    prob = h.Problem(dim=2, nx=45, ny=31, physics="euler", dtype=torch.float64, dx=0.07, dy=0.05,
+                     bc_x=bc, bc_y=bc)
+    probT = h.Problem(dim=2, nx=31, ny=45, physics="euler", dtype=torch.float64, dx=0.05, dy=0.07,
+                      bc_x=bc, bc_y=bc)
+    L = h.rhs(S, prob)
+    LT = h.rhs(ST, probT)
+    scale = float(L.abs().max())
+    assert float((LT - _transpose_euler(L)).abs().max()) <= 1e-12 * scale
+    st, stT = h.Stepper(prob), h.Stepper(probT)
+    st.step(S)
+    stT.step(ST)
+    assert abs(float(st.ctrl[6]) - float(stT.ctrl[6])) <= 1e-14 * float(st.ctrl[6])
+    assert float((ST - _transpose_euler(S)).abs().max()) <= 1e-12 * float(S.abs().max())
+
+
+def test_graph_replay_after_a_state_reset_repeats_itself():
+    """Resetting the state and the control block between replays of one captured graph
+    gives the same result every time (nothing is cached across replays)."""
+    w = CASES["euler2d_quadrants_70x45"]()
+    announce("graph replay after reset")
+    prob = P.gpu_problem(w, torch.float64)
+    S0 = P.to_gpu(w, torch.float64)
+    S = S0.clone()
+    st = h.Stepper(prob)
+    st.capture(S, steps=2)
+    outs = []
+    for r in range(3):
+        S.copy_(S0)
+        st.ctrl.zero_()
+        st.replay()
+        torch.cuda.synchronize()
+        outs.append((S.clone(), st.ctrl[:10].clone()))
+    for r in (1, 2):
+        assert torch.equal(outs[r][0], outs[0][0]) and torch.equal(outs[r][1], outs[0][1]), r
+
+
 def test_tape_and_replay_reproduce_the_step():
     w = hi.euler2d_rough(45, 38, 12)
     announce("tape/replay")
