@@ -299,8 +299,9 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the design note describes how the path would shard).", file=sys.stderr)
+        print("bench.py: the L-HWENO path runs on one GPU; multi-GPU runs are not supported "
+              "(sharding a grid needs a halo exchange and a speed all-reduce per stage, which "
+              "are not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch
