@@ -78,8 +78,8 @@ typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1, HWENO_BC_REFLECT = 2
  *                 paper does not say how its limiter treats systems): the
  *                 stencil of each cell is projected on the characteristic
  *                 fields of the cell's own state, limited field by field and
- *                 mapped back.  The adjoint entry points return
- *                 HWENO_ERR_UNSUPPORTED for it.  Ignored for scalars.
+ *                 mapped back (the adjoint entry points differentiate
+ *                 it too).  Ignored for scalars.
  *  dx, dy         cell sizes (> 0; dy ignored in 1D).
  *  gamma_gas      ratio of specific heats (> 1; Euler only).
  *  adv_speed      (a_x, a_y) for LINADV.
@@ -185,8 +185,7 @@ size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob);
  * evaluated at `state`.  The absolute values in tau are differentiated as
  * sign(x) with sign(0) = 0; ghost cells are differentiated through the
  * boundary index maps (periodic wrap, outflow copy, reflection with the
- * wall's sign flips).  HWENO_ERR_UNSUPPORTED for the characteristic limiter
- * variant with the limiter on.
+ * wall's sign flips).
  * alpha: device double[2], the speeds of the forward evaluation (replayed).
  * lam_rhs: nf fields; lam_lim: m * dim fields (limited-derivative layout of
  * hweno_limit) or NULL; lam_state: nf fields, accumulated into.  lam_state
@@ -205,9 +204,7 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state,
  * the next step on it); tape: device double[HWENO_CTRL_LEN] (as written by
  * hweno_rk3_step); ws: >= hweno_adjoint_workspace_bytes(prob) bytes.
  * lam, state0, step_ws and ws must not overlap (2D grids finish most cells
- * of each stage's adjoint in the kernel that reads the stage's inputs).
- * HWENO_ERR_UNSUPPORTED for the characteristic limiter variant with the
- * limiter on. */
+ * of each stage's adjoint in the kernel that reads the stage's inputs). */
 hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state0,
                                     const void* step_ws, size_t step_ws_bytes,
                                     const double* tape, void* lam, void* ws,

@@ -370,6 +370,51 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
   side(UR, irR, sR, uR, tR, pR, wR, gsR, gUR);
 }
 
+// reverse of limit_char(): the adjoint gout of the limited derivative (normal
+// frame) is mapped back through the right eigenvectors, the scalar limiters of
+// the characteristic fields, the left-eigenvector projections of the five
+// stencil vectors, and the cell's eigen-system.  That eigen-system is the Roe
+// average of the cell with itself, so reversing roe() with both sides equal to
+// u0 (both contributions into gu0) differentiates it exactly.  Results are
+// accumulated into gum, gu0, gup, gvm, gvp.
+template <typename T, int M>
+HW_HD void limit_char_vjp(const T* um, const T* u0, const T* up, const T* vm, const T* vp, T h,
+                          T ih, const Weights<T>& w, T gm1, const T* gout, T* gum, T* gu0,
+                          T* gup, T* gvm, T* gvp) {
+  Eigen<T, M> e;
+  e.cell(u0, gm1);
+  T a[M], b[M], c[M], dm[M], dp[M], z[M];
+  e.project(um, a);
+  e.project(u0, b);
+  e.project(up, c);
+  e.project(vm, dm);
+  e.project(vp, dp);
+#pragma unroll
+  for (int q = 0; q < M; ++q) z[q] = limit1(a[q], b[q], c[q], dm[q], dp[q], h, ih, w);
+  EigenAdj<T> ge;
+  T gz[M];
+  back_T(e, gout, gz);
+  back_eigen_adj(e, z, gout, ge);
+  T ga[M], gb[M], gc[M], gdm[M], gdp[M];
+#pragma unroll
+  for (int q = 0; q < M; ++q) {
+    ga[q] = gb[q] = gc[q] = gdm[q] = gdp[q] = T(0);
+    limit1_vjp(a[q], b[q], c[q], dm[q], dp[q], h, ih, w, gz[q], ga[q], gb[q], gc[q], gdm[q], gdp[q]);
+  }
+  T gx[M];
+  auto add = [&](const T* x, const T* gw, T* out) {
+    project_vjp(e, x, gw, gx, ge);
+#pragma unroll
+    for (int q = 0; q < M; ++q) out[q] += gx[q];
+  };
+  add(um, ga, gum);
+  add(u0, gb, gu0);
+  add(up, gc, gup);
+  add(vm, gdm, gvm);
+  add(vp, gdp, gvp);
+  roe_vjp<T, M>(u0, u0, gm1, ge, gu0, gu0);
+}
+
 // ---------------------------------------------------------------------------
 // VJP of interface_fluxes(): given the adjoints of f-hat, h-hat and the mixed
 // flux (normal frame), emit(s, mode, gU, gDn, gDt) receives adjoint

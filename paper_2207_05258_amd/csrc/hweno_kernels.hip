@@ -866,7 +866,8 @@ constexpr int cmax(int x, int y) { return x > y ? x : y; }
 // of each output entry gathers the slots that point at it.  The state tile is
 // staged cell-interleaved ([row][col][field]) so that one stencil point's
 // fields are read with a few wide LDS loads.
-template <typename T, int PHYS, int DIM, int TX, int TY, int NT>
+// CL: the characteristic limiter variant (Euler), a separate instantiation.
+template <typename T, int PHYS, int DIM, int TX, int TY, int NT, bool CL>
 __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, Consts<T> k) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
@@ -1057,18 +1058,44 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
       const int j = ry0 + r, C = rx0 - 1 + ii;
       const bool live = j >= 0 && j < ny && C >= 0 && C < nx;
       const T* p = live ? cell(C, j) : sm;
+      if constexpr (CL && PHYS == PH_EULER) {
+        T mu[M], g[5][M];
+        bool any = false;
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        const T mu = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
-        T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
-        if (mu != T(0))
-          limit1_vjp(p[-NF + c], p[c], p[NF + c], p[-NF + M + c], p[NF + M + c], hx, idx, k.lw,
-                     mu, g0, g1, g2, g3, g4);
-        gb[(0 * M + c) * NLX + q] = g0;
-        gb[(1 * M + c) * NLX + q] = g1;
-        gb[(2 * M + c) * NLX + q] = g2;
-        gb[(3 * M + c) * NLX + q] = g3;
-        gb[(4 * M + c) * NLX + q] = g4;
+        for (int c = 0; c < M; ++c) {
+          mu[c] = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
+          any = any || mu[c] != T(0);
+#pragma unroll
+          for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
+        }
+        if (any) {
+          T um[M], u0[M], up[M], vm[M], vp[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            um[c] = p[-NF + c], u0[c] = p[c], up[c] = p[NF + c];
+            vm[c] = p[-NF + M + c], vp[c] = p[NF + M + c];
+          }
+          limit_char_vjp<T, M>(um, u0, up, vm, vp, hx, idx, k.lw, k.gm1, mu, g[0], g[1], g[2],
+                               g[3], g[4]);
+        }
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+#pragma unroll
+          for (int s5 = 0; s5 < 5; ++s5) gb[(s5 * M + c) * NLX + q] = g[s5][c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const T mu = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
+          T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
+          if (mu != T(0))
+            limit1_vjp(p[-NF + c], p[c], p[NF + c], p[-NF + M + c], p[NF + M + c], hx, idx, k.lw,
+                       mu, g0, g1, g2, g3, g4);
+          gb[(0 * M + c) * NLX + q] = g0;
+          gb[(1 * M + c) * NLX + q] = g1;
+          gb[(2 * M + c) * NLX + q] = g2;
+          gb[(3 * M + c) * NLX + q] = g3;
+          gb[(4 * M + c) * NLX + q] = g4;
+        }
       }
     }
     __syncthreads();
@@ -1091,18 +1118,49 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
         const bool live = i >= 0 && i < nx && C >= 0 && C < ny;
         const T* p = live ? cell(i, C) : sm;
         constexpr int S = W * NF;
+        if constexpr (CL && PHYS == PH_EULER) {
+          // normal frame: the two momenta swap places (as in the forward)
+          T mu[M], g[5][M];
+          bool any = false;
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-          const T mu = live ? cl * a.XM[(M + c) * fs + (long long)C * nx + i] : T(0);
-          T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
-          if (mu != T(0))
-            limit1_vjp(p[-S + c], p[c], p[S + c], p[-S + 2 * M + c], p[S + 2 * M + c], hy, idy,
-                       k.lw, mu, g0, g1, g2, g3, g4);
-          gb[(0 * M + c) * NLY + q] = g0;
-          gb[(1 * M + c) * NLY + q] = g1;
-          gb[(2 * M + c) * NLY + q] = g2;
-          gb[(3 * M + c) * NLY + q] = g3;
-          gb[(4 * M + c) * NLY + q] = g4;
+          for (int c = 0; c < M; ++c) {
+            const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
+            mu[c] = live ? cl * a.XM[(M + qc) * fs + (long long)C * nx + i] : T(0);
+            any = any || mu[c] != T(0);
+#pragma unroll
+            for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
+          }
+          if (any) {
+            T um[M], u0[M], up[M], vm[M], vp[M];
+#pragma unroll
+            for (int c = 0; c < M; ++c) {
+              const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
+              um[c] = p[-S + qc], u0[c] = p[qc], up[c] = p[S + qc];
+              vm[c] = p[-S + 2 * M + qc], vp[c] = p[S + 2 * M + qc];
+            }
+            limit_char_vjp<T, M>(um, u0, up, vm, vp, hy, idy, k.lw, k.gm1, mu, g[0], g[1], g[2],
+                                 g[3], g[4]);
+          }
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
+#pragma unroll
+            for (int s5 = 0; s5 < 5; ++s5) gb[(s5 * M + qc) * NLY + q] = g[s5][c];
+          }
+        } else {
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            const T mu = live ? cl * a.XM[(M + c) * fs + (long long)C * nx + i] : T(0);
+            T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
+            if (mu != T(0))
+              limit1_vjp(p[-S + c], p[c], p[S + c], p[-S + 2 * M + c], p[S + 2 * M + c], hy, idy,
+                         k.lw, mu, g0, g1, g2, g3, g4);
+            gb[(0 * M + c) * NLY + q] = g0;
+            gb[(1 * M + c) * NLY + q] = g1;
+            gb[(2 * M + c) * NLY + q] = g2;
+            gb[(3 * M + c) * NLY + q] = g3;
+            gb[(4 * M + c) * NLY + q] = g4;
+          }
         }
       }
       __syncthreads();
@@ -1653,7 +1711,14 @@ struct RunAdj {
     a.fo = fo;
     constexpr int TX = AdjTile<DIM>::TX, TY = AdjTile<DIM>::TY, NT = AdjTile<DIM>::NT;
     const unsigned tiles = (unsigned)(((L.nxe + TX - 1) / TX) * ((L.nye + TY - 1) / TY));
-    timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+    if constexpr (PHYS == PH_EULER) {
+      if (char_limiter(p))
+        timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT, true><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+      else
+        timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT, false><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+    } else {
+      timed(s, [&] { k_adjoint<T, PHYS, DIM, TX, TY, NT, false><<<tiles, NT, 0, s>>>(a, make_consts<T>(p)); });
+    }
     if (a.fused) {
       const long long nb = (4ll * a.ny + 4ll * (a.nx - 4)) * fo.nf;
       k_fold_band<T><<<(unsigned)((nb + 255) / 256), 256, 0, s>>>(fo);
@@ -1869,8 +1934,6 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, con
                                size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
-  if (prob->physics == HWENO_EULER && prob->limiter_on && prob->limiter_characteristic)
-    return fail(HWENO_ERR_UNSUPPORTED, "the adjoint of the characteristic limiter is not implemented");
   if (empty(prob)) return ok();
   if (!state || !alpha || !lam_rhs || !lam_state || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state, alpha, lam_rhs, lam_state and ws must be non-NULL");
@@ -1888,8 +1951,6 @@ hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state
                                     void* lam, void* ws, size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
-  if (prob->physics == HWENO_EULER && prob->limiter_on && prob->limiter_characteristic)
-    return fail(HWENO_ERR_UNSUPPORTED, "the adjoint of the characteristic limiter is not implemented");
   if (empty(prob)) return ok();
   if (!state0 || !step_ws || !tape || !lam || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state0, step_ws, tape, lam and ws must be non-NULL");

@@ -156,6 +156,56 @@ def test_step_adjoint_matches_oracle_autograd(case, limiter_on):
     assert rel_err(got, ref) < 1e-11, rel_err(got, ref)
 
 
+CHAR_LIM = ["euler2d_rough_outflow_33x21", "euler2d_rough_periodic_20x37", "euler1d_piecewise_301",
+            "euler2d_rough_reflect_26x19", "euler1d_piecewise_reflect_150"]
+
+
+@pytest.mark.parametrize("case", CHAR_LIM)
+def test_rhs_adjoint_characteristic_limiter(case):
+    """The limiter variant on characteristic fields, differentiated through the cell's
+    eigen-system, against autograd through the oracle's variant."""
+    w = CASES[case]()
+    announce("rhs adjoint characteristic limiter", case)
+    Sg = P.to_gpu(w, torch.float64)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, torch.float64, limiter_characteristic=True)
+    op = P.oracle_problem(w, limiter_characteristic=True)
+    alpha = o.max_speeds(S, op)
+    mu_L, mu_lim = _mus(w, 21)
+    ref = oracle_rhs_vjp(S, op, alpha, mu_L, mu_lim)
+    got = h.rhs_adjoint(Sg, prob, torch.tensor(alpha, dtype=torch.float64), mu_L.cuda(), mu_lim.cuda())
+    assert rel_err(got, ref) < 1e-11, rel_err(got, ref)
+    # the limiter term alone
+    zero = torch.zeros_like(mu_L)
+    ref3 = oracle_rhs_vjp(S, op, alpha, zero, mu_lim)
+    got3 = h.rhs_adjoint(Sg, prob, torch.tensor(alpha, dtype=torch.float64), zero.cuda(), mu_lim.cuda())
+    assert rel_err(got3, ref3) < 1e-11, rel_err(got3, ref3)
+
+
+@pytest.mark.parametrize("case", ["euler2d_rough_outflow_33x21", "euler1d_piecewise_301",
+                                  "euler2d_rough_reflect_26x19", "euler2d_rough_periodic_4x4",
+                                  "euler2d_rough_reflect_4x6"])
+def test_step_adjoint_characteristic_limiter(case):
+    w = (CASES.get(case) or TINY[case])()
+    announce("step adjoint characteristic limiter", case)
+    Sg = P.to_gpu(w, torch.float64)
+    S0 = Sg.clone()
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, torch.float64, limiter_characteristic=True)
+    op = P.oracle_problem(w, limiter_characteristic=True)
+    st = h.Stepper(prob)
+    tape = torch.zeros(h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    st.step(Sg, tape=tape)
+    tp = tape.cpu()
+    alphas = [(float(tp[0]), float(tp[1])), (float(tp[2]), float(tp[3])),
+              (float(tp[4]), float(tp[5]))]
+    lam = torch.randn(Sg.shape, dtype=torch.float64, generator=torch.Generator().manual_seed(6))
+    ref = oracle_step_vjp(S, op, alphas, float(tp[6]), lam)
+    got = lam.clone().cuda()
+    h.step_adjoint(prob, S0, st, tape, got, h.adjoint_workspace(prob))
+    assert rel_err(got, ref) < 1e-11, rel_err(got, ref)
+
+
 def _loss(S, target, dx, dy):
     return 0.5 * dx * dy * ((S[0] - target[0]) ** 2).sum()
 
