@@ -441,9 +441,10 @@ def autotune_batched(stepper: BatchedStepper, trials: int = 2):
 
     Runs on clones of the states (the originals are untouched), keeps the
     fastest configuration in ``stepper`` and in a process-wide cache keyed by
-    the batch's dtype, instance count and total cell count.
+    the batch's dtype and its instances' shapes and boundary conditions.
     """
-    key = (stepper.common.dtype, stepper.n, stepper.cells)
+    key = (stepper.common.dtype,
+           tuple((int(I.nx), int(I.ny), int(I.bc_x), int(I.bc_y)) for I in stepper._host))
     if key in _AUTOTUNE_CACHE:
         stepper.variant, stepper.blocks = _AUTOTUNE_CACHE[key]
         return _AUTOTUNE_CACHE[key], None
