@@ -378,7 +378,9 @@ def main():
     }
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n, args.cpu_n1)
     out = {
-        "metric": "2D Euler HWENO cell-stage updates/s",
+        # value: the cell-stage rate; the %HBM roofline is roofline.hbm_frac, and the
+        # adjoint/forward time is adjoint.backward_over_forward
+        "metric": "2D Euler HWENO cell-stage updates/s + %HBM roofline; adjoint/forward time",
         "value": main_run["rate"],
         "unit": "cell-stage updates/s",
         "n_gpus": 1,

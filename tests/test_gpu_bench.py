@@ -31,6 +31,8 @@ def test_bench_reduced_run_prints_one_valid_json_line():
         assert k in d, k
     assert d["n_gpus"] == 1 and d["steps"] == 3 and d["warmup"] == 1 and d["dtype"] == "f64"
     assert d["value"] > 0 and d["status_word"] == 0 and "workload" in d["config"]
+    assert d["metric"].startswith("2D Euler HWENO cell-stage updates/s")
+    assert 0 < d["roofline"]["hbm_frac"] < 1 and d["adjoint"]["backward_over_forward"] > 0
     rf = d["roofline"]
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
