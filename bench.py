@@ -39,8 +39,8 @@ PEAK_HBM_GBS = 8000.0
 FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 
 # HBM traffic of one stage-kernel launch from rocprofv3 --pmc FETCH_SIZE /
-# WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the SHA-256 of the
-# kernel sources it was measured on (stale entries are reported as null).
+# WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the hash of the built
+# device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
     ("245d6bd5ec91c589", "f64", 4096): 5.0829e+09,
