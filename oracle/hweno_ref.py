@@ -28,10 +28,19 @@ Readings of passages the paper leaves open (each listed in the design notes):
     ``Euler.right_eigenvectors``; L = R^{-1} by a numerical inverse; both the
     split fluxes and the split derivative fluxes are projected.
   * The limiter acts component by component on the conserved variables:
-    U_x along x, U_y along y.
+    U_x along x, U_y along y.  An optional variant (``limiter_characteristic``)
+    limits the characteristic fields of each cell's own state instead.
   * The mixed fluxes use the step sizes of eq. (ode2H): the y-differences of
     xi-hat are divided by dy and the x-differences of eta-hat by dx.
   * Outflow boundaries copy the nearest interior value of every field.
+  * Reflecting walls (Euler, Example 3.7) fill ghost cells with the mirror
+    image of the interior, with the wall-normal momentum and the derivatives
+    along the wall normal negated.
+
+Parity unpinned (documented choices with nothing in the paper to check them
+against): the component-wise limiter for systems and the outflow copy of the
+derivative fields.  The characteristic limiter variant is pinned only through
+its special cases (linear weights, data along one eigenvector).
 """
 from __future__ import annotations
 
