@@ -139,3 +139,37 @@ def test_limiter_ablation_table5():
     assert 0.1 < l1_320 / p1 < 10 and 0.1 < li_320 / pi < 10, (l1_320, p1, li_320, pi)
     _, with_lim = _errs("table4", (320,))
     assert with_lim[0][0] < 1e-3 * l1_320     # the limiter keeps the run stable
+
+
+def test_linear_advection_as_configured_sits_on_the_rk3_floor():
+    """1D linear advection, u0 = 0.5 + sin(pi x) on periodic [0, 2], CFL 0.6 with dt
+    proportional to dx (not the accuracy scaling), T = 2, N = 50..400: the time error
+    of SSP-RK3 dominates, so the GPU's error equals the closed form |G(z)^n - e^{-i pi T}|
+    with G(z) = 1 + z + z^2/2 + z^3/6, z = -i pi dt (last step clipped), within 5 %,
+    and falls at third order."""
+    errs = {}
+    for n in (50, 100, 200, 400):
+        w = hi.scalar_sine_1d(n, "linadv")
+        announce("linear advection as configured", n)
+        prob = P.gpu_problem(w, torch.float64, cfl=0.6)
+        S = P.to_gpu(w, torch.float64)
+        st = h.Stepper(prob)
+        while st.t < 2.0 * (1 - 1e-13):
+            for _ in range(64):
+                st.step(S, t_end=2.0)
+        assert st.status & ~h.hweno.ST_SKIPPED == 0
+        x = _x(n, 0, 2)
+        err = float(np.abs(S[0, 0].cpu().numpy() - (0.5 + np.sin(np.pi * (x - 2.0)))).max())
+        dt = 0.6 * w.dx
+        full = int(np.floor(2.0 / dt + 1e-9))
+        last = 2.0 - full * dt
+
+        def G(hh):
+            z = -1j * np.pi * hh
+            return 1 + z + z * z / 2 + z ** 3 / 6
+        amp = G(dt) ** full * (G(last) if last > 1e-12 else 1.0)
+        floor = abs(amp - np.exp(-1j * np.pi * 2.0))
+        assert 0.95 < err / floor < 1.05, (n, err, floor)
+        errs[n] = err
+    for a, b in ((50, 100), (100, 200), (200, 400)):
+        assert 2.9 < math.log2(errs[a] / errs[b]) < 3.1, errs
