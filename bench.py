@@ -43,16 +43,16 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("245d6bd5ec91c589", "f64", 4096): 5.0829e+09,
-    ("245d6bd5ec91c589", "f32", 4096): 2.6241e+09,
+    ("53dfb49246a5456c", "f64", 4096): 5.0834e+09,
+    ("53dfb49246a5456c", "f32", 4096): 2.6243e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("245d6bd5ec91c589", "f64", 4096): 1.040e9,
-    ("245d6bd5ec91c589", "f32", 4096): 9.209e8,
+    ("53dfb49246a5456c", "f64", 4096): 1.040e9,
+    ("53dfb49246a5456c", "f32", 4096): 9.209e8,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
 # lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
