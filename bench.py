@@ -43,16 +43,16 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("53dfb49246a5456c", "f64", 4096): 5.0834e+09,
-    ("53dfb49246a5456c", "f32", 4096): 2.6243e+09,
+    ("8707460b60ca9aae", "f64", 4096): 5.0833e+09,
+    ("8707460b60ca9aae", "f32", 4096): 2.6249e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("53dfb49246a5456c", "f64", 4096): 1.040e9,
-    ("53dfb49246a5456c", "f32", 4096): 9.209e8,
+    ("8707460b60ca9aae", "f64", 4096): 1.040e9,
+    ("8707460b60ca9aae", "f32", 4096): 9.207e8,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
 # lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
@@ -124,8 +124,7 @@ def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
     prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=dtype, dx=1.0 / n, dy=1.0 / n,
                      bc_x=h.OUTFLOW, bc_y=h.OUTFLOW)
     st = h.Stepper(prob)
-    for _ in range(warmup):
-        st.step(S)
+    st.steps(S, warmup)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -134,8 +133,7 @@ def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
-    for _ in range(steps):
-        st.step(S)
+    st.steps(S, steps)      # one call: each step's stage-1 speeds come from the step before
     e1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -191,8 +189,9 @@ def run_batched(steps: int, warmup: int, n_inst: int = 256, seed: int = 0):
 
 def run_small(n: int = 4000, steps: int = 200):
     """A 1D Euler grid of n cells (piecewise-constant data, periodic, FP64), where a step
-    is a few microseconds of GPU work: eager steps against the same steps captured in
-    one graph and replayed."""
+    is a few microseconds of GPU work: eager single-step calls, one multi-step call
+    (no separate speed pass after the first step), and those single steps captured
+    in one graph and replayed."""
     import torch
 
     import hweno_inputs as hi
@@ -210,6 +209,10 @@ def run_small(n: int = 4000, steps: int = 200):
         st.step(S)
     torch.cuda.synchronize()
     eager = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    st.steps(S, steps)
+    torch.cuda.synchronize()
+    multi = time.perf_counter() - t0
     st.capture(S, steps=steps)
     st.replay()
     torch.cuda.synchronize()
@@ -218,7 +221,8 @@ def run_small(n: int = 4000, steps: int = 200):
     torch.cuda.synchronize()
     graph = time.perf_counter() - t0
     return {"workload": f"1D Euler, {n} cells, FP64", "steps": steps,
-            "eager_us_per_step": eager * 1e6 / steps, "graph_us_per_step": graph * 1e6 / steps,
+            "eager_us_per_step": eager * 1e6 / steps, "multi_step_call_us_per_step": multi * 1e6 / steps,
+            "graph_us_per_step": graph * 1e6 / steps,
             "graph_value": n * 3 * steps / graph, "unit": "cell-stage updates/s",
             "status": st.status}
 

@@ -174,6 +174,19 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws,
                             size_t ws_bytes, double dt_fixed, double t_end,
                             double* tape, const double* replay, void* stream);
 
+/* n_steps consecutive SSP-RK3 steps of `state` in one call, each exactly as
+ * hweno_rk3_step with the same dt_fixed and t_end (no replay).  Between the
+ * steps of one call nothing else touches the state, so the stage-1 speeds of
+ * step k+1 are folded by step k's third stage (which already evaluates every
+ * new cell) instead of by a separate pass over the state: the results, the
+ * control block and the tapes are bitwise those of n_steps single calls.
+ * Uses control-block entries [10..11] as scratch.  tapes: device
+ * double[n_steps][HWENO_CTRL_LEN] (one record per step, as `tape` of
+ * hweno_rk3_step) or NULL.  n_steps >= 0. */
+hweno_status hweno_rk3_steps(const hweno_problem* prob, void* state, void* ws, size_t ws_bytes,
+                             int32_t n_steps, double dt_fixed, double t_end, double* tapes,
+                             void* stream);
+
 /* Bytes of device workspace the adjoint entry points need for `prob`
  * (a ghost-padded adjoint buffer and three stage adjoints).  0 if invalid. */
 size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob);

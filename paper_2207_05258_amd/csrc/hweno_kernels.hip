@@ -49,6 +49,7 @@ struct StageArgs {
   double dx, dy;
   double dt_fixed, t_end, cfl;
   int replay;
+  int fold_next;      // stage 3 folds the new state's speeds into ctrl[10..11]
 };
 
 __device__ __forceinline__ int map_index(int i, int n, int bc) {
@@ -541,9 +542,10 @@ __global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs
   stage_tile<T, PHYS, DIM, K, TX, TY, NT, CL>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
                                               flags);
   if constexpr (K > 0) {
-    // speeds of the new stage state feed the next stage's splitting
-    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + 2 * K, a.status,
-                   K < 3 && !a.replay);
+    // speeds of the new stage state feed the next stage's splitting; after
+    // stage 3 they are the next step's stage-1 speeds (multi-step calls)
+    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + (K < 3 ? 2 * K : 10), a.status,
+                   !a.replay && (K < 3 || a.fold_next));
   }
 }
 
@@ -1219,13 +1221,20 @@ __global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, long lon
   block_fold<256>(double(mx), double(my), flags, alpha, status, true);
 }
 
-__global__ void k_begin(double* ctrl, const double* replay) {
+// Start of a step: stage speeds from the replay record, or cleared for the
+// speed reduction, or (take_next) stage-1 speeds from what the previous step's
+// stage 3 folded into ctrl[10..11]; those slots are then cleared for this
+// step's stage 3.
+__global__ void k_begin(double* ctrl, const double* replay, int take_next) {
   const int t = threadIdx.x;
+  const double nxt = (take_next && t < 2) ? ctrl[10 + t] : 0.0;
+  __syncthreads();
   if (replay) {
     if (t < 7) ctrl[t] = replay[t];
   } else if (t < 6) {
-    ctrl[t] = 0.0;
+    ctrl[t] = nxt;
   }
+  if (t == 10 || t == 11) ctrl[t] = 0.0;
 }
 
 __global__ void k_zero(double* p, int n) {
@@ -1237,6 +1246,11 @@ __global__ void k_finish(double* ctrl, double* tape) {
     if (ctrl[6] > 0.0) {
       ctrl[7] += ctrl[6];
       ctrl[9] += 1.0;
+    } else {
+      // skipped step: the state is unchanged, so the next step's stage-1
+      // speeds (taken from ctrl[10..11] in multi-step calls) are this step's
+      ctrl[10] = ctrl[0];
+      ctrl[11] = ctrl[1];
     }
     if (tape) {
       for (int q = 0; q < 10; ++q) tape[q] = ctrl[q];
@@ -1596,15 +1610,18 @@ struct RunLimit {
 
 struct RunStep {
   template <typename T, int PHYS, int DIM>
+  // take_next: stage-1 speeds come from the previous step's stage 3 (the state
+  // has not changed since); fold_next: this step's stage 3 provides them
   static hweno_status run(const hweno_problem* p, void* state, void* ws, double dt_fixed,
-                          double t_end, double* tape, const double* replay, hipStream_t s) {
+                          double t_end, double* tape, const double* replay, bool take_next,
+                          bool fold_next, hipStream_t s) {
     const WsLayout L = ws_layout(p);
     char* w = (char*)ws;
     double* ctrl = (double*)(w + L.ctrl);
     const long long n = cells_of(p);
     const Consts<T> k = make_consts<T>(p);
-    k_begin<<<1, 64, 0, s>>>(ctrl, replay);
-    if (!replay) {
+    k_begin<<<1, 64, 0, s>>>(ctrl, replay, take_next && !replay ? 1 : 0);
+    if (!replay && !take_next) {
       k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>(
           (const T*)state, n, k, ctrl, (unsigned long long*)(ctrl + 8));
     }
@@ -1616,6 +1633,7 @@ struct RunStep {
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
     a.replay = replay ? 1 : 0;
+    a.fold_next = (fold_next && !replay) ? 1 : 0;
     T* s1 = (T*)(w + L.s1);
     T* s2 = (T*)(w + L.s2);
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
@@ -1924,8 +1942,32 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws, si
   if (((uintptr_t)ws & 255u) != 0) return fail(HWENO_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
     return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
-  st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end, tape, replay, (hipStream_t)stream);
+  st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end, tape, replay, false, false,
+                         (hipStream_t)stream);
   if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_rk3_steps(const hweno_problem* prob, void* state, void* ws, size_t ws_bytes,
+                             int32_t n_steps, double dt_fixed, double t_end, double* tapes,
+                             void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (n_steps < 0) return fail(HWENO_ERR_INVALID_ARG, "n_steps must be >= 0");
+  if (empty(prob) || n_steps == 0) return ok();
+  if (!state || !ws) return fail(HWENO_ERR_INVALID_ARG, "state and ws must be non-NULL");
+  const size_t need = ws_layout(prob).total;
+  if (ws_bytes < need)
+    return fail(HWENO_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  if (((uintptr_t)ws & 255u) != 0) return fail(HWENO_ERR_WORKSPACE, "workspace must be 256-byte aligned");
+  if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
+    return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
+  for (int32_t q = 0; q < n_steps; ++q) {
+    st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end,
+                           tapes ? tapes + (size_t)q * HWENO_CTRL_LEN : (double*)nullptr,
+                           (const double*)nullptr, q > 0, q + 1 < n_steps, (hipStream_t)stream);
+    if (st) return st;
+  }
   return ok();
 }
 

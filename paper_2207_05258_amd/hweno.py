@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
             "hweno_limit": ([P, vp, vp, vp], ctypes.c_int),
             "hweno_rk3_step": ([P, vp, vp, ctypes.c_size_t, ctypes.c_double, ctypes.c_double,
                                 vp, vp, vp], ctypes.c_int),
+            "hweno_rk3_steps": ([P, vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double,
+                                 ctypes.c_double, vp, vp], ctypes.c_int),
             "hweno_adjoint_workspace_bytes": ([P], ctypes.c_size_t),
             "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "hweno_rk3_step_adjoint": ([P, vp, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t,
@@ -281,6 +283,20 @@ class Stepper:
         _check(lib().hweno_rk3_step(ctypes.byref(self._c), _ptr(S), _ptr(self.ws), self.nbytes,
                                     float(dt or 0.0), float(t_end or 0.0), _ptr(tape),
                                     _ptr(replay), _stream()), "hweno_rk3_step")
+        return S
+
+    def steps(self, S: torch.Tensor, n: int, dt: Optional[float] = None,
+              t_end: Optional[float] = None, tapes: Optional[torch.Tensor] = None):
+        """``n`` steps of S in place in one call (hweno_rk3_steps): each step's stage-1
+        speeds are folded by the previous step's last stage; bitwise the same as ``n``
+        calls of ``step``.  ``tapes``: float64 GPU tensor [n, CTRL_LEN] or None."""
+        _require(S, self.prob, self.prob.nf, "state")
+        if tapes is not None and (tapes.dtype != torch.float64 or not tapes.is_cuda or
+                                  tapes.numel() < n * CTRL_LEN or not tapes.is_contiguous()):
+            raise ValueError(f"tapes must be a contiguous float64 GPU tensor of >= {n} x {CTRL_LEN}")
+        _check(lib().hweno_rk3_steps(ctypes.byref(self._c), _ptr(S), _ptr(self.ws), self.nbytes,
+                                     int(n), float(dt or 0.0), float(t_end or 0.0), _ptr(tapes),
+                                     _stream()), "hweno_rk3_steps")
         return S
 
     def capture(self, S: torch.Tensor, steps: int = 1, dt: Optional[float] = None,

@@ -69,6 +69,7 @@ int main() {
       CHECK(hweno_rk3_step(&p, nullptr, nullptr, 0, 0.0, 0.0, nullptr, nullptr, nullptr) == st);
       CHECK(hweno_rhs(&p, nullptr, nullptr, nullptr, 1, nullptr) == st);
       CHECK(hweno_limit(&p, nullptr, nullptr, nullptr) == st);
+      CHECK(hweno_rk3_steps(&p, nullptr, nullptr, 0, 3, 0.0, 0.0, nullptr, nullptr) == st);
       continue;
     }
     ++valid;
@@ -79,6 +80,10 @@ int main() {
     CHECK(empty ? s1 == HWENO_OK : s1 == HWENO_ERR_INVALID_ARG);
     const hweno_status s2 = hweno_rhs(&p, nullptr, nullptr, nullptr, 1, nullptr);
     CHECK(empty ? s2 == HWENO_OK : s2 == HWENO_ERR_INVALID_ARG);
+    const hweno_status s3 = hweno_rk3_steps(&p, nullptr, nullptr, 0, 2, 0.0, 0.0, nullptr, nullptr);
+    CHECK(empty ? s3 == HWENO_OK : s3 == HWENO_ERR_INVALID_ARG);
+    CHECK(hweno_rk3_steps(&p, nullptr, nullptr, 0, -1, 0.0, 0.0, nullptr, nullptr) == HWENO_ERR_INVALID_ARG);
+    CHECK(hweno_rk3_steps(&p, nullptr, nullptr, 0, 0, 0.0, 0.0, nullptr, nullptr) == HWENO_OK);
   }
   CHECK(valid > 1000);
   CHECK(hweno_validate(nullptr) == HWENO_ERR_INVALID_ARG);

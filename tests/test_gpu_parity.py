@@ -380,6 +380,50 @@ def test_graph_replay_after_a_state_reset_repeats_itself():
         assert torch.equal(outs[r][0], outs[0][0]) and torch.equal(outs[r][1], outs[0][1]), r
 
 
+MULTI = [("euler2d_quadrants_70x45", torch.float64, {}),
+         ("euler2d_quadrants_70x45", torch.float32, {}),
+         ("euler1d_piecewise_777_s5", torch.float64, {}),
+         ("linadv1d_sine_200", torch.float64, {"dt": 2e-3}),
+         ("burgers2d_sine_40x33", torch.float32, {}),
+         ("euler2d_rough_reflect_47x29", torch.float64, {"limiter_characteristic": True}),
+         ("euler2d_rsmooth_64x40", torch.float64, {"t_end_steps": 3.5})]
+
+
+@pytest.mark.parametrize("case,dtype,kw", MULTI,
+                         ids=[f"{c}-{'f64' if d == torch.float64 else 'f32'}-{i}"
+                              for i, (c, d, _) in enumerate(MULTI)])
+def test_multi_step_call_equals_single_steps(case, dtype, kw):
+    """hweno_rk3_steps folds each step's stage-1 speeds in the previous step's last
+    stage; the state, the control block and every tape record are bitwise those of
+    single steps (including steps skipped after t_end is reached mid-call)."""
+    w = CASES[case]()
+    announce("multi-step call", case, dtype, kw)
+    kw = dict(kw)
+    dt = kw.pop("dt", None)
+    t_steps = kw.pop("t_end_steps", None)
+    prob = P.gpu_problem(w, dtype, **kw)
+    A, B = P.to_gpu(w, dtype), P.to_gpu(w, dtype)
+    sa, sb = h.Stepper(prob), h.Stepper(prob)
+    t_end = None
+    if t_steps is not None:          # reach t_end after 3.5 steps: one clipped step, then skips
+        probe = h.Stepper(prob)
+        Sp = P.to_gpu(w, dtype)
+        probe.step(Sp)
+        t_end = float(probe.t) * t_steps
+    n = 7
+    ta = torch.zeros(n, h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    tb = torch.zeros_like(ta)
+    for q in range(n):
+        sa.step(A, dt=dt, t_end=t_end, tape=ta[q])
+    sb.steps(B, n, dt=dt, t_end=t_end, tapes=tb)
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
+    assert torch.equal(sa.ctrl[:10], sb.ctrl[:10])
+    assert torch.equal(ta[:, :10], tb[:, :10])
+    if t_steps is not None:
+        assert sb.status & h.hweno.ST_SKIPPED and float(sb.ctrl[7]) == pytest.approx(t_end)
+
+
 def test_tape_and_replay_reproduce_the_step():
     w = hi.euler2d_rough(45, 38, 12)
     announce("tape/replay")
