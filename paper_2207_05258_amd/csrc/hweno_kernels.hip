@@ -1221,18 +1221,15 @@ __global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, long lon
   block_fold<256>(double(mx), double(my), flags, alpha, status, true);
 }
 
-// Start of a step: stage speeds from the replay record, or cleared for the
-// speed reduction, or (take_next) stage-1 speeds from what the previous step's
-// stage 3 folded into ctrl[10..11]; those slots are then cleared for this
-// step's stage 3.
-__global__ void k_begin(double* ctrl, const double* replay, int take_next) {
+// Start of a step: stage speeds and dt from the replay record, or speeds
+// cleared for the speed reduction; the next-step speed slots ctrl[10..11]
+// are cleared for this step's stage 3 (multi-step calls fold into them).
+__global__ void k_begin(double* ctrl, const double* replay) {
   const int t = threadIdx.x;
-  const double nxt = (take_next && t < 2) ? ctrl[10 + t] : 0.0;
-  __syncthreads();
   if (replay) {
     if (t < 7) ctrl[t] = replay[t];
   } else if (t < 6) {
-    ctrl[t] = nxt;
+    ctrl[t] = 0.0;
   }
   if (t == 10 || t == 11) ctrl[t] = 0.0;
 }
@@ -1241,7 +1238,10 @@ __global__ void k_zero(double* p, int n) {
   if ((int)threadIdx.x < n) p[threadIdx.x] = 0.0;
 }
 
-__global__ void k_finish(double* ctrl, double* tape) {
+// End of a step: time and step count, tape record.  begin_next: also start
+// the next step of a multi-step call (what k_begin does with take_next), so
+// consecutive steps need one small launch between them instead of two.
+__global__ void k_finish(double* ctrl, double* tape, int begin_next) {
   if (threadIdx.x == 0) {
     if (ctrl[6] > 0.0) {
       ctrl[7] += ctrl[6];
@@ -1255,6 +1255,14 @@ __global__ void k_finish(double* ctrl, double* tape) {
     if (tape) {
       for (int q = 0; q < 10; ++q) tape[q] = ctrl[q];
     }
+  }
+  if (begin_next) {
+    __syncthreads();
+    const int t = threadIdx.x;
+    const double nxt = t < 2 ? ctrl[10 + t] : 0.0;
+    __syncthreads();
+    if (t < 6) ctrl[t] = nxt;
+    if (t == 10 || t == 11) ctrl[t] = 0.0;
   }
 }
 
@@ -1612,6 +1620,8 @@ struct RunStep {
   template <typename T, int PHYS, int DIM>
   // take_next: stage-1 speeds come from the previous step's stage 3 (the state
   // has not changed since); fold_next: this step's stage 3 provides them
+  // (multi-step calls: the previous step's k_finish already began this one when
+  // take_next, and this one's k_finish begins the next when fold_next)
   static hweno_status run(const hweno_problem* p, void* state, void* ws, double dt_fixed,
                           double t_end, double* tape, const double* replay, bool take_next,
                           bool fold_next, hipStream_t s) {
@@ -1620,7 +1630,7 @@ struct RunStep {
     double* ctrl = (double*)(w + L.ctrl);
     const long long n = cells_of(p);
     const Consts<T> k = make_consts<T>(p);
-    k_begin<<<1, 64, 0, s>>>(ctrl, replay, take_next && !replay ? 1 : 0);
+    if (!(take_next && !replay)) k_begin<<<1, 64, 0, s>>>(ctrl, replay);
     if (!replay && !take_next) {
       k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>(
           (const T*)state, n, k, ctrl, (unsigned long long*)(ctrl + 8));
@@ -1658,7 +1668,7 @@ struct RunStep {
     } else {
       stages(std::false_type{});
     }
-    k_finish<<<1, 64, 0, s>>>(ctrl, tape);
+    k_finish<<<1, 64, 0, s>>>(ctrl, tape, fold_next && !replay ? 1 : 0);
     return launch_check("rk3_step");
   }
 };
