@@ -610,11 +610,12 @@ class Rollout(torch.autograd.Function):
                 steppers[n].step(S, dt=dt, tape=tapes[n])
             kept = ([states[n] for n in range(n_steps)], steppers)
         else:
+            # one multi-step call per segment between checkpoints
             st = Stepper(prob, device=S.device)
-            for n in range(n_steps):
-                if n % ckpt == 0:
-                    ckpts.append(S.clone())
-                st.step(S, dt=dt, tape=tapes[n])
+            for n0 in range(0, n_steps, ckpt):
+                n1 = min(n0 + ckpt, n_steps)
+                ckpts.append(S.clone())
+                st.steps(S, n1 - n0, dt=dt, tapes=tapes[n0:n1])
         ctx.prob, ctx.n_steps, ctx.ckpt = prob, n_steps, ckpt
         ctx.ckpts, ctx.tapes, ctx.kept = ckpts, tapes, kept
         Rollout.last_tapes = tapes
