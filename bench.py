@@ -401,6 +401,8 @@ def main():
                    "nx": args.n, "ny": args.n, "fields": 12, "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "paper_timings": "none published: the paper shows efficiency only as error-versus-CPU-time "
+                         "figures, without numbers or stated hardware",
         "variant": variant,
         "batched": batched,
         "adjoint": adjoint,
