@@ -43,16 +43,16 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("09cd720c5df9ed45", "f64", 4096): 5.0834e+09,
-    ("09cd720c5df9ed45", "f32", 4096): 2.6228e+09,
+    ("a4b334107164e6c9", "f64", 4096): 5.0837e+09,
+    ("a4b334107164e6c9", "f32", 4096): 2.6227e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("09cd720c5df9ed45", "f64", 4096): 1.040e9,
-    ("09cd720c5df9ed45", "f32", 4096): 9.207e8,
+    ("a4b334107164e6c9", "f64", 4096): 9.769e8,
+    ("a4b334107164e6c9", "f32", 4096): 8.624e8,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
 # lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.

@@ -53,34 +53,27 @@ HW_HD T hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, T g
   const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
   const T p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
   const T p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
-  const T a1 = T(19.0 / 192.0) * Hs + T(79.0 / 48.0) * H0 + T(27.0 / 64.0) * dl;
-  const T a2 = T(0.375) * Hd + T(1.25) * lap;
-  const T a3 = -(T(11.0 / 24.0) * Hs + T(17.0 / 6.0) * H0) - T(1.875) * dl;
-  const T a4 = T(-0.25) * Hd - T(0.5) * lap;
-  const T a5 = T(0.25) * Hs + H0 + T(0.75) * dl;
-  const T t0 = a1 + T(0.25) * a3 + T(0.0625) * a5;
-  const T t1 = a2 + T(63.0 / 130.0) * a4;
-  const T t2 = a3 + T(8825.0 / 10934.0) * a5;
-  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * t2 * t2 +
-               T(1421461.0 / 2275.0) * a4 * a4 + T(21520059541.0 / 1377684.0) * a5 * a5;
+  // beta_0 as the sum of squares of hw_plus(): H0 and four linear forms
+  constexpr T c11 = T(0.5284229075567874), c12 = T(2.0976788148466414);
+  constexpr T c21 = T(-1.6032089149031234), c22 = T(-12.66183557959969), c23 = T(-7.934126704702969);
+  constexpr T c41 = T(-6.249090043648465), c42 = T(-12.49818008729693);
+  constexpr T c51 = T(31.24546092343706), c52 = T(124.98184369374825), c53 = T(93.73638277031118);
+  const T x1 = c11 * Hd + c12 * lap;
+  const T x2 = c21 * Hs + c22 * H0 + c23 * dl;
+  const T x4 = c41 * Hd + c42 * lap;
+  const T x5 = c51 * Hs + c52 * H0 + c53 * dl;
+  const T b0 = H0 * H0 + x1 * x1 + x2 * x2 + x4 * x4 + x5 * x5;
   const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp, h2 = H0 * H0;
   const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
   const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
   T gp0, gp1, gp2, gb0, gb1, gb2;
   const T value = combine_vjp(p0, p1, p2, b0, b1, b2, w, g, gp0, gp1, gp2, gb0, gb1, gb2);
   // smoothness indicators
-  const T gt0 = T(2) * t0 * gb0;
-  const T gt1 = T(26.0 / 3.0) * t1 * gb0;
-  const T gt2 = T(781.0 / 10.0) * t2 * gb0;
-  const T ga1 = gt0;
-  const T ga2 = gt1;
-  const T ga3 = T(0.25) * gt0 + gt2;
-  const T ga4 = T(2.0 * 1421461.0 / 2275.0) * a4 * gb0 + T(63.0 / 130.0) * gt1;
-  const T ga5 = T(2.0 * 21520059541.0 / 1377684.0) * a5 * gb0 + T(0.0625) * gt0 +
-                T(8825.0 / 10934.0) * gt2;
+  const T g2 = T(2) * gb0;
+  const T gx1 = g2 * x1, gx2 = g2 * x2, gx4 = g2 * x4, gx5 = g2 * x5;
   const T gu1 = T(26.0 / 3.0) * u1 * gb1;
   const T gu2 = T(26.0 / 3.0) * u2 * gb2;
-  T gH0_ = T(2) * H0 * (gb1 + gb2) + gu1 + gu2;
+  T gH0_ = T(2) * H0 * (gb1 + gb2 + gb0) + gu1 + gu2 + c22 * gx2 + c52 * gx5;
   T gfm_ = gu1, gf0_ = gu2 - gu1, gfp_ = -gu2;
   // candidate values
   T gs_ = T(11.0 / 60.0) * gp0;
@@ -91,12 +84,11 @@ HW_HD T hw_plus_vjp(T fm, T f0, T fp, T Hm, T H0, T Hp, const Weights<T>& w, T g
   gf0_ += T(5.0 / 6.0) * gp1 + T(5.0 / 6.0) * gp2;
   gH0_ += T(2.0 / 3.0) * gp1 + T(1.0 / 3.0) * gp2;
   gfp_ += T(1.0 / 6.0) * gp2;
-  // monomial coefficients
-  const T gHs = T(19.0 / 192.0) * ga1 - T(11.0 / 24.0) * ga3 + T(0.25) * ga5;
-  gH0_ += T(79.0 / 48.0) * ga1 - T(17.0 / 6.0) * ga3 + ga5;
-  const T gdl = T(27.0 / 64.0) * ga1 - T(1.875) * ga3 + T(0.75) * ga5;
-  gHd += T(0.375) * ga2 - T(0.25) * ga4;
-  const T glap = T(1.25) * ga2 - T(0.5) * ga4;
+  // the linear forms of beta_0
+  const T gHs = c21 * gx2 + c51 * gx5;
+  const T gdl = c23 * gx2 + c53 * gx5;
+  gHd += c11 * gx1 + c41 * gx4;
+  const T glap = c12 * gx1 + c42 * gx4;
   gs_ += glap;
   gf0_ -= T(2) * glap;
   gfm += gfm_ + gs_ + gdl;
@@ -114,30 +106,30 @@ HW_HD void limit1_vjp(T um, T u0, T up, T vm, T vp, T h, T ih, const Weights<T>&
                       T& gum, T& gu0, T& gup, T& gvm, T& gvp) {
   const T Vs = h * (vm + vp), Vd = h * (vm - vp);
   const T lap = um - T(2) * u0 + up;
-  const T a1 = T(0.75) * (up - um) - T(0.25) * Vs;
-  const T a2 = T(0.25) * Vd + lap;
-  const T a3 = T(0.25) * Vs + T(0.25) * (um - up);
-  const T a4 = T(-0.25) * Vd - T(0.5) * lap;
-  const T t0 = a1 + T(0.25) * a3;
-  const T t1 = a2 + T(63.0 / 130.0) * a4;
-  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * a3 * a3 +
-               T(1421461.0 / 2275.0) * a4 * a4;
+  const T D = up - um;
+  const T a1 = T(0.75) * D - T(0.25) * Vs;
+  // beta_0 as the sum of squares of limit1()
+  constexpr T k11 = T(0.2682146576235209), k12 = T(1.5772623149801082), k3 = T(1.5622499799967993);
+  constexpr T c41 = T(-6.249090043648465), c42 = T(-12.49818008729693);
+  const T x0 = T(11.0 / 16.0) * D - T(3.0 / 16.0) * Vs;
+  const T x1 = k11 * Vd + k12 * lap;
+  const T x3 = k3 * (Vs - D);
+  const T x4 = c41 * Vd + c42 * lap;
+  const T b0 = x0 * x0 + x1 * x1 + x3 * x3 + x4 * x4;
   const T d1 = u0 - um, d2 = up - u0;
   T gP0, gP1, gP2, gb0, gb1, gb2;
   combine_vjp(a1 * ih, d1 * ih, d2 * ih, b0, d1 * d1, d2 * d2, w, g, gP0, gP1, gP2, gb0, gb1, gb2);
   const T gd1 = gP1 * ih + T(2) * d1 * gb1;
   const T gd2 = gP2 * ih + T(2) * d2 * gb2;
-  const T gt0 = T(2) * t0 * gb0;
-  const T gt1 = T(26.0 / 3.0) * t1 * gb0;
-  const T ga1 = gP0 * ih + gt0;
-  const T ga2 = gt1;
-  const T ga3 = T(781.0 / 10.0) * a3 * gb0 + T(0.25) * gt0;
-  const T ga4 = T(2.0 * 1421461.0 / 2275.0) * a4 * gb0 + T(63.0 / 130.0) * gt1;
-  const T gVs = T(-0.25) * ga1 + T(0.25) * ga3;
-  const T gVd = T(0.25) * ga2 - T(0.25) * ga4;
-  const T glap = ga2 - T(0.5) * ga4;
-  gup += T(0.75) * ga1 - T(0.25) * ga3 + glap + gd2;
-  gum += T(-0.75) * ga1 + T(0.25) * ga3 + glap - gd1;
+  const T g2 = T(2) * gb0;
+  const T gx0 = g2 * x0, gx1 = g2 * x1, gx3 = g2 * x3, gx4 = g2 * x4;
+  const T ga1 = gP0 * ih;
+  const T gD = T(0.75) * ga1 + T(11.0 / 16.0) * gx0 - k3 * gx3;
+  const T gVs = T(-0.25) * ga1 - T(3.0 / 16.0) * gx0 + k3 * gx3;
+  const T gVd = k11 * gx1 + c41 * gx4;
+  const T glap = k12 * gx1 + c42 * gx4;
+  gup += gD + glap + gd2;
+  gum += -gD + glap - gd1;
   gu0 += T(-2) * glap + gd1 - gd2;
   gvm += h * (gVs + gVd);
   gvp += h * (gVs - gVd);

@@ -158,18 +158,19 @@ HW_HD T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
   const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
   const T p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
   const T p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
-  // monomial coefficients of p0 in (x - x_i)/dx
-  const T a1 = T(19.0 / 192.0) * Hs + T(79.0 / 48.0) * H0 + T(27.0 / 64.0) * dl;
-  const T a2 = T(0.375) * Hd + T(1.25) * lap;
-  const T a3 = -(T(11.0 / 24.0) * Hs + T(17.0 / 6.0) * H0) - T(1.875) * dl;
-  const T a4 = T(-0.25) * Hd - T(0.5) * lap;
-  const T a5 = T(0.25) * Hs + H0 + T(0.75) * dl;
-  const T t0 = a1 + T(0.25) * a3 + T(0.0625) * a5;
-  const T t1 = a2 + T(63.0 / 130.0) * a4;
-  const T t2 = a3 + T(8825.0 / 10934.0) * a5;
-  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * t2 * t2 +
-               T(1421461.0 / 2275.0) * a4 * a4 +
-               T(21520059541.0 / 1377684.0) * a5 * a5;
+  // beta_0 from the monomial coefficients a1..a5 of p0 in (x - x_i)/dx, i.e.
+  //   (a1 + a3/4 + a5/16)^2 + 13/3 (a2 + 63/130 a4)^2 + 781/20 (a3 + 8825/10934 a5)^2
+  //   + 1421461/2275 a4^2 + 21520059541/1377684 a5^2,
+  // written as a sum of five squares of linear forms in (H0, Hd, lap, Hs, dl):
+  // the first form reduces exactly to H0 (p0'(x_i) dx = H_i, a Hermite
+  // condition), and each other one carries the square root of its weight.
+  const T x1 = T(0.5284229075567874) * Hd + T(2.0976788148466414) * lap;  // sqrt(13/3)(33 Hd + 131 lap)/130
+  const T x2 = T(-1.6032089149031234) * Hs + T(-12.66183557959969) * H0 +
+               T(-7.934126704702969) * dl;                              // sqrt(781/20)(a3 + 8825/10934 a5)
+  const T x4 = T(-6.249090043648465) * Hd + T(-12.49818008729693) * lap;  // sqrt(1421461/2275) a4
+  const T x5 = T(31.24546092343706) * Hs + T(124.98184369374825) * H0 +
+               T(93.73638277031118) * dl;                               // sqrt(21520059541/1377684) a5
+  const T b0 = H0 * H0 + x1 * x1 + x2 * x2 + x4 * x4 + x5 * x5;
   const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp, h2 = H0 * H0;
   const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
   const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
@@ -184,16 +185,19 @@ HW_HD T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
                                     const Weights<T>& w) {
   const T Vs = h * (vm + vp), Vd = h * (vm - vp);
   const T lap = um - T(2) * u0 + up;
-  const T a1 = T(0.75) * (up - um) - T(0.25) * Vs;  // = dx q0'(x_i)
-  const T a2 = T(0.25) * Vd + lap;
-  const T a3 = T(0.25) * Vs + T(0.25) * (um - up);
-  const T a4 = T(-0.25) * Vd - T(0.5) * lap;
-  const T t0 = a1 + T(0.25) * a3;
-  const T t1 = a2 + T(63.0 / 130.0) * a4;
-  const T b0 = t0 * t0 + T(13.0 / 3.0) * t1 * t1 + T(781.0 / 20.0) * a3 * a3 +
-               T(1421461.0 / 2275.0) * a4 * a4;
+  const T D = up - um;
+  const T a1 = T(0.75) * D - T(0.25) * Vs;  // = dx q0'(x_i)
+  // beta_0 of q0 from its coefficients a1..a4,
+  //   (a1 + a3/4)^2 + 13/3 (a2 + 63/130 a4)^2 + 781/20 a3^2 + 1421461/2275 a4^2,
+  // as a sum of four squares of linear forms (weights' square roots folded in)
+  const T x0 = T(11.0 / 16.0) * D - T(3.0 / 16.0) * Vs;                  // a1 + a3/4
+  const T x1 = T(0.2682146576235209) * Vd + T(1.5772623149801082) * lap;  // sqrt(13/3)(a2 + 63/130 a4)
+  const T x3 = T(1.5622499799967993) * (Vs - D);                         // sqrt(781/20) a3
+  const T x4 = T(-6.249090043648465) * Vd + T(-12.49818008729693) * lap;  // sqrt(1421461/2275) a4
+  const T b0 = x0 * x0 + x1 * x1 + x3 * x3 + x4 * x4;
   const T d1 = u0 - um, d2 = up - u0;
-  return combine(a1 * ih, d1 * ih, d2 * ih, b0, d1 * d1, d2 * d2, w);
+  // the combination is linear in the candidates q_l' = (a1, d1, d2) / dx
+  return ih * combine(a1, d1, d2, b0, d1 * d1, d2 * d2, w);
 }
 
 // ---------------------------------------------------------------------------
