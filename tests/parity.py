@@ -8,7 +8,11 @@ i.e. derivative fields are compared in cell-size-scaled units, which is the
 scale in which they enter the reconstruction (H = dx h).  Raw derivative
 increments carry an intrinsic rounding of order eps_machine * N, so they are
 gated in these units.  The right-hand side is compared as a step increment:
-dx * L_U and dx^2 * L_D against max |U_ref|.
+dx * L_U and dx^2 * L_D against the larger of max |U_c| and max |dx * L_U,c|
+of the reference.  The increment is a flux difference, whose rounding scales
+with the flux; for a component that is zero everywhere (the momentum of a
+fluid at rest, as in the blast-wave problem) the flux is carried by the
+pressure alone and only the increment itself sets the scale.
 """
 from __future__ import annotations
 
@@ -66,7 +70,7 @@ def rhs_errors(L, Lref, U, w: hi.Workload):
     m = w.m
     errs = {}
     for c in range(m):
-        scale = float(U[c].abs().max()) or 1.0
+        scale = max(float(U[c].abs().max()), w.dx * float(Lref[c].abs().max())) or 1.0
         errs[f"LU{c}"] = w.dx * float((L[c] - Lref[c]).abs().max()) / scale
         errs[f"LUx{c}"] = w.dx * w.dx * float((L[m + c] - Lref[m + c]).abs().max()) / scale
         if w.dim == 2:

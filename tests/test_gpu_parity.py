@@ -66,6 +66,10 @@ CASES = {
         lambda: _with_bc(hi.euler2d_quadrants(40, 36, 9), hi.REFLECT, hi.PERIODIC),
     "euler2d_rsmooth_outflowx_reflecty_31x44":
         lambda: _with_bc(hi.euler2d_random_smooth(31, 44, 10), hi.OUTFLOW, hi.REFLECT),
+    # the paper's discontinuous 1D problems (Examples 3.5-3.7) at their sizes
+    "lax_200": lambda: hi.lax_1d(200),
+    "shu_osher_400": lambda: hi.shu_osher_1d(400),
+    "blast_waves_800": lambda: hi.blast_waves_1d(800),
 }
 
 
