@@ -27,6 +27,9 @@ GAMMA_GAS = 1.4
 PERIODIC = 0
 OUTFLOW = 1
 REFLECT = 2
+EDGES = 3   # each side of the direction described in Workload.edges
+
+SEG_OUTFLOW, SEG_REFLECT, SEG_STATE = 0, 1, 2
 
 
 @dataclass
@@ -46,6 +49,11 @@ class Workload:
     adv_speed: tuple = (1.0, 1.0)
     name: str = ""
     info: dict = field(default_factory=dict)
+    # sides x_lo, x_hi, y_lo, y_hi where a bc is EDGES: each
+    # ((kind_0, kind_1), (s0, s1, s2), (state_0, state_1)); a ghost cell at
+    # position pos along the side, d beyond it, at time t takes segment 0 when
+    # pos < s0 + s1 t + s2 d (conserved states, zero derivatives for SEG_STATE)
+    edges: Optional[tuple] = None
 
     @property
     def nx(self) -> int:
@@ -217,6 +225,49 @@ def shu_osher_1d(n: int) -> Workload:
 # ---------------------------------------------------------------------------
 # 2D Euler
 # ---------------------------------------------------------------------------
+
+def normal_shock_states(mach: float, rho1: float, p1: float, gamma=GAMMA_GAS):
+    """Rankine-Hugoniot states of a normal shock of Mach number ``mach`` moving
+    into gas at rest (rho1, p1): (shock speed, rho2, normal velocity u2, p2)."""
+    c1 = np.sqrt(gamma * p1 / rho1)
+    s = mach * c1
+    m2 = mach * mach
+    rho2 = rho1 * (gamma + 1.0) * m2 / ((gamma - 1.0) * m2 + 2.0)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (m2 - 1.0))
+    u2 = s * (1.0 - rho1 / rho2)
+    return s, rho2, u2, p2
+
+
+def double_mach(nx: int, ny: int) -> Workload:
+    """Double Mach reflection (Example 3.11) on [0, 4] x [0, 1], T = 0.2: a Mach 10
+    shock into (rho, u, v, p) = (1.4, 0, 0, 1), through (1/6, 0) at 60 degrees to
+    the x axis, moving along its normal n = (sin 60, -cos 60).  Post-shock state from
+    the Rankine-Hugoniot relations (rho = 8, |u| = 8.25, p = 116.5).  Boundaries:
+    post-shock inflow on the left; outflow on the right; on the bottom post-shock
+    inflow for x < 1/6 and a wall beyond; on the top the exact shock, which meets
+    the height y = 1 + d of a ghost centre at x = 1/6 + y / sqrt(3) + s t / sin 60."""
+    lo, hi = (0.0, 0.0), (4.0, 1.0)
+    x = centers(nx, lo[0], hi[0])[None, :]
+    y = centers(ny, lo[1], hi[1])[:, None]
+    s, rho2, u2, p2 = normal_shock_states(10.0, 1.4, 1.0)
+    nrm = (np.sin(np.pi / 3.0), -np.cos(np.pi / 3.0))
+    x0, r3 = 1.0 / 6.0, np.sqrt(3.0)
+    post = (rho2, u2 * nrm[0], u2 * nrm[1], p2)
+    pre = (1.4, 0.0, 0.0, 1.0)
+    behind = x < x0 + y / r3
+    prim = [np.where(behind, a, b) * np.ones((ny, nx)) for a, b in zip(post, pre)]
+    U = conserved_2d(*prim)
+    S = np.concatenate([U, np.zeros_like(U), np.zeros_like(U)])
+    post_c = tuple(float(v[0, 0]) for v in conserved_2d(*[np.full((1, 1), q) for q in post]))
+    pre_c = tuple(float(v[0, 0]) for v in conserved_2d(*[np.full((1, 1), q) for q in pre]))
+    inflow = ((SEG_STATE, SEG_STATE), (0.0, 0.0, 0.0), (post_c, post_c))
+    outflow = ((SEG_OUTFLOW, SEG_OUTFLOW), (0.0, 0.0, 0.0), (pre_c, pre_c))
+    bottom = ((SEG_STATE, SEG_REFLECT), (x0, 0.0, 0.0), (post_c, pre_c))
+    top = ((SEG_STATE, SEG_STATE), (x0 + hi[1] / r3, s / nrm[0], 1.0 / r3), (post_c, pre_c))
+    return Workload(S, 2, "euler", (hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny, EDGES, EDGES,
+                    lo, hi, name=f"double_mach_{nx}x{ny}",
+                    info={"t_end": 0.2, "shock_speed": s, "post": post, "pre": pre},
+                    edges=(inflow, outflow, bottom, top))
 
 def euler2d_quadrants(nx: int, ny: int, seed: int, bc=OUTFLOW) -> Workload:
     """Four constant quadrants of [0,1]^2 split at x = 1/2, y = 1/2.

@@ -49,7 +49,35 @@ typedef enum {
 
 typedef enum { HWENO_F32 = 0, HWENO_F64 = 1 } hweno_dtype;
 typedef enum { HWENO_LINADV = 0, HWENO_BURGERS = 1, HWENO_EULER = 2 } hweno_physics;
-typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1, HWENO_BC_REFLECT = 2 } hweno_bc;
+typedef enum {
+  HWENO_BC_PERIODIC = 0,
+  HWENO_BC_OUTFLOW = 1,
+  HWENO_BC_REFLECT = 2,
+  HWENO_BC_EDGES = 3
+} hweno_bc;
+
+/* Segment kinds of an edge-described side (HWENO_BC_EDGES). */
+typedef enum { HWENO_SEG_OUTFLOW = 0, HWENO_SEG_REFLECT = 1, HWENO_SEG_STATE = 2 } hweno_seg;
+
+/* One side of the domain under HWENO_BC_EDGES (the boundaries of the double
+ * Mach reflection problem, Example 3.11: an inflow stretch followed by a
+ * wall on the bottom, the exact motion of an oblique shock on the top).
+ * The side is cut in two segments at the position, measured along the side
+ * from the domain's low corner (cell centres at (i + 1/2) dx, (j + 1/2) dy),
+ *     split = split[0] + split[1] * t + split[2] * d,
+ * where t is the time of the state being read and d the distance of the
+ * ghost cell's centre beyond the side ((k - 1/2) h for ghost layer k = 1, 2).
+ * Ghost cells before the split take segment 0, the others segment 1:
+ *   HWENO_SEG_OUTFLOW  copy of the nearest interior cell (all fields);
+ *   HWENO_SEG_REFLECT  solid wall, as HWENO_BC_REFLECT;
+ *   HWENO_SEG_STATE    the conserved state `state[s]` (rho, rho u, rho v, E)
+ *                      with every derivative field zero (an inflow).
+ * A side may not combine OUTFLOW with REFLECT. */
+typedef struct {
+  int32_t kind[2];
+  double split[3];
+  double state[2][4];
+} hweno_edge;
 
 /* Problem description (host memory, read during the call only).
  *  dim            1 or 2.
@@ -67,6 +95,10 @@ typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1, HWENO_BC_REFLECT = 2
  *                 Euler only (HWENO_ERR_UNSUPPORTED for scalar laws, which
  *                 have no mirror symmetry with the same flux); at least 2
  *                 cells across the wall's direction.
+ *                 edges = each side of the direction described by `edges`
+ *                 (2D Euler with the component-wise limiter, single-grid
+ *                 forward entry points only: the batched and adjoint entry
+ *                 points return HWENO_ERR_UNSUPPORTED).
  *  characteristic Euler only: 1 = nonlinear flux reconstruction in local
  *                 characteristic fields (Remarks 2.1/2.2; Roe average),
  *                 0 = component by component.  Ignored for scalars.
@@ -87,6 +119,11 @@ typedef enum { HWENO_BC_PERIODIC = 0, HWENO_BC_OUTFLOW = 1, HWENO_BC_REFLECT = 2
  *                 limiter.  Each must be > 0 and sum to 1 within 1e-12.
  *  eps            epsilon of the nonlinear weights (> 0; paper: 1e-6).
  *  cfl            CFL number for the device-side time step (> 0; paper: 0.6).
+ *  edges          sides x_lo, x_hi, y_lo, y_hi, read when that direction's
+ *                 bc is HWENO_BC_EDGES.  The stages of hweno_rk3_step(s)
+ *                 read them at their own times t_n, t_n + dt, t_n + dt/2
+ *                 (t_n = simulated time in the control block);
+ *                 hweno_rhs and hweno_limit read them at t = 0.
  */
 typedef struct {
   int32_t dim, nx, ny;
@@ -98,6 +135,7 @@ typedef struct {
   double adv_speed[2];
   double lin_w[3], lim_w[3];
   double eps, cfl;
+  hweno_edge edges[4];
 } hweno_problem;
 
 /* Step control block: HWENO_CTRL_LEN doubles of device memory at the start of

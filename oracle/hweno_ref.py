@@ -36,10 +36,19 @@ Readings of passages the paper leaves open (each listed in the design notes):
   * Reflecting walls (Euler, Example 3.7) fill ghost cells with the mirror
     image of the interior, with the wall-normal momentum and the derivatives
     along the wall normal negated.
+  * Edge-described sides (the boundaries of Example 3.11): a side is cut in
+    two segments at split = s0 + s1 t + s2 d along it (d: distance of the
+    ghost centre beyond the side).  A segment is an outflow copy, a wall, or
+    an inflow holding a prescribed state with zero derivatives ("exact
+    post-shock condition", "exact motion of the shock").  Each Runge-Kutta
+    stage reads the ghosts at the time of its input state: t, t + dt,
+    t + dt/2.
 
 Parity unpinned (documented choices with nothing in the paper to check them
-against): the component-wise limiter for systems and the outflow copy of the
-derivative fields.  The characteristic limiter variant is pinned only through
+against): the component-wise limiter for systems, the outflow copy of the
+derivative fields, and the zero derivatives and stage times of inflow
+segments (pinned only where an edge reduces to a plain boundary or a state
+that is already uniform).  The characteristic limiter variant is pinned only through
 its special cases (linear weights, data along one eigenvector).
 """
 from __future__ import annotations
@@ -54,6 +63,24 @@ DTYPE = torch.float64
 PERIODIC = 0
 OUTFLOW = 1
 REFLECT = 2   # solid wall: mirror image, wall-normal momentum and normal derivatives odd
+EDGES = 3     # each side of the direction described by an Edge
+
+SEG_OUTFLOW, SEG_REFLECT, SEG_STATE = 0, 1, 2
+
+
+@dataclass(frozen=True)
+class Edge:
+    """One side of the domain cut in two segments (Example 3.11's boundaries).
+
+    A ghost cell at position ``pos`` along the side (measured from the domain's
+    low corner, cell centres at (j + 1/2) h) and distance ``d`` beyond it takes
+    segment 0 when pos < split[0] + split[1] t + split[2] d, else segment 1.
+    Kinds: SEG_OUTFLOW (copy), SEG_REFLECT (wall), SEG_STATE (``state[s]``,
+    conserved variables, with zero derivatives)."""
+
+    kind: Tuple[int, int] = (SEG_OUTFLOW, SEG_OUTFLOW)
+    split: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    state: Tuple[Tuple[float, ...], Tuple[float, ...]] = ((0.0,) * 4, (0.0,) * 4)
 
 
 @dataclass
@@ -77,6 +104,8 @@ class Problem:
     # Euler only: apply the limiter to local characteristic fields of each cell
     # instead of component by component (a variant; the paper does not say)
     limiter_characteristic: bool = False
+    # sides x_lo, x_hi, y_lo, y_hi, read where bc_x / bc_y is EDGES
+    edges: Optional[Tuple[Edge, Edge, Edge, Edge]] = None
     # test-only switches: force the nonlinear weights to the linear ones
     linear_recon: bool = False
     linear_limiter: bool = False
@@ -93,6 +122,10 @@ class Problem:
 
 
 def problem_from_workload(w, **kw) -> Problem:
+    edges = getattr(w, "edges", None)
+    if edges is not None and "edges" not in kw:
+        kw["edges"] = tuple(Edge(kind=tuple(e[0]), split=tuple(e[1]),
+                                 state=(tuple(e[2][0]), tuple(e[2][1]))) for e in edges)
     return Problem(dim=w.dim, physics=w.physics, dx=w.dx, dy=w.dy,
                    bc_x=w.bc_x, bc_y=w.bc_y, gamma_gas=w.gamma_gas,
                    adv_speed=tuple(w.adv_speed), **kw)
@@ -382,6 +415,54 @@ def _pad(A, axis, bc, width=2, parity=None):
     return out * (1 - ghost.view(shape) + ghost.view(shape) * p)
 
 
+def _pad_edges(A, axis, prob, d, role, t, width=2):
+    """Ghost cells along ``axis`` (direction d) of A = [components, ny, nx] for a
+    direction under EDGES.  ``role``: "U" (conserved variables), "n" (their
+    derivative along d) or "t" (across d), which decides what a wall's parity
+    and an inflow's zero derivative do to A."""
+    n = A.shape[axis]
+    lo, hi = prob.edges[2 * d], prob.edges[2 * d + 1]
+    wall_lo, wall_hi = SEG_REFLECT in lo.kind, SEG_REFLECT in hi.kind
+    if (wall_lo or wall_hi) and n < width:
+        raise ValueError("a reflecting wall needs at least as many cells as ghost cells")
+    k = torch.arange(-width, n + width)
+    src = torch.where(k < 0, (-1 - k) if wall_lo else torch.zeros_like(k),
+                      torch.where(k >= n, (2 * n - 1 - k) if wall_hi else torch.full_like(k, n - 1), k))
+    out = A.index_select(axis, src).clone()
+    # tangential coordinates of the cells along the side
+    t_axis = 1 if axis == 2 else 2
+    h_t = prob.dy if axis == 2 else prob.dx
+    h_d = prob.dx if axis == 2 else prob.dy
+    pos = (torch.arange(A.shape[t_axis], dtype=DTYPE) + 0.5) * h_t
+    if prob.physics == "euler":
+        pu, pn, pt = _parities(prob, d)
+        par = {"U": pu, "n": pn, "t": pt}[role]
+    else:
+        par = None
+    for layer in range(1, width + 1):
+        depth = (layer - 0.5) * h_d
+        for side, e, g in ((0, lo, width - layer), (1, hi, n + width - 1 + layer)):
+            split = e.split[0] + e.split[1] * t + e.split[2] * depth
+            seg1 = pos >= split                      # segment of each ghost cell along the side
+            ghost = out.narrow(axis, g, 1)           # view [m, 1, n_t] or [m, n_t, 1]
+            for sg, mask in ((0, ~seg1), (1, seg1)):
+                if not bool(mask.any()):
+                    continue
+                shape = [1, 1, 1]
+                shape[t_axis] = -1
+                msk = mask.view(shape)
+                if e.kind[sg] == SEG_REFLECT:
+                    p = torch.as_tensor(par, dtype=A.dtype).view(-1, 1, 1)
+                    ghost.copy_(torch.where(msk, ghost * p, ghost))
+                elif e.kind[sg] == SEG_STATE:
+                    if role == "U":
+                        val = torch.as_tensor(e.state[sg][:A.shape[0]], dtype=A.dtype).view(-1, 1, 1)
+                    else:
+                        val = torch.zeros(A.shape[0], 1, 1, dtype=A.dtype)
+                    ghost.copy_(torch.where(msk, val.expand_as(ghost), ghost))
+    return out
+
+
 def _parities(prob, d):
     """Parities of (U, derivative along d, derivative across d) under reflection
     across a wall normal to direction d: the momentum component normal to the
@@ -414,10 +495,11 @@ def max_speeds(S, prob) -> Tuple[float, float]:
 # Semi-discrete operator (eqs. odeH, ode2H; Remarks 2.1 and 2.2)
 # ===========================================================================
 
-def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
+def _direction_fluxes(U, Dn, Dt, prob, d, alpha, t=0.0):
     """Interface fluxes along direction d for interfaces -1/2 .. n-1/2.
 
-    U, Dn (derivative along d), Dt (derivative across d, or None): [m, ny, nx].
+    U, Dn (derivative along d), Dt (derivative across d, or None): [m, ny, nx];
+    t: time of the state (read by edge-described sides).
     Returns (f-hat, h-hat, mixed-hat), each with the component axis first.
     """
     phys = physics_of(prob)
@@ -426,8 +508,13 @@ def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
     dd = prob.dx if d == 0 else prob.dy
     n = U.shape[axis]
     pu, pn, pt = _parities(prob, d) if bc == REFLECT else (None, None, None)
-    Up = _pad(U, axis, bc, parity=pu).movedim(0, -1)
-    Dnp = _pad(Dn, axis, bc, parity=pn).movedim(0, -1)
+
+    def pad(A, par, role):
+        if bc == EDGES:
+            return _pad_edges(A, axis, prob, d, role, t)
+        return _pad(A, axis, bc, parity=par)
+    Up = pad(U, pu, "U").movedim(0, -1)
+    Dnp = pad(Dn, pn, "n").movedim(0, -1)
     cax = axis - 1   # grid axis once the component axis has moved last
 
     def at(A, k):    # stencil point i-1+k of the interfaces i+1/2, i = -1..n-1
@@ -469,7 +556,7 @@ def _direction_fluxes(U, Dn, Dt, prob, d, alpha):
 
     mixed = None
     if Dt is not None:
-        Dtp = _pad(Dt, axis, bc, parity=pt).movedim(0, -1)
+        Dtp = pad(Dt, pt, "t").movedim(0, -1)
         AT = phys.jvp(Up, Dtp, d)
         # eq. (mixed): central four-point value, no splitting
         mixed = (-at(AT, 0) + 7.0 * at(AT, 1) + 7.0 * at(AT, 2) - at(AT, 3)) / 12.0
@@ -482,26 +569,27 @@ def _difference(Fh, axis, h):
     return -(Fh.narrow(axis, 1, n) - Fh.narrow(axis, 0, n)) / h
 
 
-def rhs(S, prob: Problem, alpha: Optional[Tuple[float, float]] = None):
-    """Semi-discrete right-hand side L(S) (eqs. odeH and ode2H)."""
+def rhs(S, prob: Problem, alpha: Optional[Tuple[float, float]] = None, t: float = 0.0):
+    """Semi-discrete right-hand side L(S) (eqs. odeH and ode2H) of the state at time t."""
     if alpha is None:
         alpha = max_speeds(S, prob)
     U, V, W = _split(S, prob)
-    fh, hh, eh = _direction_fluxes(U, V, W, prob, 0, alpha[0])
+    fh, hh, eh = _direction_fluxes(U, V, W, prob, 0, alpha[0], t)
     LU = _difference(fh, 2, prob.dx)
     LV = _difference(hh, 2, prob.dx)
     if prob.dim == 1:
         return torch.cat([LU, LV])
     LW = _difference(eh, 2, prob.dx)
-    gh, th, xh = _direction_fluxes(U, W, V, prob, 1, alpha[1])
+    gh, th, xh = _direction_fluxes(U, W, V, prob, 1, alpha[1], t)
     LU = LU + _difference(gh, 1, prob.dy)
     LW = LW + _difference(th, 1, prob.dy)
     LV = LV + _difference(xh, 1, prob.dy)
     return torch.cat([LU, LV, LW])
 
 
-def limited_derivatives(S, prob: Problem):
-    """Limited derivatives: U_x along x (and U_y along y) by Section 2.2."""
+def limited_derivatives(S, prob: Problem, t: float = 0.0):
+    """Limited derivatives: U_x along x (and U_y along y) by Section 2.2, of the
+    state at time t."""
     U, V, W = _split(S, prob)
     d, eps, lin = prob.lim_w, prob.eps, prob.linear_limiter
 
@@ -512,8 +600,12 @@ def limited_derivatives(S, prob: Problem):
         n = U.shape[axis]
         dr = 0 if axis == 2 else 1
         pu, pn, _ = _parities(prob, dr) if bc == REFLECT else (None, None, None)
-        Up = _pad(U, axis, bc, 1, parity=pu)
-        Dp = _pad(D, axis, bc, 1, parity=pn)
+        if bc == EDGES:
+            Up = _pad_edges(U, axis, prob, dr, "U", t, 1)
+            Dp = _pad_edges(D, axis, prob, dr, "n", t, 1)
+        else:
+            Up = _pad(U, axis, bc, 1, parity=pu)
+            Dp = _pad(D, axis, bc, 1, parity=pn)
         um, u0, up = (Up.narrow(axis, k, n) for k in range(3))
         vm, vp = Dp.narrow(axis, 0, n), Dp.narrow(axis, 2, n)
         if not char:
@@ -536,11 +628,11 @@ def limited_derivatives(S, prob: Problem):
     return torch.cat(out)
 
 
-def hat(S, prob: Problem):
+def hat(S, prob: Problem, t: float = 0.0):
     """(U, limited derivatives), or S itself with the limiter switched off."""
     if not prob.limiter_on:
         return S
-    return torch.cat([S[:prob.m], limited_derivatives(S, prob)])
+    return torch.cat([S[:prob.m], limited_derivatives(S, prob, t)])
 
 
 def cfl_dt(alpha, prob: Problem) -> float:
@@ -550,22 +642,25 @@ def cfl_dt(alpha, prob: Problem) -> float:
     return prob.cfl / (alpha[0] / prob.dx + alpha[1] / prob.dy)
 
 
-def rk3_step(S, prob: Problem, dt: Optional[float] = None, alphas=None):
+def rk3_step(S, prob: Problem, dt: Optional[float] = None, alphas=None, t: float = 0.0):
     """One SSP-RK3 step with limited derivatives in the update only (Section 2.2).
 
     ``alphas``: optional per-stage wave speeds (replay); otherwise each stage
-    computes them from its own state.  Returns (S^{n+1}, dt, alphas).
+    computes them from its own state.  ``t``: time of S; the stage inputs sit
+    at t, t + dt and t + dt/2 (what edge-described sides read).
+    Returns (S^{n+1}, dt, alphas).
     """
     a = [None, None, None] if alphas is None else list(alphas)
     a[0] = a[0] if a[0] is not None else max_speeds(S, prob)
     if dt is None:
         dt = cfl_dt(a[0], prob)
-    H0 = hat(S, prob)
-    S1 = H0 + dt * rhs(S, prob, a[0])
+    t1, t2 = t + dt, t + 0.5 * dt
+    H0 = hat(S, prob, t)
+    S1 = H0 + dt * rhs(S, prob, a[0], t)
     a[1] = a[1] if a[1] is not None else max_speeds(S1, prob)
-    S2 = 0.75 * H0 + 0.25 * (hat(S1, prob) + dt * rhs(S1, prob, a[1]))
+    S2 = 0.75 * H0 + 0.25 * (hat(S1, prob, t1) + dt * rhs(S1, prob, a[1], t1))
     a[2] = a[2] if a[2] is not None else max_speeds(S2, prob)
-    S3 = H0 / 3.0 + 2.0 / 3.0 * (hat(S2, prob) + dt * rhs(S2, prob, a[2]))
+    S3 = H0 / 3.0 + 2.0 / 3.0 * (hat(S2, prob, t2) + dt * rhs(S2, prob, a[2], t2))
     return S3, dt, a
 
 
@@ -577,7 +672,7 @@ def run(S, prob: Problem, t_end: float, dt_rule=None, max_steps=10 ** 7):
         a0 = max_speeds(S, prob)
         dt = dt_rule(a0) if dt_rule is not None else cfl_dt(a0, prob)
         dt = min(dt, t_end - t)
-        S, _, _ = rk3_step(S, prob, dt, [a0, None, None])
+        S, _, _ = rk3_step(S, prob, dt, [a0, None, None], t)
         t += dt
         steps += 1
     return S, steps

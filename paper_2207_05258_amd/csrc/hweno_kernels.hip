@@ -96,6 +96,37 @@ __host__ __device__ __forceinline__ int mirror_sign(int f, int m, bool euler, in
   return s;
 }
 
+// Sides described by hweno_edge (HWENO_BC_EDGES) in kernel-argument form;
+// sides 0..3 = x_lo, x_hi, y_lo, y_hi.
+struct EdgeArgs {
+  int kind[4][2];
+  int mirror[4];  // the side stages with the mirror map (it has a wall segment)
+  double split[4][3];
+  double state[4][2][4];
+  double t0;      // time of the state read by the right-hand side and the limiter entry points
+};
+
+// map_index2 with a per-side choice between mirror and copy on edge-described
+// directions; always inside the grid
+__device__ __forceinline__ int map_edge(int i, int n, int bc, int mlo, int mhi) {
+  if (bc != HWENO_BC_EDGES) return map_index2(i, n, bc);
+  if (i < 0)
+    i = mlo ? -1 - i : 0;
+  else if (i >= n)
+    i = mhi ? 2 * n - 1 - i : n - 1;
+  return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+// Segment (0 or 1) of side `side` taken by a ghost cell at position `pos`
+// along the side, `depth` beyond it, at time t: split = s0 + s1 t + s2 depth,
+// evaluated in that order with separately rounded products and sums.
+__device__ __forceinline__ int edge_segment(const EdgeArgs& e, int side, double pos, double depth,
+                                            double t) {
+  const double sp = __dadd_rn(__dadd_rn(e.split[side][0], __dmul_rn(e.split[side][1], t)),
+                              __dmul_rn(e.split[side][2], depth));
+  return pos < sp ? 0 : 1;
+}
+
 // Loads and stores through the global address space.  Pointers that arrive
 // through memory (the batched instance descriptors) are generic to the
 // compiler, which then cannot rule out aliasing with the LDS tile and
@@ -244,11 +275,13 @@ __device__ __forceinline__ bool stage_dt(const StageArgs<double>* unused, double
 // ---------------------------------------------------------------------------
 // CL: the characteristic variant of the limiter (Euler; a separate
 // instantiation so the default kernels carry none of its code).
-template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT, bool CL>
+// EDG: edge-described sides (2D Euler; a separate instantiation), read from *e.
+template <typename T, int PHYS, int DIM, int K, int TX, int TY, int NT, bool CL, bool EDG = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T>& k,
                                            int tile_x, int tile_y, double dt, double alx,
                                            double aly, T* __restrict__ sm, T* __restrict__ fb,
-                                           T& sx, T& sy, uint32_t& flags) {
+                                           T& sx, T& sy, uint32_t& flags,
+                                           const EdgeArgs* e = nullptr) {
   constexpr int M = Comps<PHYS, DIM>::M;
   constexpr int NF = Comps<PHYS, DIM>::NF;
   constexpr int HY = (DIM == 2) ? 2 : 0;
@@ -274,8 +307,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
     if (q < W * HR) {
       const int lr = q / W, lc = q - lr * W;
       const int ii = i0 - 2 + lc, jj = j0 - HY + lr;
-      const int gi = map_index2(ii, nx, a.bc_x);
-      const int gj = (DIM == 2) ? map_index2(jj, ny, a.bc_y) : 0;
+      int gi, gj;
+      if constexpr (EDG) {
+        gi = map_edge(ii, nx, a.bc_x, e->mirror[0], e->mirror[1]);
+        gj = map_edge(jj, ny, a.bc_y, e->mirror[2], e->mirror[3]);
+      } else {
+        gi = map_index2(ii, nx, a.bc_x);
+        gj = (DIM == 2) ? map_index2(jj, ny, a.bc_y) : 0;
+      }
       const long long g = (long long)gj * nx + gi;
 #pragma unroll
       for (int f = 0; f < NF; ++f) v[r][f] = gld(a.in + f * fs + g);
@@ -307,6 +346,38 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
           const int sg = (mx ? mirror_sign(f, M, true, 0) : 1) * (my ? mirror_sign(f, M, true, 1) : 1);
           if (sg < 0) sm[f * HR * W + q] = -sm[f * HR * W + q];
         }
+      }
+    }
+  }
+  if constexpr (EDG) {
+    // Edge-described sides, at the time of this stage's input: ghost cells of
+    // a wall segment take the mirror signs, those of an inflow segment the
+    // prescribed state with zero derivatives; outflow segments keep the copy
+    // staged above.  Corner ghosts take both rules; no stencil reads them.
+    const bool ex = a.bc_x == HWENO_BC_EDGES && (i0 - 2 < 0 || i0 - 2 + W > nx);
+    const bool ey = a.bc_y == HWENO_BC_EDGES && (j0 - HY < 0 || j0 - HY + HR > ny);
+    if (ex || ey) {
+      const double te = (K == 0) ? e->t0 : a.ctrl[7] + (K == 1 ? 0.0 : (K == 2 ? dt : 0.5 * dt));
+      for (int q = tid; q < W * HR; q += NT) {
+        const int lr = q / W, lc = q - lr * W;
+        const int ii = i0 - 2 + lc, jj = j0 - HY + lr;
+        auto apply = [&](int side, int d, double pos, double depth) {
+          const int sg = edge_segment(*e, side, pos, depth, te);
+          const int kd = e->kind[side][sg];
+          if (kd == HWENO_SEG_REFLECT) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+              if (mirror_sign(f, M, true, d) < 0) sm[f * HR * W + q] = -sm[f * HR * W + q];
+          } else if (kd == HWENO_SEG_STATE) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f)
+              sm[f * HR * W + q] = f < M ? T(e->state[side][sg][f]) : T(0);
+          }
+        };
+        if (ex && ii < 0) apply(0, 0, (jj + 0.5) * a.dy, (-ii - 0.5) * a.dx);
+        if (ex && ii >= nx) apply(1, 0, (jj + 0.5) * a.dy, (ii - nx + 0.5) * a.dx);
+        if (ey && jj < 0) apply(2, 1, (ii + 0.5) * a.dx, (-jj - 0.5) * a.dy);
+        if (ey && jj >= ny) apply(3, 1, (ii + 0.5) * a.dx, (jj - ny + 0.5) * a.dy);
       }
     }
   }
@@ -541,6 +612,53 @@ __global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs
   uint32_t flags = 0;
   stage_tile<T, PHYS, DIM, K, TX, TY, NT, CL>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb, sx, sy,
                                               flags);
+  if constexpr (K > 0) {
+    // speeds of the new stage state feed the next stage's splitting; after
+    // stage 3 they are the next step's stage-1 speeds (multi-step calls)
+    block_fold<NT>(double(sx), double(sy), flags, a.ctrl + (K < 3 ? 2 * K : 10), a.status,
+                   !a.replay && (K < 3 || a.fold_next));
+  }
+}
+
+// 2D Euler with edge-described sides (component-wise limiter).  The body
+// repeats k_stage's: handing the kernel parameters to a shared device
+// function by reference costs k_stage its register allocation (spills).
+// Three waves per SIMD in FP32: at five the boundary fix-up spills.
+template <typename T>
+struct EdgeOcc {
+  static constexpr int WAVES = sizeof(T) == 4 ? 3 : 2;
+};
+
+template <typename T, int K, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT, (EdgeOcc<T>::WAVES)) void k_stage_edges(StageArgs<T> a,
+                                                                             Consts<T> k,
+                                                                             EdgeArgs e) {
+  constexpr int PHYS = PH_EULER, DIM = 2;
+  constexpr int M = Comps<PHYS, DIM>::M;
+  constexpr int NF = Comps<PHYS, DIM>::NF;
+  constexpr int HY = (DIM == 2) ? 2 : 0;
+  constexpr int NQ = (DIM == 2) ? 3 : 2;
+  __shared__ T sm[NF * (TY + 2 * HY) * (TX + 4)];
+  __shared__ T fb[NQ * M * (TY + 1) * (TX + 1)];
+
+  double dt = 0.0, alx, aly;
+  if constexpr (K == 0) {
+    alx = a.alpha[0];
+    aly = a.alpha[1];
+  } else {
+    alx = a.ctrl[2 * (K - 1)];
+    aly = a.ctrl[2 * (K - 1) + 1];
+    if (!stage_dt<DIM, K>(nullptr, a.ctrl, a.dt_fixed, a.t_end, a.cfl, a.dx, a.dy, a.replay,
+                          blockIdx.x == 0 && threadIdx.x == 0, a.status, dt))
+      return;  // uniform over the grid: the step is skipped
+  }
+  const int ntx = (a.nx + TX - 1) / TX;
+  const int t = xcd_band(blockIdx.x, gridDim.x);
+  const int tile_y = t / ntx, tile_x = t - tile_y * ntx;
+  T sx = T(0), sy = T(0);
+  uint32_t flags = 0;
+  stage_tile<T, PH_EULER, 2, K, TX, TY, NT, false, true>(a, k, tile_x, tile_y, dt, alx, aly, sm,
+                                                         fb, sx, sy, flags, &e);
   if constexpr (K > 0) {
     // speeds of the new stage state feed the next stage's splitting; after
     // stage 3 they are the next step's stage-1 speeds (multi-step calls)
@@ -1267,44 +1385,70 @@ __global__ void k_finish(double* ctrl, double* tape, int begin_next) {
 }
 
 // limited derivatives (Section 2.2), one thread per cell, all components
+// One neighbour of a cell for the limiter: its cell index and what a ghost
+// there holds (0: a copy, 1: the mirror image with the wall signs, 2: the
+// prescribed state `st` with zero derivatives).
+struct LimNb {
+  long long at;
+  int mode;
+  const double* st;
+};
+
 template <typename T, int PHYS, int DIM>
 __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __restrict__ out,
                                                int nx, int ny, int bc_x, int bc_y,
-                                               double dx, double dy, Consts<T> k) {
+                                               double dx, double dy, Consts<T> k, EdgeArgs e) {
   constexpr int M = Comps<PHYS, DIM>::M;
   const long long n = (long long)nx * ny;
   const long long i = blockIdx.x * 256ll + threadIdx.x;
   if (i >= n) return;
   const int gj = (int)(i / nx), gi = (int)(i - (long long)gj * nx);
   constexpr bool EU = PHYS == PH_EULER;
-  const long long xm = (long long)gj * nx + map_index(gi - 1, nx, bc_x);
-  const long long xp = (long long)gj * nx + map_index(gi + 1, nx, bc_x);
-  const bool mxm = mirrored(gi - 1, nx, bc_x), mxp = mirrored(gi + 1, nx, bc_x);
-  // value of field f at a neighbour, with the wall signs when it is a mirrored ghost
-  auto nb = [&](int f, long long at, bool mir, int d) {
-    const T x = S[f * n + at];
-    return (mir && mirror_sign(f, M, EU, d) < 0) ? -x : x;
+  // neighbour at index q (column or row) along direction d; one cell deep,
+  // so mirror and copy read the same interior cell
+  auto neighbour = [&](int q, int d) -> LimNb {
+    const int nn = d == 0 ? nx : ny, bc = d == 0 ? bc_x : bc_y;
+    const int mq = map_index(q, nn, bc);
+    LimNb r;
+    r.at = d == 0 ? (long long)gj * nx + mq : (long long)mq * nx + gi;
+    r.mode = mirrored(q, nn, bc) ? 1 : 0;
+    r.st = nullptr;
+    if (bc == HWENO_BC_EDGES && (q < 0 || q >= nn)) {
+      const int side = 2 * d + (q < 0 ? 0 : 1);
+      const double pos = d == 0 ? (gj + 0.5) * dy : (gi + 0.5) * dx;
+      const int sg = edge_segment(e, side, pos, 0.5 * (d == 0 ? dx : dy), e.t0);
+      const int kd = e.kind[side][sg];
+      r.mode = kd == HWENO_SEG_REFLECT ? 1 : (kd == HWENO_SEG_STATE ? 2 : 0);
+      r.st = e.state[side][sg];
+    }
+    return r;
+  };
+  const LimNb nxm = neighbour(gi - 1, 0), nxp = neighbour(gi + 1, 0);
+  // value of field f at a neighbour: a copy, the wall signs of a mirrored
+  // ghost, or an inflow state
+  auto nbv = [&](int f, const LimNb& b, int d) -> T {
+    if (b.mode == 2) return f < M ? T(b.st[f]) : T(0);
+    const T x = S[f * n + b.at];
+    return (b.mode == 1 && mirror_sign(f, M, EU, d) < 0) ? -x : x;
   };
   if (EU && k.limiter_char) {
     // characteristic variant (normal frame: the momenta swap places for y)
     T um[M], u0[M], up[M], vm[M], vp[M], r[M];
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      um[c] = nb(c, xm, mxm, 0), u0[c] = S[c * n + i], up[c] = nb(c, xp, mxp, 0);
-      vm[c] = nb(M + c, xm, mxm, 0), vp[c] = nb(M + c, xp, mxp, 0);
+      um[c] = nbv(c, nxm, 0), u0[c] = S[c * n + i], up[c] = nbv(c, nxp, 0);
+      vm[c] = nbv(M + c, nxm, 0), vp[c] = nbv(M + c, nxp, 0);
     }
     limit_char<T, M>(um, u0, up, vm, vp, T(dx), T(1.0 / dx), k.lw, k.gm1, r);
 #pragma unroll
     for (int c = 0; c < M; ++c) out[c * n + i] = r[c];
     if constexpr (DIM == 2) {
-      const long long ym = (long long)map_index(gj - 1, ny, bc_y) * nx + gi;
-      const long long yp = (long long)map_index(gj + 1, ny, bc_y) * nx + gi;
-      const bool mym = mirrored(gj - 1, ny, bc_y), myp = mirrored(gj + 1, ny, bc_y);
+      const LimNb nym = neighbour(gj - 1, 1), nyp = neighbour(gj + 1, 1);
 #pragma unroll
       for (int c = 0; c < M; ++c) {
         const int q = (c == 1) ? 2 : (c == 2) ? 1 : c;
-        um[c] = nb(q, ym, mym, 1), u0[c] = S[q * n + i], up[c] = nb(q, yp, myp, 1);
-        vm[c] = nb(2 * M + q, ym, mym, 1), vp[c] = nb(2 * M + q, yp, myp, 1);
+        um[c] = nbv(q, nym, 1), u0[c] = S[q * n + i], up[c] = nbv(q, nyp, 1);
+        vm[c] = nbv(2 * M + q, nym, 1), vp[c] = nbv(2 * M + q, nyp, 1);
       }
       limit_char<T, M>(um, u0, up, vm, vp, T(dy), T(1.0 / dy), k.lw, k.gm1, r);
 #pragma unroll
@@ -1314,18 +1458,15 @@ __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __res
   }
 #pragma unroll
   for (int c = 0; c < M; ++c) {
-    out[c * n + i] = limit1(nb(c, xm, mxm, 0), S[c * n + i], nb(c, xp, mxp, 0),
-                            nb(M + c, xm, mxm, 0), nb(M + c, xp, mxp, 0), T(dx), T(1.0 / dx),
-                            k.lw);
+    out[c * n + i] = limit1(nbv(c, nxm, 0), S[c * n + i], nbv(c, nxp, 0), nbv(M + c, nxm, 0),
+                            nbv(M + c, nxp, 0), T(dx), T(1.0 / dx), k.lw);
   }
   if constexpr (DIM == 2) {
-    const long long ym = (long long)map_index(gj - 1, ny, bc_y) * nx + gi;
-    const long long yp = (long long)map_index(gj + 1, ny, bc_y) * nx + gi;
-    const bool mym = mirrored(gj - 1, ny, bc_y), myp = mirrored(gj + 1, ny, bc_y);
+    const LimNb nym = neighbour(gj - 1, 1), nyp = neighbour(gj + 1, 1);
 #pragma unroll
     for (int c = 0; c < M; ++c) {
-      out[(M + c) * n + i] = limit1(nb(c, ym, mym, 1), S[c * n + i], nb(c, yp, myp, 1),
-                                    nb(2 * M + c, ym, mym, 1), nb(2 * M + c, yp, myp, 1), T(dy),
+      out[(M + c) * n + i] = limit1(nbv(c, nym, 1), S[c * n + i], nbv(c, nyp, 1),
+                                    nbv(2 * M + c, nym, 1), nbv(2 * M + c, nyp, 1), T(dy),
                                     T(1.0 / dy), k.lw);
     }
   }
@@ -1414,6 +1555,10 @@ bool weights_ok(const double* w) {
   return std::fabs(w[0] + w[1] + w[2] - 1.0) <= 1e-12;
 }
 
+bool has_edges(const hweno_problem* p) {
+  return p->bc_x == HWENO_BC_EDGES || (p->dim == 2 && p->bc_y == HWENO_BC_EDGES);
+}
+
 hweno_status validate(const hweno_problem* p) {
   if (!p) return fail(HWENO_ERR_INVALID_ARG, "problem pointer is NULL");
   if (p->dim != 1 && p->dim != 2) return fail(HWENO_ERR_INVALID_ARG, "dim must be 1 or 2 (got %d)", p->dim);
@@ -1425,10 +1570,50 @@ hweno_status validate(const hweno_problem* p) {
   if (p->dtype != HWENO_F32 && p->dtype != HWENO_F64)
     return fail(HWENO_ERR_INVALID_ARG, "unknown dtype %d", p->dtype);
   auto bc_ok = [](int b) {
-    return b == HWENO_BC_PERIODIC || b == HWENO_BC_OUTFLOW || b == HWENO_BC_REFLECT;
+    return b == HWENO_BC_PERIODIC || b == HWENO_BC_OUTFLOW || b == HWENO_BC_REFLECT ||
+           b == HWENO_BC_EDGES;
   };
   if (!bc_ok(p->bc_x) || (p->dim == 2 && !bc_ok(p->bc_y)))
     return fail(HWENO_ERR_INVALID_ARG, "unknown boundary condition");
+  if (has_edges(p)) {
+    if (p->physics != HWENO_EULER || p->dim != 2 || p->limiter_characteristic)
+      return fail(HWENO_ERR_UNSUPPORTED,
+                  "edge-described sides are built for 2D Euler with the component-wise limiter");
+    for (int d = 0; d < 2; ++d) {
+      if ((d == 0 ? p->bc_x : p->bc_y) != HWENO_BC_EDGES) continue;
+      const int across = d == 0 ? p->nx : p->ny;
+      for (int side = 0; side < 2; ++side) {
+        const hweno_edge& e = p->edges[2 * d + side];
+        bool out = false, wall = false;
+        for (int sg = 0; sg < 2; ++sg) {
+          const int kd = e.kind[sg];
+          if (kd != HWENO_SEG_OUTFLOW && kd != HWENO_SEG_REFLECT && kd != HWENO_SEG_STATE)
+            return fail(HWENO_ERR_INVALID_ARG, "edge %d: unknown segment kind %d", 2 * d + side, kd);
+          out = out || kd == HWENO_SEG_OUTFLOW;
+          wall = wall || kd == HWENO_SEG_REFLECT;
+          if (kd == HWENO_SEG_STATE) {
+            const double* q = e.state[sg];
+            for (int c = 0; c < 4; ++c)
+              if (!std::isfinite(q[c]))
+                return fail(HWENO_ERR_INVALID_ARG, "edge %d: state %d is not finite", 2 * d + side, sg);
+            const double pr =
+                (p->gamma_gas - 1.0) * (q[3] - 0.5 * (q[1] * q[1] + q[2] * q[2]) / q[0]);
+            if (!(q[0] > 0.0) || !(pr > 0.0))
+              return fail(HWENO_ERR_INVALID_ARG,
+                          "edge %d: state %d needs positive density and pressure", 2 * d + side, sg);
+          }
+        }
+        for (int k = 0; k < 3; ++k)
+          if (!std::isfinite(e.split[k]))
+            return fail(HWENO_ERR_INVALID_ARG, "edge %d: split is not finite", 2 * d + side);
+        if (out && wall)
+          return fail(HWENO_ERR_INVALID_ARG, "edge %d combines an outflow and a wall segment",
+                      2 * d + side);
+        if (wall && across < 2)
+          return fail(HWENO_ERR_INVALID_ARG, "a reflecting wall needs at least 2 cells across");
+      }
+    }
+  }
   if (p->physics != HWENO_EULER &&
       (p->bc_x == HWENO_BC_REFLECT || (p->dim == 2 && p->bc_y == HWENO_BC_REFLECT)))
     return fail(HWENO_ERR_UNSUPPORTED, "reflecting walls are defined for the Euler equations only");
@@ -1541,6 +1726,22 @@ hweno_status dispatch(const hweno_problem* p, Args&&... args) {
   return fail(HWENO_ERR_UNSUPPORTED, "unsupported combination");
 }
 
+EdgeArgs edge_args(const hweno_problem* p) {
+  EdgeArgs e;
+  std::memset(&e, 0, sizeof e);
+  for (int side = 0; side < 4; ++side) {
+    const hweno_edge& h = p->edges[side];
+    for (int sg = 0; sg < 2; ++sg) {
+      e.kind[side][sg] = h.kind[sg];
+      for (int c = 0; c < 4; ++c) e.state[side][sg][c] = h.state[sg][c];
+    }
+    e.mirror[side] = h.kind[0] == HWENO_SEG_REFLECT || h.kind[1] == HWENO_SEG_REFLECT;
+    for (int q = 0; q < 3; ++q) e.split[side][q] = h.split[q];
+  }
+  e.t0 = 0.0;
+  return e;
+}
+
 template <typename T, int PHYS, int DIM>
 StageArgs<T> base_args(const hweno_problem* p) {
   StageArgs<T> a;
@@ -1597,6 +1798,13 @@ struct RunRhs {
     a.out = (T*)rhs;
     a.alpha = alpha;
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
+    if constexpr (PHYS == PH_EULER && DIM == 2) {
+      if (has_edges(p)) {
+        k_stage_edges<T, 0, TX, TY, NT><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
+            a, make_consts<T>(p), edge_args(p));
+        return launch_check("rhs");
+      }
+    }
     k_stage<T, PHYS, DIM, 0, TX, TY, NT, false><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
         a, make_consts<T>(p));
     return launch_check("rhs");
@@ -1611,7 +1819,7 @@ struct RunLimit {
     k_limit<T, PHYS, DIM><<<blocks, 256, 0, s>>>((const T*)state, (T*)out, p->nx,
                                                  DIM == 2 ? p->ny : 1, p->bc_x, p->bc_y,
                                                  p->dx, DIM == 2 ? p->dy : 1.0,
-                                                 make_consts<T>(p));
+                                                 make_consts<T>(p), edge_args(p));
     return launch_check("limit");
   }
 };
@@ -1661,6 +1869,22 @@ struct RunStep {
       timed(s, [&] { k_stage<T, PHYS, DIM, 3, TX, TY, NT, CL><<<grid, NT, 0, s>>>(a, k); });
     };
     if constexpr (PHYS == PH_EULER) {
+      if constexpr (DIM == 2) {
+        if (has_edges(p)) {
+          const EdgeArgs e = edge_args(p);
+          a.in = (const T*)state;
+          a.out = s1;
+          timed(s, [&] { k_stage_edges<T, 1, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
+          a.in = s1;
+          a.out = s2;
+          timed(s, [&] { k_stage_edges<T, 2, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
+          a.in = s2;
+          a.out = (T*)state;
+          timed(s, [&] { k_stage_edges<T, 3, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
+          k_finish<<<1, 64, 0, s>>>(ctrl, tape, fold_next && !replay ? 1 : 0);
+          return launch_check("rk3_step");
+        }
+      }
       if (char_limiter(p))
         stages(std::true_type{});
       else
@@ -1885,6 +2109,8 @@ hweno_status batch_common_ok(const hweno_problem* common) {
   if (!common) return fail(HWENO_ERR_INVALID_ARG, "problem pointer is NULL");
   if (common->dim != 2 || common->physics != HWENO_EULER)
     return fail(HWENO_ERR_UNSUPPORTED, "batched stepping is built for 2D Euler only");
+  if (has_edges(common))
+    return fail(HWENO_ERR_UNSUPPORTED, "batched stepping has no edge-described sides");
   hweno_problem q = *common;
   if (q.nx < 1) q.nx = 1;
   if (q.ny < 1) q.ny = 1;
@@ -1982,7 +2208,7 @@ hweno_status hweno_rk3_steps(const hweno_problem* prob, void* state, void* ws, s
 }
 
 size_t hweno_adjoint_workspace_bytes(const hweno_problem* prob) {
-  if (validate(prob) != HWENO_OK) return 0;
+  if (validate(prob) != HWENO_OK || has_edges(prob)) return 0;
   return adj_layout(prob).total;
 }
 
@@ -1991,6 +2217,7 @@ hweno_status hweno_rhs_adjoint(const hweno_problem* prob, const void* state, con
                                size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
+  if (has_edges(prob)) return fail(HWENO_ERR_UNSUPPORTED, "the adjoint has no edge-described sides");
   if (empty(prob)) return ok();
   if (!state || !alpha || !lam_rhs || !lam_state || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state, alpha, lam_rhs, lam_state and ws must be non-NULL");
@@ -2008,6 +2235,7 @@ hweno_status hweno_rk3_step_adjoint(const hweno_problem* prob, const void* state
                                     void* lam, void* ws, size_t ws_bytes, void* stream) {
   hweno_status st = validate(prob);
   if (st) return st;
+  if (has_edges(prob)) return fail(HWENO_ERR_UNSUPPORTED, "the adjoint has no edge-described sides");
   if (empty(prob)) return ok();
   if (!state0 || !step_ws || !tape || !lam || !ws)
     return fail(HWENO_ERR_INVALID_ARG, "state0, step_ws, tape, lam and ws must be non-NULL");
@@ -2051,6 +2279,8 @@ hweno_status hweno_batch_prepare(const hweno_problem* common, hweno_instance* in
     p.bc_y = I.bc_y;
     p.dx = I.dx;
     p.dy = I.dy;
+    if (has_edges(&p))
+      return fail(HWENO_ERR_UNSUPPORTED, "instance %d: batched stepping has no edge-described sides", q);
     st = validate(&p);
     if (st) return fail(st, "instance %d: %s", q, g_last_error.c_str());
     if (I.nx < 1 || I.ny < 1) return fail(HWENO_ERR_INVALID_ARG, "instance %d: nx, ny must be >= 1", q);

@@ -24,13 +24,33 @@ ST_NONFINITE, ST_RHO, ST_PRESSURE, ST_SKIPPED = 1, 2, 4, 8
 
 PHYSICS = {"linadv": 0, "burgers": 1, "euler": 2}
 DTYPES = {torch.float32: 0, torch.float64: 1}
-PERIODIC, OUTFLOW, REFLECT = 0, 1, 2
+PERIODIC, OUTFLOW, REFLECT, EDGES = 0, 1, 2, 3
+SEG_OUTFLOW, SEG_REFLECT, SEG_STATE = 0, 1, 2
 
 
 class HwenoError(RuntimeError):
     def __init__(self, code: int, where: str, detail: str):
         super().__init__(f"{where}: {_status_name(code)}: {detail}")
         self.code = code
+
+
+class _CEdge(ctypes.Structure):
+    _fields_ = [
+        ("kind", ctypes.c_int32 * 2), ("split", ctypes.c_double * 3),
+        ("state", (ctypes.c_double * 4) * 2),
+    ]
+
+
+@dataclass(frozen=True)
+class Edge:
+    """One side under bc EDGES (mirrors hweno_edge): ghost cells before the split
+    split[0] + split[1] t + split[2] d along the side take segment 0, the others
+    segment 1; kinds SEG_OUTFLOW / SEG_REFLECT / SEG_STATE (the conserved state
+    of that segment, derivatives zero)."""
+
+    kind: Tuple[int, int] = (SEG_OUTFLOW, SEG_OUTFLOW)
+    split: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    state: Tuple[Tuple[float, ...], Tuple[float, ...]] = ((0.0,) * 4, (0.0,) * 4)
 
 
 class _CProblem(ctypes.Structure):
@@ -44,6 +64,7 @@ class _CProblem(ctypes.Structure):
         ("gamma_gas", ctypes.c_double), ("adv_speed", ctypes.c_double * 2),
         ("lin_w", ctypes.c_double * 3), ("lim_w", ctypes.c_double * 3),
         ("eps", ctypes.c_double), ("cfl", ctypes.c_double),
+        ("edges", _CEdge * 4),
     ]
 
 
@@ -138,6 +159,8 @@ class Problem:
     lim_w: Tuple[float, float, float] = (0.98, 0.01, 0.01)
     eps: float = 1e-6
     cfl: float = 0.6
+    # sides x_lo, x_hi, y_lo, y_hi, read where bc_x / bc_y is EDGES
+    edges: Optional[Tuple[Edge, Edge, Edge, Edge]] = None
 
     @property
     def m(self) -> int:
@@ -167,6 +190,11 @@ class Problem:
         p.lin_w[:] = [float(x) for x in self.lin_w]
         p.lim_w[:] = [float(x) for x in self.lim_w]
         p.eps, p.cfl = float(self.eps), float(self.cfl)
+        for e, edge in enumerate(self.edges or ()):
+            p.edges[e].kind[:] = [int(x) for x in edge.kind]
+            p.edges[e].split[:] = [float(x) for x in edge.split]
+            for sgm in range(2):
+                p.edges[e].state[sgm][:] = [float(x) for x in edge.state[sgm]]
         return p
 
 

@@ -50,6 +50,17 @@ static hweno_problem base(std::mt19937_64& g) {
   p.cfl = pick(g) == 0 ? 0.0 : 0.6;
   if (pick(g) == 0) p.dx = NAN;
   if (pick(g) == 0) p.nx = 1 << 29;
+  // edge descriptions (read when a bc is HWENO_BC_EDGES): kinds 0..3, splits and
+  // states with the odd non-finite or non-physical value
+  std::uniform_real_distribution<double> v(-1.0, 3.0);
+  for (auto& e : p.edges) {
+    e.kind[0] = (int)(g() % 4), e.kind[1] = (int)(g() % 4);
+    for (double& x : e.split) x = pick(g) == 0 ? NAN : v(g);
+    for (auto& st : e.state) {
+      st[0] = 0.1 + std::fabs(v(g)), st[1] = v(g), st[2] = v(g), st[3] = 5.0 + v(g);
+      if (pick(g) == 0) st[3] = -1.0;
+    }
+  }
   return p;
 }
 
@@ -73,7 +84,15 @@ int main() {
       continue;
     }
     ++valid;
-    CHECK(ws > 0 && ws % 256 == 0 && wa > 0);
+    const bool edges = p.bc_x == HWENO_BC_EDGES || (p.dim == 2 && p.bc_y == HWENO_BC_EDGES);
+    CHECK(ws > 0 && ws % 256 == 0 && (edges ? wa == 0 : wa > 0));
+    if (edges) {
+      // the adjoint has no edge-described sides: refused before any pointer is read
+      CHECK(hweno_rhs_adjoint(&p, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, 0, nullptr) ==
+            HWENO_ERR_UNSUPPORTED);
+      CHECK(hweno_rk3_step_adjoint(&p, nullptr, nullptr, 0, nullptr, nullptr, nullptr, 0, nullptr) ==
+            HWENO_ERR_UNSUPPORTED);
+    }
     const bool empty = p.nx == 0 || (p.dim == 2 && p.ny == 0);
     // NULL buffers: refused, or nothing to do for an empty grid; never a HIP call
     const hweno_status s1 = hweno_rk3_step(&p, nullptr, nullptr, 0, 0.0, 0.0, nullptr, nullptr, nullptr);

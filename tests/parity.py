@@ -31,6 +31,9 @@ TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
 
 
 def gpu_problem(w: hi.Workload, dtype, **kw):
+    if w.edges is not None and "edges" not in kw:
+        kw["edges"] = tuple(h.Edge(kind=tuple(e[0]), split=tuple(e[1]),
+                                   state=(tuple(e[2][0]), tuple(e[2][1]))) for e in w.edges)
     return h.Problem(dim=w.dim, nx=w.nx, ny=w.ny, physics=w.physics, dtype=dtype, dx=w.dx,
                      dy=w.dy, bc_x=w.bc_x, bc_y=w.bc_y, gamma_gas=w.gamma_gas,
                      adv_speed=tuple(w.adv_speed), **kw)

@@ -191,3 +191,58 @@ def test_product_package_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def _edges_problem(**kw):
+    import hweno_inputs as hi
+    from tests import parity as P
+    w = hi.double_mach(64, 16)
+    return P.gpu_problem(w, torch.float64, **kw)
+
+
+def test_edge_described_sides_are_checked_on_host():
+    L = _lib_or_skip()
+    good = _edges_problem()
+    assert L.hweno_validate(ctypes.byref(good.c())) == 0
+    # the binding carries every edge field into the C struct
+    c = good.c()
+    assert c.bc_x == h.EDGES and c.edges[3].kind[0] == h.SEG_STATE
+    assert c.edges[2].kind[1] == h.SEG_REFLECT and c.edges[3].split[2] == good.edges[3].split[2]
+    # scalar laws, 1D and the characteristic limiter are not built with edges
+    assert L.hweno_validate(ctypes.byref(_prob(physics="burgers", bc_x=h.EDGES,
+                                                edges=good.edges).c())) == 2
+    assert L.hweno_validate(ctypes.byref(_edges_problem(limiter_characteristic=True).c())) == 2
+
+    def with_edge(k, **field):
+        e = good.edges[k]
+        e = h.Edge(**{**dict(kind=e.kind, split=e.split, state=e.state), **field})
+        return _edges_problem(edges=tuple(e if q == k else good.edges[q] for q in range(4)))
+    bad = [
+        with_edge(1, kind=(h.SEG_OUTFLOW, h.SEG_REFLECT)),    # copy and mirror on one side
+        with_edge(0, kind=(h.SEG_STATE, 7)),
+        with_edge(3, split=(0.7, float("nan"), 0.5)),
+        with_edge(0, state=((1.0, 0.0, 0.0, -1.0), (1.0, 0.0, 0.0, 2.5))),   # p < 0
+        with_edge(0, state=((0.0, 0.0, 0.0, 1.0), (1.0, 0.0, 0.0, 2.5))),    # rho = 0
+    ]
+    for p in bad:
+        assert L.hweno_validate(ctypes.byref(p.c())) == 1, L.hweno_last_error().decode()
+    thin = _edges_problem()
+    thin.ny = 1
+    assert L.hweno_validate(ctypes.byref(thin.c())) == 1        # a wall needs 2 cells across
+
+
+def test_edges_are_refused_by_the_adjoint_and_batched_entry_points_on_host():
+    L = _lib_or_skip()
+    c = _edges_problem().c()
+    assert L.hweno_adjoint_workspace_bytes(ctypes.byref(c)) == 0
+    assert L.hweno_rhs_adjoint(ctypes.byref(c), None, None, None, None, None, None, 0, None) == 2
+    assert L.hweno_rk3_step_adjoint(ctypes.byref(c), None, None, 0, None, None, None, 0, None) == 2
+    inst = (h.hweno._CInstance * 1)()
+    inst[0].nx, inst[0].ny, inst[0].dx, inst[0].dy = 64, 16, 1 / 16, 1 / 16
+    inst[0].bc_x = inst[0].bc_y = h.OUTFLOW
+    total = ctypes.c_int32(0)
+    assert L.hweno_batch_prepare(ctypes.byref(c), inst, 1, ctypes.byref(total)) == 2
+    plain = _prob().c()
+    assert L.hweno_batch_prepare(ctypes.byref(plain), inst, 1, ctypes.byref(total)) == 0
+    inst[0].bc_y = h.EDGES
+    assert L.hweno_batch_prepare(ctypes.byref(plain), inst, 1, ctypes.byref(total)) == 2

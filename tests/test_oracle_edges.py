@@ -1,0 +1,156 @@
+"""Pins of the oracle's edge-described sides (the boundaries of Example 3.11).
+
+Each test compares against something built without the edge rule:
+  * edges whose segments are all walls, or all outflow copies, are the plain
+    reflecting / outflow boundaries, which have their own pins;
+  * a uniform flow along a channel (inflow of the same state, outflow, walls
+    parallel to the flow) is an exact steady solution: the operator vanishes;
+  * a contact discontinuity (uniform velocity and pressure, density jump along
+    a straight line) is advected exactly by the Euler equations.  Its ghost cells
+    described by moving, depth-dependent splits must be the exact solution in a
+    domain two cells wider on every side, so the operator and the limiter on the
+    small domain equal those of the wide domain on the same cells.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import hweno_inputs as hi
+from oracle import hweno_ref as o
+
+GAM = 1.4
+
+
+def _cons(rho, u, v, p):
+    return (rho, rho * u, rho * v, p / (GAM - 1.0) + 0.5 * rho * (u * u + v * v))
+
+
+def _edge(kinds, split=(0.0, 0.0, 0.0), states=((1.0, 0.0, 0.0, 2.5),) * 2):
+    return o.Edge(kind=tuple(kinds), split=tuple(split), state=tuple(tuple(s) for s in states))
+
+
+def _smooth(nx=20, ny=18):
+    w = hi.euler2d_random_smooth(nx, ny, 3)
+    return o.as_tensor(w.S), w
+
+
+def test_all_wall_and_all_outflow_edges_are_the_plain_boundaries():
+    S, w = _smooth()
+    base = dict(dim=2, physics="euler", dx=w.dx, dy=w.dy)
+    plain = o.Problem(bc_x=o.REFLECT, bc_y=o.OUTFLOW, **base)
+    wall = _edge((o.SEG_REFLECT, o.SEG_REFLECT), (0.3, 1.0, 0.2))
+    out = _edge((o.SEG_OUTFLOW, o.SEG_OUTFLOW), (0.5, -2.0, 0.7))
+    edged = o.Problem(bc_x=o.EDGES, bc_y=o.EDGES, edges=(wall, wall, out, out), **base)
+    a = o.max_speeds(S, plain)
+    for t in (0.0, 0.13):
+        assert torch.equal(o.rhs(S, edged, a, t), o.rhs(S, plain, a))
+        assert torch.equal(o.limited_derivatives(S, edged, t), o.limited_derivatives(S, plain))
+    s1, _, _ = o.rk3_step(S, plain)
+    s2, _, _ = o.rk3_step(S, edged, t=0.4)
+    assert torch.equal(s1, s2)
+
+
+def test_uniform_channel_flow_is_stationary():
+    nx, ny = 24, 12
+    q = _cons(1.3, 0.7, 0.0, 2.0)
+    U = torch.tensor(q, dtype=torch.float64).view(4, 1, 1).expand(4, ny, nx)
+    S = torch.cat([U, torch.zeros(8, ny, nx, dtype=torch.float64)])
+    inflow = _edge((o.SEG_STATE, o.SEG_STATE), (0.0, 0.0, 0.0), (q, q))
+    out = _edge((o.SEG_OUTFLOW, o.SEG_OUTFLOW))
+    # bottom: inflow of the same state up to x = 0.4, then a wall; top: a wall
+    bottom = _edge((o.SEG_STATE, o.SEG_REFLECT), (0.4, 0.0, 0.0), (q, q))
+    top = _edge((o.SEG_REFLECT, o.SEG_REFLECT))
+    prob = o.Problem(dim=2, physics="euler", dx=1.0 / nx, dy=0.5 / ny, bc_x=o.EDGES,
+                     bc_y=o.EDGES, edges=(inflow, out, bottom, top))
+    L = o.rhs(S, prob, None, 0.25)
+    assert float(L.abs().max()) <= 1e-12 * max(abs(x) for x in q) * nx
+    S1, _, _ = o.rk3_step(S, prob, t=0.25)
+    assert float((S1 - S).abs().max()) <= 1e-13 * max(abs(x) for x in q)
+
+
+def _contact(theta, c, vel, rhos, p, lo, n, h, t, pad):
+    """Cell-centre data of the advected contact on a grid of n = (nx, ny) cells of
+    size h from lo, with ``pad`` extra cells on every side."""
+    nx, ny = n
+    xs = lo[0] + (np.arange(-pad, nx + pad) + 0.5) * h[0]
+    ys = lo[1] + (np.arange(-pad, ny + pad) + 0.5) * h[1]
+    X, Y = np.meshgrid(xs, ys)
+    w = vel[0] * math.cos(theta) + vel[1] * math.sin(theta)
+    A = X * math.cos(theta) + Y * math.sin(theta) < c + w * t
+    qa, qb = _cons(rhos[0], vel[0], vel[1], p), _cons(rhos[1], vel[0], vel[1], p)
+    U = np.stack([np.where(A, qa[k], qb[k]) for k in range(4)])
+    return torch.cat([torch.as_tensor(U), torch.zeros(8, *U.shape[1:], dtype=torch.float64)])
+
+
+@pytest.mark.parametrize("theta_deg", [50.0, 125.0])
+def test_moving_oblique_contact_ghosts_equal_a_wider_domain(theta_deg):
+    theta = math.radians(theta_deg)
+    nx, ny, Lx, Ly = 24, 20, 1.0, 1.0
+    h = (Lx / nx, Ly / ny)
+    vel, rhos, p, t = (0.3, -0.2), (1.0, 0.4), 1.0, 0.37
+    ct, st = math.cos(theta), math.sin(theta)
+    c = 0.55 if theta_deg < 90 else 0.25
+    w = vel[0] * ct + vel[1] * st
+    qa, qb = _cons(rhos[0], vel[0], vel[1], p), _cons(rhos[1], vel[0], vel[1], p)
+    # side-by-side: the region x cos + y sin < c + w t holds state A; on each side the
+    # boundary of that region, solved for the coordinate along the side, is the split,
+    # and segment 0 (before the split) is A where the coordinate's coefficient is > 0
+    def side(s0, s1, s2, coef):
+        kinds = (o.SEG_STATE, o.SEG_STATE)
+        states = (qa, qb) if coef > 0 else (qb, qa)
+        return _edge(kinds, (s0, s1, s2), states)
+    left = side(c / st, w / st, ct / st, st)                       # x = -d
+    right = side((c - Lx * ct) / st, w / st, -ct / st, st)         # x = Lx + d
+    bottom = side(c / ct, w / ct, st / ct, ct)                     # y = -d
+    top = side((c - Ly * st) / ct, w / ct, -st / ct, ct)           # y = Ly + d
+    small = _contact(theta, c, vel, rhos, p, (0.0, 0.0), (nx, ny), h, t, 0)
+    wide = _contact(theta, c, vel, rhos, p, (0.0, 0.0), (nx, ny), h, t, 2)
+    # both states occur inside the small domain
+    assert 0 < int((small[0] == rhos[0]).sum()) < nx * ny
+    ps = o.Problem(dim=2, physics="euler", dx=h[0], dy=h[1], bc_x=o.EDGES, bc_y=o.EDGES,
+                   edges=(left, right, bottom, top))
+    pw = o.Problem(dim=2, physics="euler", dx=h[0], dy=h[1], bc_x=o.OUTFLOW, bc_y=o.OUTFLOW)
+    a = o.max_speeds(small, ps)
+    inner = (slice(None), slice(2, 2 + ny), slice(2, 2 + nx))
+    Ls, Lw = o.rhs(small, ps, a, t), o.rhs(wide, pw, a)[inner]
+    scale = float(Lw.abs().max())
+    assert scale > 0
+    assert float((Ls - Lw).abs().max()) <= 1e-13 * scale
+    Ds = o.limited_derivatives(small, ps, t)
+    Dw = o.limited_derivatives(wide, pw)[inner]
+    assert float((Ds - Dw).abs().max()) <= 1e-13 * (float(Dw.abs().max()) + 1.0)
+    # the same sides read at another time do not give the wide domain's operator
+    assert float((o.rhs(small, ps, a, t + 0.2) - Lw).abs().max()) > 1e-3 * scale
+
+
+def test_double_mach_initial_state_is_consistent_with_its_edges():
+    """At t = 0 the top side's split is where the shock line crosses each ghost row,
+    and the left side holds the post-shock state the interior holds near it."""
+    w = hi.double_mach(48, 12)
+    prob = o.problem_from_workload(w)
+    S = o.as_tensor(w.S)
+    # the operator vanishes on every cell whose stencils (three cells either way,
+    # ghosts included) see one state only: the inflow, wall and top ghosts continue
+    # the data there; next to the shock it does not vanish
+    x = (np.arange(w.nx) + 0.5) * w.dx
+    y = (np.arange(-3, w.ny + 3) + 0.5) * w.dy
+    xs = np.concatenate([np.full(3, -1.0), x, np.full(3, 9.0)])
+    behind = xs[None, :] < 1.0 / 6.0 + y[:, None] / math.sqrt(3.0)
+    uniform = np.ones((w.ny, w.nx), dtype=bool)
+    for dj in range(-3, 4):
+        for di in range(-3, 4):
+            uniform &= behind[3 + dj:3 + dj + w.ny, 3 + di:3 + di + w.nx] == behind[3:-3, 3:-3]
+    # the bottom wall beyond x = 1/6 mirrors the pre-shock state, which is at rest
+    assert uniform.sum() > w.nx * w.ny // 2
+    L = o.rhs(S, prob, None, 0.0)
+    Lu = L[:, torch.as_tensor(uniform)]
+    assert float(Lu.abs().max()) <= 1e-12 * float(L.abs().max())
+    assert float(L[:, torch.as_tensor(~uniform)].abs().max()) > 1e-3 * float(L.abs().max())
+    # the shock crosses the top row's ghost cells where the interior line continues
+    top = prob.edges[3]
+    x_top = 1.0 / 6.0 + 1.0 / math.sqrt(3.0)
+    assert top.split[0] == pytest.approx(x_top, rel=1e-15)
+    assert top.split[2] == pytest.approx(1.0 / math.sqrt(3.0), rel=1e-15)
+    assert top.split[1] == pytest.approx(10.0 / math.sin(math.pi / 3.0), rel=1e-14)
