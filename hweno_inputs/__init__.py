@@ -54,6 +54,8 @@ class Workload:
     # position pos along the side, d beyond it, at time t takes segment 0 when
     # pos < s0 + s1 t + s2 d (conserved states, zero derivatives for SEG_STATE)
     edges: Optional[tuple] = None
+    # (i_s, j_s): cells i >= i_s, j < j_s are solid (a step against the bottom-right corner)
+    obstacle: Optional[tuple] = None
 
     @property
     def nx(self) -> int:
@@ -268,6 +270,26 @@ def double_mach(nx: int, ny: int) -> Workload:
                     lo, hi, name=f"double_mach_{nx}x{ny}",
                     info={"t_end": 0.2, "shock_speed": s, "post": post, "pre": pre},
                     edges=(inflow, outflow, bottom, top))
+
+def forward_step(nx: int, ny: int) -> Workload:
+    """Forward-facing step (Example 3.12): a wind tunnel [0, 3] x [0, 1] with a step
+    from x = 0.6 to the exit, 0.2 high, filled with a right-going Mach 3 flow
+    (rho, u, v, p) = (1.4, 3, 0, 1); inflow of that state on the left, outflow on the
+    right, walls on the bottom, the top and the step; T = 4.  nx and ny must be
+    multiples of 5 so that the step's faces fall on cell faces."""
+    if nx % 5 or ny % 5:
+        raise ValueError("nx and ny must be multiples of 5")
+    lo, hi = (0.0, 0.0), (3.0, 1.0)
+    free = (1.4, 3.0, 0.0, 1.0)
+    U = conserved_2d(*[np.full((ny, nx), q) for q in free])
+    S = np.concatenate([U, np.zeros_like(U), np.zeros_like(U)])
+    q = tuple(float(v[0, 0]) for v in conserved_2d(*[np.full((1, 1), c) for c in free]))
+    inflow = ((SEG_STATE, SEG_STATE), (0.0, 0.0, 0.0), (q, q))
+    outflow = ((SEG_OUTFLOW, SEG_OUTFLOW), (0.0, 0.0, 0.0), (q, q))
+    return Workload(S, 2, "euler", (hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny, EDGES, REFLECT,
+                    lo, hi, name=f"forward_step_{nx}x{ny}", info={"t_end": 4.0, "free": free},
+                    edges=(inflow, outflow, outflow, outflow), obstacle=(nx // 5, ny // 5))
+
 
 def euler2d_quadrants(nx: int, ny: int, seed: int, bc=OUTFLOW) -> Workload:
     """Four constant quadrants of [0,1]^2 split at x = 1/2, y = 1/2.

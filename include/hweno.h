@@ -96,9 +96,9 @@ typedef struct {
  *                 have no mirror symmetry with the same flux); at least 2
  *                 cells across the wall's direction.
  *                 edges = each side of the direction described by `edges`
- *                 (2D Euler with the component-wise limiter, single-grid
- *                 forward entry points only: the batched and adjoint entry
- *                 points return HWENO_ERR_UNSUPPORTED).
+ *                 (2D Euler, single-grid forward entry points only: the
+ *                 batched and adjoint entry points return
+ *                 HWENO_ERR_UNSUPPORTED).
  *  characteristic Euler only: 1 = nonlinear flux reconstruction in local
  *                 characteristic fields (Remarks 2.1/2.2; Roe average),
  *                 0 = component by component.  Ignored for scalars.
@@ -124,6 +124,16 @@ typedef struct {
  *                 read them at their own times t_n, t_n + dt, t_n + dt/2
  *                 (t_n = simulated time in the control block);
  *                 hweno_rhs and hweno_limit read them at t = 0.
+ *  obstacle       {i_s, j_s}: the cells i >= i_s, j < j_s are solid (the
+ *                 step of Example 3.12, against the bottom-right corner),
+ *                 {0, 0} = none.  Needs bc_x == HWENO_BC_EDGES, 2 <= i_s <= nx
+ *                 and 1 <= j_s <= ny - 2.  Its faces x = i_s dx and
+ *                 y = j_s dy are walls: along x a solid cell holds the mirror
+ *                 image of the fluid across the front face, along y the
+ *                 mirror image across the top face (each with the wall
+ *                 signs).  Solid cells keep their values, enter no wave speed
+ *                 and have a zero right-hand side; the limiter leaves their
+ *                 derivatives as they are.
  */
 typedef struct {
   int32_t dim, nx, ny;
@@ -136,6 +146,7 @@ typedef struct {
   double lin_w[3], lim_w[3];
   double eps, cfl;
   hweno_edge edges[4];
+  int32_t obstacle[2];
 } hweno_problem;
 
 /* Step control block: HWENO_CTRL_LEN doubles of device memory at the start of

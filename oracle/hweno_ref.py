@@ -36,6 +36,12 @@ Readings of passages the paper leaves open (each listed in the design notes):
   * Reflecting walls (Euler, Example 3.7) fill ghost cells with the mirror
     image of the interior, with the wall-normal momentum and the derivatives
     along the wall normal negated.
+  * The step of Example 3.12 is an obstacle of solid cells (i >= i_s, j < j_s)
+    whose faces are walls: for the fluxes and the limiter along x a solid cell
+    holds the mirror image of the fluid across the front face, along y the
+    mirror image across the top face.  Solid cells keep their state.  The
+    paper treats the step corner "as in" its reference, which is not at hand:
+    no corner correction is applied.
   * Edge-described sides (the boundaries of Example 3.11): a side is cut in
     two segments at split = s0 + s1 t + s2 d along it (d: distance of the
     ghost centre beyond the side).  A segment is an outflow copy, a wall, or
@@ -106,6 +112,8 @@ class Problem:
     limiter_characteristic: bool = False
     # sides x_lo, x_hi, y_lo, y_hi, read where bc_x / bc_y is EDGES
     edges: Optional[Tuple[Edge, Edge, Edge, Edge]] = None
+    # (i_s, j_s): the cells i >= i_s, j < j_s are solid (the step of Example 3.12)
+    obstacle: Optional[Tuple[int, int]] = None
     # test-only switches: force the nonlinear weights to the linear ones
     linear_recon: bool = False
     linear_limiter: bool = False
@@ -122,6 +130,9 @@ class Problem:
 
 
 def problem_from_workload(w, **kw) -> Problem:
+    obstacle = getattr(w, "obstacle", None)
+    if obstacle is not None and "obstacle" not in kw:
+        kw["obstacle"] = tuple(obstacle)
     edges = getattr(w, "edges", None)
     if edges is not None and "edges" not in kw:
         kw["edges"] = tuple(Edge(kind=tuple(e[0]), split=tuple(e[1]),
@@ -463,6 +474,36 @@ def _pad_edges(A, axis, prob, d, role, t, width=2):
     return out
 
 
+def _solid(prob, ny, nx):
+    """Mask [ny, nx] of the obstacle's solid cells (all False without one)."""
+    m = torch.zeros(ny, nx, dtype=torch.bool)
+    if prob.obstacle is not None:
+        i_s, j_s = prob.obstacle
+        m[:j_s, i_s:] = True
+    return m
+
+
+def _obstacle_image(A, prob, d, role):
+    """A = [components, ny, nx] with every solid cell replaced by the mirror image
+    of the fluid across the obstacle's face normal to direction d (the front face
+    x = i_s dx for d = 0, the top face y = j_s dy for d = 1), times the parity of
+    ``role`` ("U", "n": derivative along d, "t": across d) under that reflection.
+    Solid cells deeper than the fluid can mirror take a clamped copy; no stencil
+    of a fluid cell reaches them."""
+    if prob.obstacle is None:
+        return A
+    i_s, j_s = prob.obstacle
+    ny, nx = A.shape[1], A.shape[2]
+    jj, ii = torch.meshgrid(torch.arange(ny), torch.arange(nx), indexing="ij")
+    if d == 0:
+        src_j, src_i = jj, (2 * i_s - 1 - ii).clamp(0, nx - 1)
+    else:
+        src_j, src_i = (2 * j_s - 1 - jj).clamp(0, ny - 1), ii
+    pu, pn, pt = _parities(prob, d)
+    par = torch.as_tensor({"U": pu, "n": pn, "t": pt}[role], dtype=A.dtype).view(-1, 1, 1)
+    return torch.where(_solid(prob, ny, nx), A[:, src_j, src_i] * par, A)
+
+
 def _parities(prob, d):
     """Parities of (U, derivative along d, derivative across d) under reflection
     across a wall normal to direction d: the momentum component normal to the
@@ -486,8 +527,9 @@ def max_speeds(S, prob) -> Tuple[float, float]:
     """alpha_d = max over the grid of |f_d'(u)| (global LF speed, Section 2.1)."""
     phys = physics_of(prob)
     U = _split(S, prob)[0].movedim(0, -1)
-    ax = float(phys.speed(U, 0).max())
-    ay = float(phys.speed(U, 1).max()) if prob.dim == 2 else 0.0
+    fluid = ~_solid(prob, U.shape[0], U.shape[1])    # solid cells enter no speed
+    ax = float(phys.speed(U, 0)[fluid].max())
+    ay = float(phys.speed(U, 1)[fluid].max()) if prob.dim == 2 else 0.0
     return ax, ay
 
 
@@ -574,17 +616,22 @@ def rhs(S, prob: Problem, alpha: Optional[Tuple[float, float]] = None, t: float 
     if alpha is None:
         alpha = max_speeds(S, prob)
     U, V, W = _split(S, prob)
-    fh, hh, eh = _direction_fluxes(U, V, W, prob, 0, alpha[0], t)
+    img = _obstacle_image
+    fh, hh, eh = _direction_fluxes(img(U, prob, 0, "U"), img(V, prob, 0, "n"),
+                                   None if W is None else img(W, prob, 0, "t"), prob, 0, alpha[0], t)
     LU = _difference(fh, 2, prob.dx)
     LV = _difference(hh, 2, prob.dx)
     if prob.dim == 1:
         return torch.cat([LU, LV])
     LW = _difference(eh, 2, prob.dx)
-    gh, th, xh = _direction_fluxes(U, W, V, prob, 1, alpha[1], t)
+    gh, th, xh = _direction_fluxes(img(U, prob, 1, "U"), img(W, prob, 1, "n"),
+                                   img(V, prob, 1, "t"), prob, 1, alpha[1], t)
     LU = LU + _difference(gh, 1, prob.dy)
     LW = LW + _difference(th, 1, prob.dy)
     LV = LV + _difference(xh, 1, prob.dy)
-    return torch.cat([LU, LV, LW])
+    L = torch.cat([LU, LV, LW])
+    # solid cells: zero right-hand side
+    return torch.where(_solid(prob, S.shape[1], S.shape[2]), torch.zeros_like(L), L)
 
 
 def limited_derivatives(S, prob: Problem, t: float = 0.0):
@@ -599,12 +646,13 @@ def limited_derivatives(S, prob: Problem, t: float = 0.0):
     def along(D, axis, bc, h):
         n = U.shape[axis]
         dr = 0 if axis == 2 else 1
+        Ui, D = _obstacle_image(U, prob, dr, "U"), _obstacle_image(D, prob, dr, "n")
         pu, pn, _ = _parities(prob, dr) if bc == REFLECT else (None, None, None)
         if bc == EDGES:
-            Up = _pad_edges(U, axis, prob, dr, "U", t, 1)
+            Up = _pad_edges(Ui, axis, prob, dr, "U", t, 1)
             Dp = _pad_edges(D, axis, prob, dr, "n", t, 1)
         else:
-            Up = _pad(U, axis, bc, 1, parity=pu)
+            Up = _pad(Ui, axis, bc, 1, parity=pu)
             Dp = _pad(D, axis, bc, 1, parity=pn)
         um, u0, up = (Up.narrow(axis, k, n) for k in range(3))
         vm, vp = Dp.narrow(axis, 0, n), Dp.narrow(axis, 2, n)
@@ -625,7 +673,9 @@ def limited_derivatives(S, prob: Problem, t: float = 0.0):
     out = [along(V, 2, prob.bc_x, prob.dx)]
     if prob.dim == 2:
         out.append(along(W, 1, prob.bc_y, prob.dy))
-    return torch.cat(out)
+    D = torch.cat(out)
+    # solid cells keep their derivatives
+    return torch.where(_solid(prob, S.shape[1], S.shape[2]), S[prob.m:], D)
 
 
 def hat(S, prob: Problem, t: float = 0.0):
@@ -655,12 +705,16 @@ def rk3_step(S, prob: Problem, dt: Optional[float] = None, alphas=None, t: float
     if dt is None:
         dt = cfl_dt(a[0], prob)
     t1, t2 = t + dt, t + 0.5 * dt
+    solid = _solid(prob, S.shape[1], S.shape[2])
+
+    def keep(X):     # the obstacle's solid cells keep their state exactly
+        return torch.where(solid, S, X) if prob.obstacle is not None else X
     H0 = hat(S, prob, t)
-    S1 = H0 + dt * rhs(S, prob, a[0], t)
+    S1 = keep(H0 + dt * rhs(S, prob, a[0], t))
     a[1] = a[1] if a[1] is not None else max_speeds(S1, prob)
-    S2 = 0.75 * H0 + 0.25 * (hat(S1, prob, t1) + dt * rhs(S1, prob, a[1], t1))
+    S2 = keep(0.75 * H0 + 0.25 * (hat(S1, prob, t1) + dt * rhs(S1, prob, a[1], t1)))
     a[2] = a[2] if a[2] is not None else max_speeds(S2, prob)
-    S3 = H0 / 3.0 + 2.0 / 3.0 * (hat(S2, prob, t2) + dt * rhs(S2, prob, a[2], t2))
+    S3 = keep(H0 / 3.0 + 2.0 / 3.0 * (hat(S2, prob, t2) + dt * rhs(S2, prob, a[2], t2)))
     return S3, dt, a
 
 

@@ -104,7 +104,13 @@ struct EdgeArgs {
   double split[4][3];
   double state[4][2][4];
   double t0;      // time of the state read by the right-hand side and the limiter entry points
+  int oi, oj;     // solid cells i >= oi, j < oj (oj == 0: no obstacle)
 };
+
+// cell (i, j) of the grid is solid
+__device__ __forceinline__ bool solid_cell(const EdgeArgs& e, int i, int j) {
+  return j < e.oj && i >= e.oi && j >= 0;
+}
 
 // map_index2 with a per-side choice between mirror and copy on edge-described
 // directions; always inside the grid
@@ -268,6 +274,37 @@ __device__ __forceinline__ bool stage_dt(const StageArgs<double>* unused, double
   return dt > 0.0;
 }
 
+// the LDS rectangle of columns [c0, c1) and rows [r0, r1) holds solid cells
+__device__ __forceinline__ bool obstacle_near(const EdgeArgs& e, int c0, int c1, int r0, int r1) {
+  return e.oj > 0 && c1 > e.oi && r0 < e.oj && r1 > 0;
+}
+
+// Solid cells of the staged tile take the mirror image of the fluid across the
+// obstacle's front face (d = 0) or top face (d = 1), with the wall signs of
+// that direction, read from the stage input.  Cells deeper than two inside the
+// obstacle take a clamped, finite copy; no stencil that enters a result reads
+// them.  Each thread rewrites the entries it staged.
+template <typename T, int M, int NF, int HR, int W, int NT>
+__device__ __forceinline__ void obstacle_mirror(const StageArgs<T>& a, const EdgeArgs& e, T* sm,
+                                                int i0, int j0, int HY, int d) {
+  const int nx = a.nx, ny = a.ny;
+  for (int q = threadIdx.x; q < W * HR; q += NT) {
+    const int lr = q / W, lc = q - lr * W;
+    const int ii = i0 - 2 + lc, jj = j0 - HY + lr;
+    if (!solid_cell(e, ii, jj)) continue;
+    int si = d == 0 ? 2 * e.oi - 1 - ii : ii;
+    int sj = d == 0 ? jj : 2 * e.oj - 1 - jj;
+    si = si < 0 ? 0 : (si >= nx ? nx - 1 : si);
+    sj = sj < 0 ? 0 : (sj >= ny ? ny - 1 : sj);
+    const long long g = (long long)sj * nx + si;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+      const T x = gld(a.in + f * a.fs + g);
+      sm[f * HR * W + q] = mirror_sign(f, M, true, d) < 0 ? -x : x;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // One tile of one stage (K = 1, 2, 3) or of the right-hand side (K = 0).
 // NT threads; TX x TY cells (TX*TY <= NT); sm, fb: LDS staging buffers.
@@ -380,6 +417,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
         if (ey && jj >= ny) apply(3, 1, (ii + 0.5) * a.dx, (jj - ny + 0.5) * a.dy);
       }
     }
+    // Obstacle, x-interfaces: a solid cell holds the mirror image of the fluid
+    // across the front face x = oi dx (read from the stage input, wall signs)
+    if (obstacle_near(*e, i0 - 2, i0 - 2 + W, j0 - HY, j0 - HY + HR))
+      obstacle_mirror<T, M, NF, HR, W, NT>(a, *e, sm, i0, j0, HY, 0);
   }
   __syncthreads();
 
@@ -434,6 +475,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
     const T idy = T(1.0 / a.dy);
     const T hy = T(a.dy);
     __syncthreads();
+    if constexpr (EDG) {
+      // Obstacle, y-interfaces: the mirror image across the top face y = oj dy
+      if (obstacle_near(*e, i0 - 2, i0 - 2 + W, j0 - HY, j0 - HY + HR)) {
+        obstacle_mirror<T, M, NF, HR, W, NT>(a, *e, sm, i0, j0, HY, 1);
+        __syncthreads();
+      }
+    }
     // ---- y-interfaces: between local rows iy-1 and iy, iy = 0..TY ----
     for (int q = tid; q < TX * FR; q += NT) {
       const int iy = q / TX, cc = q - iy * TX;
@@ -483,6 +531,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
   const long long g = (long long)gj * nx + gi;
   const T* own = sm + (ty + HY) * W + tx + 2;
   if (!inside) return;
+  if constexpr (EDG) {
+    if (solid_cell(*e, gi, gj)) {
+      // solid: zero right-hand side, the state carried through unchanged
+#pragma unroll
+      for (int f = 0; f < NF; ++f) gst(a.out + f * fs + g, K == 0 ? T(0) : gld(a.in + f * fs + g));
+      return;
+    }
+  }
 
   if constexpr (K == 0) {
 #pragma unroll
@@ -496,12 +552,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
     T Sh[NF];
     constexpr bool charlim = CL && PHYS == PH_EULER;
     const bool complim = k.limiter_on && !charlim;
+    // the x-neighbour of a fluid cell next to the obstacle's front face is that
+    // cell's own mirror image (the stage buffer holds the y-image there)
+    bool front = false;
+    if constexpr (EDG) front = gi == e->oi - 1 && gj < e->oj;
 #pragma unroll
     for (int c = 0; c < M; ++c) {
       const T* u = own + (c * HR) * W;
       const T* v = own + ((M + c) * HR) * W;
       Sh[c] = u[0];
-      Sh[M + c] = complim ? limit1(u[-1], u[0], u[1], v[-1], v[1], hx, idx, k.lw) : v[0];
+      T up = u[1], vp = v[1];
+      if constexpr (EDG) {
+        if (front) {
+          up = mirror_sign(c, M, true, 0) < 0 ? -u[0] : u[0];
+          vp = mirror_sign(M + c, M, true, 0) < 0 ? -v[0] : v[0];
+        }
+      }
+      Sh[M + c] = complim ? limit1(u[-1], u[0], up, v[-1], vp, hx, idx, k.lw) : v[0];
       if constexpr (DIM == 2) {
         const T* w = own + ((2 * M + c) * HR) * W;
         Sh[2 * M + c] = complim ? limit1(u[-W], u[0], u[W], w[-W], w[W], T(a.dy),
@@ -519,6 +586,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
           const T* u = own + (c * HR) * W;
           const T* v = own + ((M + c) * HR) * W;
           um[c] = u[-1], u0[c] = u[0], up[c] = u[1], vm[c] = v[-1], vp[c] = v[1];
+          if constexpr (EDG) {
+            if (front) {
+              up[c] = mirror_sign(c, M, true, 0) < 0 ? -u[0] : u[0];
+              vp[c] = mirror_sign(M + c, M, true, 0) < 0 ? -v[0] : v[0];
+            }
+          }
         }
         limit_char<T, M>(um, u0, up, vm, vp, hx, idx, k.lw, k.gm1, r);
 #pragma unroll
@@ -620,7 +693,7 @@ __global__ __launch_bounds__(NT, (StageOcc<T, K>::WAVES)) void k_stage(StageArgs
   }
 }
 
-// 2D Euler with edge-described sides (component-wise limiter).  The body
+// 2D Euler with edge-described sides (CL: the characteristic limiter).  The body
 // repeats k_stage's: handing the kernel parameters to a shared device
 // function by reference costs k_stage its register allocation (spills).
 // Three waves per SIMD in FP32: at five the boundary fix-up spills.
@@ -629,7 +702,7 @@ struct EdgeOcc {
   static constexpr int WAVES = sizeof(T) == 4 ? 3 : 2;
 };
 
-template <typename T, int K, int TX, int TY, int NT>
+template <typename T, int K, int TX, int TY, int NT, bool CL>
 __global__ __launch_bounds__(NT, (EdgeOcc<T>::WAVES)) void k_stage_edges(StageArgs<T> a,
                                                                              Consts<T> k,
                                                                              EdgeArgs e) {
@@ -657,8 +730,8 @@ __global__ __launch_bounds__(NT, (EdgeOcc<T>::WAVES)) void k_stage_edges(StageAr
   const int tile_y = t / ntx, tile_x = t - tile_y * ntx;
   T sx = T(0), sy = T(0);
   uint32_t flags = 0;
-  stage_tile<T, PH_EULER, 2, K, TX, TY, NT, false, true>(a, k, tile_x, tile_y, dt, alx, aly, sm,
-                                                         fb, sx, sy, flags, &e);
+  stage_tile<T, PH_EULER, 2, K, TX, TY, NT, CL, true>(a, k, tile_x, tile_y, dt, alx, aly, sm, fb,
+                                                      sx, sy, flags, &e);
   if constexpr (K > 0) {
     // speeds of the new stage state feed the next stage's splitting; after
     // stage 3 they are the next step's stage-1 speeds (multi-step calls)
@@ -1339,6 +1412,29 @@ __global__ __launch_bounds__(256) void k_alpha(const T* __restrict__ S, long lon
   block_fold<256>(double(mx), double(my), flags, alpha, status, true);
 }
 
+// k_alpha over the fluid cells of a 2D Euler grid with an obstacle (solid
+// cells enter no speed)
+template <typename T>
+__global__ __launch_bounds__(256) void k_alpha_obstacle(const T* __restrict__ S, int nx, int ny,
+                                                        int oi, int oj, Consts<T> k,
+                                                        double* alpha, unsigned long long* status) {
+  const long long n = (long long)nx * ny;
+  T mx = T(0), my = T(0);
+  uint32_t flags = 0;
+  for (long long i = blockIdx.x * 256ll + threadIdx.x; i < n; i += 256ll * gridDim.x) {
+    const int j = (int)(i / nx), c = (int)(i - (long long)j * nx);
+    if (j < oj && c >= oi) continue;
+    T U[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) U[q] = S[q * n + i];
+    T sx, sy;
+    point_speeds<T, PH_EULER, 2>(U, k, sx, sy, flags);
+    mx = (dbits(double(sx)) > dbits(double(mx))) ? sx : mx;
+    my = (dbits(double(sy)) > dbits(double(my))) ? sy : my;
+  }
+  block_fold<256>(double(mx), double(my), flags, alpha, status, true);
+}
+
 // Start of a step: stage speeds and dt from the replay record, or speeds
 // cleared for the speed reduction; the next-step speed slots ctrl[10..11]
 // are cleared for this step's stage 3 (multi-step calls fold into them).
@@ -1404,6 +1500,11 @@ __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __res
   if (i >= n) return;
   const int gj = (int)(i / nx), gi = (int)(i - (long long)gj * nx);
   constexpr bool EU = PHYS == PH_EULER;
+  if (e.oj > 0 && solid_cell(e, gi, gj)) {
+    // solid cells keep their derivatives
+    for (int f = 0; f < M * DIM; ++f) out[f * n + i] = S[(M + f) * n + i];
+    return;
+  }
   // neighbour at index q (column or row) along direction d; one cell deep,
   // so mirror and copy read the same interior cell
   auto neighbour = [&](int q, int d) -> LimNb {
@@ -1413,6 +1514,12 @@ __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __res
     r.at = d == 0 ? (long long)gj * nx + mq : (long long)mq * nx + gi;
     r.mode = mirrored(q, nn, bc) ? 1 : 0;
     r.st = nullptr;
+    if (e.oj > 0 && (d == 0 ? solid_cell(e, q, gj) : solid_cell(e, gi, q))) {
+      // a solid neighbour is the cell's own mirror image across the obstacle's face
+      r.at = i;
+      r.mode = 1;
+      return r;
+    }
     if (bc == HWENO_BC_EDGES && (q < 0 || q >= nn)) {
       const int side = 2 * d + (q < 0 ? 0 : 1);
       const double pos = d == 0 ? (gj + 0.5) * dy : (gi + 0.5) * dx;
@@ -1575,10 +1682,18 @@ hweno_status validate(const hweno_problem* p) {
   };
   if (!bc_ok(p->bc_x) || (p->dim == 2 && !bc_ok(p->bc_y)))
     return fail(HWENO_ERR_INVALID_ARG, "unknown boundary condition");
+  if (p->obstacle[0] != 0 || p->obstacle[1] != 0) {
+    if (p->dim != 2 || p->bc_x != HWENO_BC_EDGES)
+      return fail(HWENO_ERR_UNSUPPORTED, "an obstacle needs a 2D grid with edge-described x sides");
+    if (p->obstacle[0] < 2 || p->obstacle[0] > p->nx || p->obstacle[1] < 1 ||
+        p->obstacle[1] > p->ny - 2)
+      return fail(HWENO_ERR_INVALID_ARG,
+                  "obstacle {%d, %d}: needs 2 <= i_s <= nx and 1 <= j_s <= ny - 2",
+                  p->obstacle[0], p->obstacle[1]);
+  }
   if (has_edges(p)) {
-    if (p->physics != HWENO_EULER || p->dim != 2 || p->limiter_characteristic)
-      return fail(HWENO_ERR_UNSUPPORTED,
-                  "edge-described sides are built for 2D Euler with the component-wise limiter");
+    if (p->physics != HWENO_EULER || p->dim != 2)
+      return fail(HWENO_ERR_UNSUPPORTED, "edge-described sides are built for 2D Euler");
     for (int d = 0; d < 2; ++d) {
       if ((d == 0 ? p->bc_x : p->bc_y) != HWENO_BC_EDGES) continue;
       const int across = d == 0 ? p->nx : p->ny;
@@ -1739,6 +1854,8 @@ EdgeArgs edge_args(const hweno_problem* p) {
     for (int q = 0; q < 3; ++q) e.split[side][q] = h.split[q];
   }
   e.t0 = 0.0;
+  e.oi = p->obstacle[0];
+  e.oj = p->obstacle[1];
   return e;
 }
 
@@ -1779,6 +1896,14 @@ struct RunAlpha {
                           unsigned long long* status, hipStream_t s) {
     const long long n = cells_of(p);
     k_zero<<<1, 64, 0, s>>>(alpha, 2);
+    if constexpr (PHYS == PH_EULER && DIM == 2) {
+      if (p->obstacle[1] > 0) {
+        k_alpha_obstacle<T><<<alpha_blocks(n), 256, 0, s>>>(
+            (const T*)state, p->nx, p->ny, p->obstacle[0], p->obstacle[1], make_consts<T>(p),
+            alpha, status);
+        return launch_check("alpha");
+      }
+    }
     k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>((const T*)state, n,
                                                           make_consts<T>(p), alpha, status);
     return launch_check("alpha");
@@ -1800,7 +1925,7 @@ struct RunRhs {
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
     if constexpr (PHYS == PH_EULER && DIM == 2) {
       if (has_edges(p)) {
-        k_stage_edges<T, 0, TX, TY, NT><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
+        k_stage_edges<T, 0, TX, TY, NT, false><<<stage_grid(DIM, a.nx, a.ny), NT, 0, s>>>(
             a, make_consts<T>(p), edge_args(p));
         return launch_check("rhs");
       }
@@ -1840,8 +1965,18 @@ struct RunStep {
     const Consts<T> k = make_consts<T>(p);
     if (!(take_next && !replay)) k_begin<<<1, 64, 0, s>>>(ctrl, replay);
     if (!replay && !take_next) {
-      k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>(
-          (const T*)state, n, k, ctrl, (unsigned long long*)(ctrl + 8));
+      bool done = false;
+      if constexpr (PHYS == PH_EULER && DIM == 2) {
+        if (p->obstacle[1] > 0) {
+          k_alpha_obstacle<T><<<alpha_blocks(n), 256, 0, s>>>(
+              (const T*)state, p->nx, p->ny, p->obstacle[0], p->obstacle[1], k, ctrl,
+              (unsigned long long*)(ctrl + 8));
+          done = true;
+        }
+      }
+      if (!done)
+        k_alpha<T, PHYS, DIM><<<alpha_blocks(n), 256, 0, s>>>(
+            (const T*)state, n, k, ctrl, (unsigned long long*)(ctrl + 8));
     }
     StageArgs<T> a = base_args<T, PHYS, DIM>(p);
     a.ctrl = ctrl;
@@ -1872,15 +2007,22 @@ struct RunStep {
       if constexpr (DIM == 2) {
         if (has_edges(p)) {
           const EdgeArgs e = edge_args(p);
-          a.in = (const T*)state;
-          a.out = s1;
-          timed(s, [&] { k_stage_edges<T, 1, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
-          a.in = s1;
-          a.out = s2;
-          timed(s, [&] { k_stage_edges<T, 2, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
-          a.in = s2;
-          a.out = (T*)state;
-          timed(s, [&] { k_stage_edges<T, 3, TX, TY, NT><<<grid, NT, 0, s>>>(a, k, e); });
+          auto edge_stages = [&](auto cl) {
+            constexpr bool CLE = decltype(cl)::value;
+            a.in = (const T*)state;
+            a.out = s1;
+            timed(s, [&] { k_stage_edges<T, 1, TX, TY, NT, CLE><<<grid, NT, 0, s>>>(a, k, e); });
+            a.in = s1;
+            a.out = s2;
+            timed(s, [&] { k_stage_edges<T, 2, TX, TY, NT, CLE><<<grid, NT, 0, s>>>(a, k, e); });
+            a.in = s2;
+            a.out = (T*)state;
+            timed(s, [&] { k_stage_edges<T, 3, TX, TY, NT, CLE><<<grid, NT, 0, s>>>(a, k, e); });
+          };
+          if (char_limiter(p))
+            edge_stages(std::true_type{});
+          else
+            edge_stages(std::false_type{});
           k_finish<<<1, 64, 0, s>>>(ctrl, tape, fold_next && !replay ? 1 : 0);
           return launch_check("rk3_step");
         }

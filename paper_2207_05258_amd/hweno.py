@@ -65,6 +65,7 @@ class _CProblem(ctypes.Structure):
         ("lin_w", ctypes.c_double * 3), ("lim_w", ctypes.c_double * 3),
         ("eps", ctypes.c_double), ("cfl", ctypes.c_double),
         ("edges", _CEdge * 4),
+        ("obstacle", ctypes.c_int32 * 2),
     ]
 
 
@@ -161,6 +162,8 @@ class Problem:
     cfl: float = 0.6
     # sides x_lo, x_hi, y_lo, y_hi, read where bc_x / bc_y is EDGES
     edges: Optional[Tuple[Edge, Edge, Edge, Edge]] = None
+    # (i_s, j_s): cells i >= i_s, j < j_s are solid (a step against the bottom-right corner)
+    obstacle: Optional[Tuple[int, int]] = None
 
     @property
     def m(self) -> int:
@@ -195,6 +198,8 @@ class Problem:
             p.edges[e].split[:] = [float(x) for x in edge.split]
             for sgm in range(2):
                 p.edges[e].state[sgm][:] = [float(x) for x in edge.state[sgm]]
+        if self.obstacle is not None:
+            p.obstacle[:] = [int(x) for x in self.obstacle]
         return p
 
 

@@ -61,6 +61,8 @@ static hweno_problem base(std::mt19937_64& g) {
       if (pick(g) == 0) st[3] = -1.0;
     }
   }
+  // the obstacle (solid cells i >= i_s, j < j_s): mostly absent, else anything
+  if (pick(g) < 3) p.obstacle[0] = small(g), p.obstacle[1] = small(g);
   return p;
 }
 

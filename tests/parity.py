@@ -31,6 +31,8 @@ TOL = {torch.float64: 1e-12, torch.float32: 1e-5}
 
 
 def gpu_problem(w: hi.Workload, dtype, **kw):
+    if w.obstacle is not None and "obstacle" not in kw:
+        kw["obstacle"] = tuple(w.obstacle)
     if w.edges is not None and "edges" not in kw:
         kw["edges"] = tuple(h.Edge(kind=tuple(e[0]), split=tuple(e[1]),
                                    state=(tuple(e[2][0]), tuple(e[2][1]))) for e in w.edges)

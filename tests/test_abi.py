@@ -208,10 +208,16 @@ def test_edge_described_sides_are_checked_on_host():
     c = good.c()
     assert c.bc_x == h.EDGES and c.edges[3].kind[0] == h.SEG_STATE
     assert c.edges[2].kind[1] == h.SEG_REFLECT and c.edges[3].split[2] == good.edges[3].split[2]
-    # scalar laws, 1D and the characteristic limiter are not built with edges
+    # scalar laws and 1D are not built with edges; both limiters are
     assert L.hweno_validate(ctypes.byref(_prob(physics="burgers", bc_x=h.EDGES,
                                                 edges=good.edges).c())) == 2
-    assert L.hweno_validate(ctypes.byref(_edges_problem(limiter_characteristic=True).c())) == 2
+    assert L.hweno_validate(ctypes.byref(_edges_problem(limiter_characteristic=True).c())) == 0
+    # an obstacle needs edge-described x sides and room for the mirror images
+    step = _edges_problem(obstacle=(10, 4))
+    assert L.hweno_validate(ctypes.byref(step.c())) == 0
+    for bad_obstacle in ((1, 4), (65, 4), (10, 0), (10, 15)):
+        assert L.hweno_validate(ctypes.byref(_edges_problem(obstacle=bad_obstacle).c())) == 1
+    assert L.hweno_validate(ctypes.byref(_prob(obstacle=(10, 4)).c())) == 2
 
     def with_edge(k, **field):
         e = good.edges[k]

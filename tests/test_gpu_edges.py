@@ -1,9 +1,9 @@
 """Edge-described sides (the boundaries of the double Mach reflection, Example 3.11)
-on the GPU path against the oracle: right-hand side, limiter, single steps and
-multi-step calls with a moving split, whole runs of the double Mach problem, and the
-problem at 1920 x 480 to T = 0.2 checked against what its exact data fix (uniform
-regions stay uniform, the incident shock meets the top side where the exact shock
-does)."""
+and the step of Example 3.12 on the GPU path against the oracle: right-hand side,
+limiter, single steps and multi-step calls with a moving split, whole runs of both
+problems on small grids, and both at the customary sizes checked against what their
+data fix (uniform regions stay uniform, the incident shock meets the top side where
+the exact shock does, solid cells keep their state)."""
 import math
 import sys
 import time
@@ -57,6 +57,8 @@ CASES = {
     "double_mach_64x16": lambda: hi.double_mach(64, 16),
     "double_mach_37x11": lambda: hi.double_mach(37, 11),
     "mixed_edges_45x31": lambda: _mixed(45, 31),
+    "forward_step_60x20": lambda: hi.forward_step(60, 20),
+    "forward_step_35x15": lambda: hi.forward_step(35, 15),
 }
 
 
@@ -82,7 +84,7 @@ def test_rhs_limit_and_step_match_the_oracle(case, dtype):
     P.assert_within(P.step_errors(Sg, ref, w), P.TOL[dtype], f"step {case}")
 
 
-@pytest.mark.parametrize("case", ["double_mach_64x16", "mixed_edges_45x31"])
+@pytest.mark.parametrize("case", ["double_mach_64x16", "mixed_edges_45x31", "forward_step_60x20"])
 def test_multi_step_call_with_moving_splits_matches_the_oracle(case):
     """Eight steps in one call: every stage reads the sides at its own time."""
     w = CASES[case]()
@@ -99,6 +101,33 @@ def test_multi_step_call_with_moving_splits_matches_the_oracle(case):
         t += dt
     assert st.t == pytest.approx(t, rel=1e-12)
     P.assert_within(P.step_errors(Sg, S, w), 1e-11, f"8 steps {case}")
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("case", ["double_mach_64x16", "forward_step_60x20", "forward_step_35x15"])
+def test_characteristic_limiter_with_edges_matches_the_oracle(case, dtype):
+    """The limiter variant on characteristic fields next to edge-described sides and
+    the obstacle's faces: limiter entry point, one step, and (FP64) eight steps."""
+    w = CASES[case]()
+    announce("edges, characteristic limiter", case, dtype)
+    prob = P.gpu_problem(w, dtype, limiter_characteristic=True)
+    op = P.oracle_problem(w, limiter_characteristic=True)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    D = h.limit(Sg, prob)
+    P.assert_within(P.limit_errors(D, o.limited_derivatives(S, op, 0.0), S, w), P.TOL[dtype],
+                    f"char limit {case}")
+    st = h.Stepper(prob)
+    st.step(Sg)
+    ref, t, _ = o.rk3_step(S, op, t=0.0)
+    P.assert_within(P.step_errors(Sg, ref, w), P.TOL[dtype], f"char step {case}")
+    if dtype == torch.float64:
+        st.steps(Sg, 7)
+        for _ in range(7):
+            ref, dt, _ = o.rk3_step(ref, op, t=t)
+            t += dt
+        assert st.t == pytest.approx(t, rel=1e-12)
+        P.assert_within(P.step_errors(Sg, ref, w), 1e-11, f"char 8 steps {case}")
 
 
 def test_edges_reducing_to_plain_boundaries_equal_them_on_the_gpu():
@@ -180,3 +209,71 @@ def test_double_mach_at_1920x480():
     x_exact = 1.0 / 6.0 + y[-1] / math.sqrt(3.0) + w.info["shock_speed"] * T / math.sin(math.pi / 3)
     assert abs(x[last_behind] - x_exact) <= 3.0 * w.dx, (x[last_behind], x_exact)
     assert float(Sg[0].min()) > 0.0
+
+
+@pytest.mark.parametrize("charlim", [False, True], ids=["componentwise", "characteristic"])
+def test_forward_step_whole_run_matches_the_oracle(charlim):
+    """60 x 20 cells to T = 1 (the bow shock forms and reflects off the top wall).
+    The flow around the step amplifies rounding: a 1e-15 relative perturbation of the
+    oracle's own input grows to 2e-14 at T = 0.25, 1e-12 at 0.5 and 1.6e-10 at 1, and
+    two implementations whose steps differ by rounding (~1e-14 per step) end ~5e-9
+    apart; the run is held to 1e-7 (single steps and 8-step calls to 1e-11 and below)."""
+    w = hi.forward_step(60, 20)
+    T = 1.0
+    announce("forward step whole run 60x20", "characteristic limiter" if charlim else "")
+    prob = P.gpu_problem(w, torch.float64, limiter_characteristic=charlim)
+    Sg = P.to_gpu(w, torch.float64)
+    st = _run(prob, Sg, T)
+    So, steps = o.run(o.as_tensor(w.S), P.oracle_problem(w, limiter_characteristic=charlim), T)
+    assert int(st.ctrl[9]) == steps
+    P.assert_within(P.step_errors(Sg, So, w), 1e-7, "forward step 60x20 at T = 1")
+
+
+def test_forward_step_at_960x320():
+    """Example 3.12 at the paper's 960 x 320 cells to T = 4 (FP64) with the limiter on
+    characteristic fields: no inadmissible state, solid cells unchanged, the free stream
+    ahead of the bow shock untouched.  (With the component-wise limiter the pressure
+    behind the bow shock turns negative near t = 1.1 at 240 x 80 to 960 x 320, see
+    test_forward_step_componentwise_limiter_loses_admissibility.)"""
+    nx, ny = 960, 320
+    w = hi.forward_step(nx, ny)
+    T = w.info["t_end"]
+    announce("forward step 960x320 to T = 4")
+    prob = P.gpu_problem(w, torch.float64, limiter_characteristic=True)
+    Sg = P.to_gpu(w, torch.float64)
+    S0 = Sg.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = _run(prob, Sg, T)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    steps = int(st.ctrl[9])
+    print(f"[forward step 960x320] {steps} steps in {el:.2f} s", flush=True)
+    i_s, j_s = w.obstacle
+    assert torch.equal(Sg[:, :j_s, i_s:], S0[:, :j_s, i_s:])
+    x = (np.arange(nx) + 0.5) * w.dx
+    U = Sg[:4].cpu().numpy()
+    free = hi.conserved_2d(*[np.full((1, 1), q) for q in w.info["free"]])
+    for c in range(4):
+        assert np.abs(U[c][:, x < 0.1] - free[c][0, 0]).max() <= 1e-8 * (abs(free[c][0, 0]) + 1.0)
+    fluid = torch.ones(ny, nx, dtype=torch.bool, device=Sg.device)
+    fluid[:j_s, i_s:] = False
+    assert float(Sg[0][fluid].min()) > 0.0
+
+
+def test_forward_step_componentwise_limiter_loses_admissibility():
+    """The recorded robustness difference between the two limiter readings: at 240 x 80
+    the component-wise limiter lets the pressure behind the bow shock turn negative
+    before t = 1.5 (the status word flags it and the run stops there), the limiter on
+    characteristic fields keeps every state admissible through the same time."""
+    w = hi.forward_step(240, 80)
+    announce("forward step 240x80, both limiters to t = 1.5")
+    flags = {}
+    for charlim in (False, True):
+        st = h.Stepper(P.gpu_problem(w, torch.float64, limiter_characteristic=charlim))
+        Sg = P.to_gpu(w, torch.float64)
+        while st.t < 1.5 * (1 - 1e-13) and not (st.status & ~h.hweno.ST_SKIPPED):
+            st.steps(Sg, 100, t_end=1.5)
+        flags[charlim] = (st.status & ~h.hweno.ST_SKIPPED, st.t)
+    assert flags[True][0] == 0 and flags[True][1] == pytest.approx(1.5, rel=1e-13)
+    assert flags[False][0] & h.hweno.ST_PRESSURE, flags

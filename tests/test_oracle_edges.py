@@ -154,3 +154,84 @@ def test_double_mach_initial_state_is_consistent_with_its_edges():
     assert top.split[0] == pytest.approx(x_top, rel=1e-15)
     assert top.split[2] == pytest.approx(1.0 / math.sqrt(3.0), rel=1e-15)
     assert top.split[1] == pytest.approx(10.0 / math.sin(math.pi / 3.0), rel=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# The obstacle of Example 3.12 (solid cells i >= i_s, j < j_s, faces are walls)
+# ---------------------------------------------------------------------------
+
+def _x_edges(qa):
+    """x sides without a split: an inflow on the left, an outflow on the right."""
+    return (_edge((o.SEG_STATE, o.SEG_STATE), (0.0, 0.0, 0.0), (qa, qa)),
+            _edge((o.SEG_OUTFLOW, o.SEG_OUTFLOW)))
+
+
+def test_obstacle_across_the_whole_height_is_a_wall_on_the_right():
+    S, w = _smooth(22, 14)
+    i_s = 15
+    qa = _cons(1.1, 0.4, -0.1, 2.0)
+    lo, hi_ = _x_edges(qa)
+    base = dict(dim=2, physics="euler", dx=w.dx, dy=w.dy, bc_y=o.OUTFLOW)
+    pa = o.Problem(bc_x=o.EDGES, edges=(lo, hi_, hi_, hi_), obstacle=(i_s, w.ny), **base)
+    wall = _edge((o.SEG_REFLECT, o.SEG_REFLECT))
+    pb = o.Problem(bc_x=o.EDGES, edges=(lo, wall, hi_, hi_), **base)
+    Sb = S[:, :, :i_s].contiguous()
+    a = o.max_speeds(S, pa)
+    assert a == o.max_speeds(Sb, pb)      # solid cells enter no speed
+    La, Lb = o.rhs(S, pa, a), o.rhs(Sb, pb, a)
+    assert torch.equal(La[:, :, :i_s], Lb)
+    assert float(La[:, :, i_s:].abs().max()) == 0.0
+    Da, Db = o.limited_derivatives(S, pa), o.limited_derivatives(Sb, pb)
+    assert torch.equal(Da[:, :, :i_s], Db)
+    assert torch.equal(Da[:, :, i_s:], S[4:, :, i_s:])    # solid cells keep their derivatives
+    Sa1, _, _ = o.rk3_step(S, pa)
+    Sb1, _, _ = o.rk3_step(Sb, pb)
+    assert torch.equal(Sa1[:, :, :i_s], Sb1)
+    assert torch.equal(Sa1[:, :, i_s:], S[:, :, i_s:])
+
+
+def test_obstacle_across_the_whole_width_is_a_wall_below():
+    S, w = _smooth(16, 20)
+    j_s = 6
+    qa = _cons(1.1, 0.4, -0.1, 2.0)
+    lo, hi_ = _x_edges(qa)
+    out = _edge((o.SEG_OUTFLOW, o.SEG_OUTFLOW))
+    base = dict(dim=2, physics="euler", dx=w.dx, dy=w.dy, bc_x=o.EDGES)
+    pa = o.Problem(bc_y=o.OUTFLOW, edges=(lo, hi_, out, out), obstacle=(0, j_s), **base)
+    wall = _edge((o.SEG_REFLECT, o.SEG_REFLECT))
+    pb = o.Problem(bc_y=o.EDGES, edges=(lo, hi_, wall, out), **base)
+    Sb = S[:, j_s:, :].contiguous()
+    a = o.max_speeds(S, pa)
+    assert a == o.max_speeds(Sb, pb)
+    assert torch.equal(o.rhs(S, pa, a)[:, j_s:, :], o.rhs(Sb, pb, a))
+    assert torch.equal(o.limited_derivatives(S, pa)[:, j_s:, :], o.limited_derivatives(Sb, pb))
+    Sa1, _, _ = o.rk3_step(S, pa)
+    Sb1, _, _ = o.rk3_step(Sb, pb)
+    assert torch.equal(Sa1[:, j_s:, :], Sb1)
+
+
+def test_gas_at_rest_around_a_step_is_stationary():
+    nx, ny = 20, 14
+    q = _cons(1.2, 0.0, 0.0, 1.5)
+    U = torch.tensor(q, dtype=torch.float64).view(4, 1, 1).expand(4, ny, nx)
+    S = torch.cat([U, torch.zeros(8, ny, nx, dtype=torch.float64)])
+    wall = _edge((o.SEG_REFLECT, o.SEG_REFLECT))
+    prob = o.Problem(dim=2, physics="euler", dx=0.1, dy=0.07, bc_x=o.EDGES, bc_y=o.REFLECT,
+                     edges=(wall, wall, wall, wall), obstacle=(8, 4))
+    assert float(o.rhs(S, prob).abs().max()) <= 1e-13
+    S1, _, _ = o.rk3_step(S, prob)
+    assert float((S1 - S).abs().max()) <= 1e-14
+
+
+def test_forward_step_initial_operator_vanishes_away_from_the_front_face():
+    """The free stream is uniform and parallel to every wall but the step's front face:
+    the operator vanishes except on the fluid cells within three cells of that face."""
+    w = hi.forward_step(60, 20)
+    prob = o.problem_from_workload(w)
+    S = o.as_tensor(w.S)
+    i_s, j_s = w.obstacle
+    L = o.rhs(S, prob)
+    near = torch.zeros(w.ny, w.nx, dtype=torch.bool)
+    near[:j_s, i_s - 3:i_s] = True
+    assert float(L[:, ~near].abs().max()) <= 1e-12
+    assert float(L[:, near].abs().max()) > 1.0
