@@ -43,16 +43,16 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("a4dd751361acff49", "f64", 4096): 5.0832e+09,
-    ("a4dd751361acff49", "f32", 4096): 2.6226e+09,
+    ("e1705405e2965275", "f64", 4096): 5.0827e+09,
+    ("e1705405e2965275", "f32", 4096): 2.6222e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("a4dd751361acff49", "f64", 4096): 9.769e8,
-    ("a4dd751361acff49", "f32", 4096): 8.624e8,
+    ("e1705405e2965275", "f64", 4096): 9.769e8,
+    ("e1705405e2965275", "f32", 4096): 8.624e8,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
 # lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
@@ -227,21 +227,20 @@ def run_small(n: int = 4000, steps: int = 200):
             "status": st.status}
 
 
-def run_double_mach(nx: int = 1920, ny: int = 480):
-    """Double Mach reflection (Example 3.11) on [0, 4] x [0, 1] to T = 0.2 in FP64:
-    edge-described sides (post-shock inflow, wall from x = 1/6, exact shock motion on
-    the top), device-side time steps in multi-step calls, the last one clipped to T.
-    A warm-up of a few steps on a copy first; the time covers the whole run."""
+def _time_to_solution(w, **kw):
+    """Whole run of a 2D Euler workload with edge-described sides to its T in FP64:
+    device-side time steps in multi-step calls of 256, the last one clipped to T.  A
+    warm-up of a few steps on a copy first; the time covers the whole run."""
     import torch
 
-    import hweno_inputs as hi
     import paper_2207_05258_amd as h
-    w = hi.double_mach(nx, ny)
+    nx, ny = w.nx, w.ny
     T = w.info["t_end"]
     edges = tuple(h.Edge(kind=tuple(e[0]), split=tuple(e[1]), state=(tuple(e[2][0]), tuple(e[2][1])))
                   for e in w.edges)
     prob = h.Problem(dim=2, nx=nx, ny=ny, physics="euler", dtype=torch.float64, dx=w.dx, dy=w.dy,
-                     bc_x=w.bc_x, bc_y=w.bc_y, edges=edges)
+                     bc_x=w.bc_x, bc_y=w.bc_y, edges=edges,
+                     obstacle=None if w.obstacle is None else tuple(w.obstacle), **kw)
     S = torch.as_tensor(w.S).cuda().contiguous()
     h.Stepper(prob).steps(S.clone(), 4)
     torch.cuda.synchronize()
@@ -253,10 +252,26 @@ def run_double_mach(nx: int = 1920, ny: int = 480):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     steps = int(st.ctrl[9])
-    return {"workload": f"double Mach reflection (Example 3.11), {nx}x{ny}, T = {T}, FP64",
-            "steps": steps, "seconds": wall, "value": 3.0 * steps * nx * ny / wall,
-            "unit": "cell-stage updates/s", "t": st.t,
-            "status": st.status & ~h.hweno.ST_SKIPPED}
+    return {"steps": steps, "seconds": wall, "value": 3.0 * steps * nx * ny / wall,
+            "unit": "cell-stage updates/s", "t": st.t, "status": st.status & ~h.hweno.ST_SKIPPED}
+
+
+def run_double_mach(nx: int = 1920, ny: int = 480):
+    """Double Mach reflection (Example 3.11) on [0, 4] x [0, 1] to T = 0.2: post-shock
+    inflow, a wall from x = 1/6 on the bottom, the exact shock motion on the top."""
+    import hweno_inputs as hi
+    r = _time_to_solution(hi.double_mach(nx, ny))
+    return {"workload": f"double Mach reflection (Example 3.11), {nx}x{ny}, T = 0.2, FP64", **r}
+
+
+def run_forward_step(nx: int = 960, ny: int = 320):
+    """Forward-facing step (Example 3.12) at the paper's 960 x 320 cells to T = 4, with the
+    limiter on characteristic fields (with the component-wise limiter the pressure turns
+    negative near t = 1.1)."""
+    import hweno_inputs as hi
+    r = _time_to_solution(hi.forward_step(nx, ny), limiter_characteristic=True)
+    return {"workload": f"forward-facing step (Example 3.12), {nx}x{ny}, T = 4, FP64, "
+                        "characteristic limiter", **r}
 
 
 def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 0, dtype_name: str = "f32"):
@@ -318,8 +333,9 @@ def main():
     ap.add_argument("--no-small", action="store_true",
                     help="skip the small-grid eager-versus-graph run")
     ap.add_argument("--no-double-mach", action="store_true",
-                    help="skip the double Mach reflection run")
-    ap.add_argument("--only", choices=["batched", "adjoint", "double_mach"], default=None,
+                    help="skip the double Mach reflection and forward-step runs")
+    ap.add_argument("--only", choices=["batched", "adjoint", "double_mach", "forward_step"],
+                    default=None,
                     help="run only this part and print its JSON object (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -358,6 +374,9 @@ def main():
     if args.only == "double_mach":
         print(json.dumps(run_double_mach()), flush=True)
         return
+    if args.only == "forward_step":
+        print(json.dumps(run_forward_step()), flush=True)
+        return
 
     main_run = run_gpu(args.n, args.dtype, args.steps, args.warmup)
     print(f"# {args.dtype} {args.n}^2: {main_run['rate']:.4e} cell-stage/s, stage kernel "
@@ -390,8 +409,10 @@ def main():
               file=sys.stderr, flush=True)
 
     dmr = None if args.no_double_mach else run_double_mach()
+    fstep = None if args.no_double_mach else run_forward_step()
     if dmr is not None:
-        print(f"# double Mach 1920x480 to T = 0.2: {dmr['steps']} steps in {dmr['seconds']:.2f} s",
+        print(f"# double Mach 1920x480 to T = 0.2: {dmr['steps']} steps in {dmr['seconds']:.2f} s; "
+              f"forward step 960x320 to T = 4: {fstep['steps']} steps in {fstep['seconds']:.2f} s",
               file=sys.stderr, flush=True)
 
     small = None if args.no_small else run_small()
@@ -450,6 +471,7 @@ def main():
         "adjoint": adjoint,
         "small_grid": small,
         "double_mach": dmr,
+        "forward_step": fstep,
         "status_word": main_run["status"],
         "kernel_sha": sha,
     }
