@@ -43,16 +43,16 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("e1705405e2965275", "f64", 4096): 5.0827e+09,
-    ("e1705405e2965275", "f32", 4096): 2.6222e+09,
+    ("2b7563538fa8c656", "f64", 4096): 5.0827e+09,
+    ("2b7563538fa8c656", "f32", 4096): 2.6223e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("e1705405e2965275", "f64", 4096): 9.769e8,
-    ("e1705405e2965275", "f32", 4096): 8.624e8,
+    ("2b7563538fa8c656", "f64", 4096): 9.511e8,
+    ("2b7563538fa8c656", "f32", 4096): 8.624e8,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
 # lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
