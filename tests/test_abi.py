@@ -252,3 +252,41 @@ def test_edges_are_refused_by_the_adjoint_and_batched_entry_points_on_host():
     assert L.hweno_batch_prepare(ctypes.byref(plain), inst, 1, ctypes.byref(total)) == 0
     inst[0].bc_y = h.EDGES
     assert L.hweno_batch_prepare(ctypes.byref(plain), inst, 1, ctypes.byref(total)) == 2
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """sizeof and field offsets of hweno_problem, hweno_edge and hweno_instance as a C
+    compiler lays them out from include/hweno.h, against the binding's ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {
+        "hweno_problem": ["dim", "nx", "ny", "physics", "dtype", "bc_x", "bc_y", "characteristic",
+                          "limiter_on", "limiter_characteristic", "dx", "dy", "gamma_gas",
+                          "adv_speed", "lin_w", "lim_w", "eps", "cfl", "edges", "obstacle"],
+        "hweno_edge": ["kind", "split", "state"],
+        "hweno_instance": ["state", "ws", "nx", "ny", "bc_x", "bc_y", "dx", "dy", "dt_fixed",
+                           "t_end", "ws_bytes", "off_s1", "off_s2", "off_base", "tile_begin",
+                           "n_tiles"],
+    }
+    src = ['#include <stdio.h>', '#include <stddef.h>', '#include "hweno.h"', 'int main(void) {']
+    for st, fs in fields.items():
+        src.append(f'printf("{st} size %zu\\n", sizeof({st}));')
+        for f in fs:
+            src.append(f'printf("{st} {f} %zu\\n", offsetof({st}, {f}));')
+    src += ['return 0;', '}']
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    mirrors = {"hweno_problem": h.hweno._CProblem, "hweno_edge": h.hweno._CEdge,
+               "hweno_instance": h.hweno._CInstance}
+    for st, cls in mirrors.items():
+        assert got[(st, "size")] == ctypes.sizeof(cls), st
+        for f in fields[st]:
+            assert got[(st, f)] == getattr(cls, f).offset, (st, f)
