@@ -72,6 +72,10 @@ def test_rhs_limit_and_step_match_the_oracle(case, dtype):
     Sg = P.to_gpu(w, dtype)
     S = P.exact_input(Sg)
     a = o.max_speeds(S, op)
+    # device speeds (solid cells of an obstacle enter none)
+    a_dev = h.alpha(Sg, prob).cpu()
+    rel = 1e-13 if dtype == torch.float64 else 1e-6
+    assert abs(float(a_dev[0]) - a[0]) <= rel * a[0] and abs(float(a_dev[1]) - a[1]) <= rel * a[1]
     L = h.rhs(Sg, prob, torch.tensor(a, dtype=torch.float64))
     P.assert_within(P.rhs_errors(L, o.rhs(S, op, a, 0.0), S, w), P.TOL[dtype], f"rhs {case}")
     D = h.limit(Sg, prob)
