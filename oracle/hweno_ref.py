@@ -52,7 +52,7 @@ Readings of passages the paper leaves open (each listed in the design notes):
 
 Parity unpinned (documented choices with nothing in the paper to check them
 against): the component-wise limiter for systems, the outflow copy of the
-derivative fields, and the zero derivatives and stage times of inflow
+derivative fields, and the zero derivatives in the ghost cells of inflow
 segments (pinned only where an edge reduces to a plain boundary or a state
 that is already uniform).  The characteristic limiter variant is pinned only through
 its special cases (linear weights, data along one eigenvector).

@@ -235,3 +235,31 @@ def test_forward_step_initial_operator_vanishes_away_from_the_front_face():
     near[:j_s, i_s - 3:i_s] = True
     assert float(L[:, ~near].abs().max()) <= 1e-12
     assert float(L[:, near].abs().max()) > 1.0
+
+
+def test_stages_read_the_sides_at_the_ssp_rk3_abscissae(monkeypatch):
+    """The time each stage hands to the operator and the limiter is t + c_k dt with c
+    the row sums of the Butcher matrix of SSP-RK3 in Shu-Osher form (a_21 = 1,
+    a_31 = a_32 = 1/4): c = (0, 1, 1/2)."""
+    A = [[0.0, 0.0, 0.0], [1.0, 0.0, 0.0], [0.25, 0.25, 0.0]]
+    c = [sum(row) for row in A]
+    w = hi.double_mach(24, 8)
+    prob = o.problem_from_workload(w)
+    S = o.as_tensor(w.S)
+    seen = {"rhs": [], "lim": []}
+    rhs0, lim0 = o.rhs, o.limited_derivatives
+
+    def rhs(S_, p, a=None, t=0.0):
+        seen["rhs"].append(t)
+        return rhs0(S_, p, a, t)
+
+    def lim(S_, p, t=0.0):
+        seen["lim"].append(t)
+        return lim0(S_, p, t)
+    monkeypatch.setattr(o, "rhs", rhs)
+    monkeypatch.setattr(o, "limited_derivatives", lim)
+    t0, dt = 0.013, 1.7e-3
+    o.rk3_step(S, prob, dt, t=t0)
+    want = [t0 + ck * dt for ck in c]
+    assert seen["rhs"] == pytest.approx(want, rel=0, abs=1e-18)
+    assert seen["lim"] == pytest.approx(want, rel=0, abs=1e-18)
