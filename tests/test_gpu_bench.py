@@ -40,6 +40,11 @@ def test_bench_reduced_run_prints_one_valid_json_line():
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
     assert d["adjoint"]["grad_finite"] and d["small_grid"]["status"] == 0
+    # time-to-solution runs of Examples 3.11 and 3.12: reached T with a clean status word
+    for leg, T in (("double_mach", 0.2), ("forward_step", 4.0)):
+        r_ = d[leg]
+        assert r_["status"] == 0 and r_["steps"] > 0 and r_["value"] > 0, (leg, r_)
+        assert abs(r_["t"] - T) <= 1e-12 * T, (leg, r_["t"])
 
 
 def test_bench_refuses_several_gpus():
