@@ -358,3 +358,26 @@ def test_full_size_windows_match_the_oracle(case):
         sj_, si_ = j - j0, i - i0
         errs = P.step_errors(got[:, sj_:sj_ + k, si_:si_ + k], ref[:, sj_:sj_ + k, si_:si_ + k], w)
         P.assert_within(errs, P.TOL[torch.float64], f"{case} window {(j, i)}")
+
+
+def test_graph_replays_with_moving_splits_equal_eager_steps():
+    """The moving split reads the simulated time from the device's control block, so
+    steps captured in a graph and replayed advance the sides exactly as eager steps do:
+    two replays of five captured steps equal ten eager steps, bit for bit."""
+    w = hi.double_mach(64, 16)
+    announce("edges in a graph")
+    prob = P.gpu_problem(w, torch.float64)
+    A = P.to_gpu(w, torch.float64)
+    B = A.clone()
+    sa = h.Stepper(prob)
+    for _ in range(10):
+        sa.step(A)
+    sb = h.Stepper(prob)
+    sb.capture(B, steps=5)
+    sb.replay()
+    torch.cuda.synchronize()
+    assert int(sb.ctrl[9]) == 5
+    sb.replay()
+    torch.cuda.synchronize()
+    assert int(sb.ctrl[9]) == 10 and sb.t == sa.t
+    assert torch.equal(A, B)
