@@ -54,9 +54,11 @@ MEASURED_VALU_WAVE_INSTR = {
     ("2b7563538fa8c656", "f64", 4096): 9.511e8,
     ("2b7563538fa8c656", "f32", 4096): 8.624e8,
 }
-# VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 16
-# lanes per cycle x 2.4 GHz, for FP64 and for unpacked FP32 alike.
-PEAK_VALU_LANE_INSTR = 256 * 4 * 16 * 2.4e9
+# VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
+# x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
+# TFLOP/s is twice the FP64 one; the FP32 stage kernel, which has no packed
+# instructions, issues above the 16-lane rate).
+PEAK_VALU_LANE_INSTR = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9}
 
 
 def kernel_sha() -> str:
@@ -426,8 +428,9 @@ def main():
     valu = None
     if wave_instr is not None:
         rate = wave_instr * 64 / (main_run["stage_ms_avg"] * 1e-3)
-        valu = {"lane_instr_per_s": float(f"{rate:.4g}"), "peak": PEAK_VALU_LANE_INSTR,
-                "frac": round(rate / PEAK_VALU_LANE_INSTR, 4),
+        peak_issue = PEAK_VALU_LANE_INSTR[args.dtype]
+        valu = {"lane_instr_per_s": float(f"{rate:.4g}"), "peak": peak_issue,
+                "frac": round(rate / peak_issue, 4),
                 "source": "SQ_INSTS_VALU per launch (rocprofv3) over the live launch time"}
     roofline = {
         "bound": "alu",
