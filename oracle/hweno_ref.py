@@ -51,11 +51,14 @@ Readings of passages the paper leaves open (each listed in the design notes):
     t + dt/2.
 
 Parity unpinned (documented choices with nothing in the paper to check them
-against): the component-wise limiter for systems, the outflow copy of the
-derivative fields, and the zero derivatives in the ghost cells of inflow
-segments (pinned only where an edge reduces to a plain boundary or a state
-that is already uniform).  The characteristic limiter variant is pinned only through
-its special cases (linear weights, data along one eigenvector).
+against): the component-wise limiter for systems, and the zero derivatives in
+the ghost cells of inflow segments (pinned only where an edge reduces to a
+plain boundary or a state that is already uniform).  The characteristic
+limiter variant is pinned only through its special cases (linear weights, data
+along one eigenvector).  The outflow copy is pinned by the domain it stands
+for: repeating the edge cells outward leaves the operator and the limiter of
+the original cells unchanged, and a step of data that are constant next to an
+outflow side equals the step of the domain extended by that constant.
 """
 from __future__ import annotations
 
