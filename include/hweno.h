@@ -8,7 +8,8 @@
  * ---------------------------------------
  * Memory.  Every array argument is DEVICE memory owned by the caller
  * (e.g. torch tensors); the library allocates no device memory and keeps no
- * device state.  Pointers are borrowed until the enqueued work has completed.
+ * device state, apart from the fixed static array of hweno_rk3_step_static.
+ * Pointers are borrowed until the enqueued work has completed.
  *
  * State layout.  One contiguous buffer of nf fields, each ny * nx values of the
  * problem's dtype, x fastest ("SoA [nf][ny][nx]", ny == 1 when dim == 1):
@@ -235,6 +236,32 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws,
 hweno_status hweno_rk3_steps(const hweno_problem* prob, void* state, void* ws, size_t ws_bytes,
                              int32_t n_steps, double dt_fixed, double t_end, double* tapes,
                              void* stream);
+
+/* Allocation-free variant of hweno_rk3_step, for callers that cannot
+ * allocate device memory (code under hipGraph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The step is exactly that of
+ * hweno_rk3_step (same kernels, bitwise the same results, control block and
+ * tape); only the stage states S1, S2 and the limited base derivatives live
+ * in a static device array of the library, HWENO_STATIC_SCRATCH_BYTES per GPU,
+ * held by every GPU the library runs on until the process ends.  Nothing is
+ * allocated or freed by the call, and nothing must start at zero in that
+ * array: every step writes each stage state before reading it.
+ * ctrl: device double[HWENO_CTRL_LEN], the step control block (as the first
+ *   HWENO_CTRL_LEN doubles of a hweno_rk3_step workspace: zero it before the
+ *   first step of a run; t and the status word accumulate there).
+ * dt_fixed, t_end, tape, replay, stream: as for hweno_rk3_step.  The stream's
+ *   device must be the current device.
+ * Size limit: 2 * align256(cells * nf * elem) + align256(cells * m * dim * elem)
+ *   bytes must not exceed HWENO_STATIC_SCRATCH_BYTES (64 MiB: 2D Euler up to
+ *   262144 cells in FP64, e.g. 512 x 512, and 524288 in FP32); a larger grid
+ *   returns HWENO_ERR_WORKSPACE before any HIP call.
+ * Concurrency: all calls on one GPU share its array, so calls that overlap in
+ *   time on one GPU (other streams, other host threads) race and corrupt
+ *   each other's stages; serialise them on one stream. */
+#define HWENO_STATIC_SCRATCH_BYTES (64u * 1024u * 1024u)
+hweno_status hweno_rk3_step_static(const hweno_problem* prob, void* state, double* ctrl,
+                                   double dt_fixed, double t_end, double* tape,
+                                   const double* replay, void* stream);
 
 /* Bytes of device workspace the adjoint entry points need for `prob`
  * (a ghost-padded adjoint buffer and three stage adjoints).  0 if invalid. */

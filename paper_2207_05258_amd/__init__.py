@@ -7,5 +7,5 @@ from .hweno import (BatchedStepper, Rollout, adjoint_workspace, autotune_batched
                     rollout_bytes_kept,
                     rollout_replay, step_adjoint, CTRL_LEN, EDGES, OUTFLOW, PERIODIC, REFLECT,  # noqa: F401
                     SEG_OUTFLOW, SEG_REFLECT, SEG_STATE, Edge, HwenoError, Problem, Stepper,
-                    alpha, lib, limit, problem_for, rhs, rk3_step_, timing_begin, timing_end, validate,
+                    alpha, lib, limit, problem_for, rhs, rk3_step_, rk3_step_static, timing_begin, timing_end, validate,
                     workspace_bytes)

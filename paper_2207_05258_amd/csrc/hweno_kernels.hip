@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <utility>
@@ -1586,6 +1587,12 @@ __global__ __launch_bounds__(256) void k_limit(const T* __restrict__ S, T* __res
 // ===========================================================================
 using namespace hweno;
 
+// Stage states and limited base derivatives of the allocation-free step
+// (hweno_rk3_step_static).  Each GPU that runs the library holds its own copy
+// for the life of the process.  On the host this name is only a handle for
+// hipGetSymbolAddress: kernels receive the device address it returns.
+static __device__ __align__(256) unsigned char scratch[HWENO_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_last_error;
@@ -1949,18 +1956,38 @@ struct RunLimit {
   }
 };
 
+// where one step keeps its control block, its two stage states and the
+// limited base derivatives
+struct StepBufs {
+  double* ctrl;
+  void* s1;
+  void* s2;
+  void* base;
+};
+
+StepBufs ws_bufs(const hweno_problem* p, void* ws) {
+  const WsLayout L = ws_layout(p);
+  char* w = (char*)ws;
+  return StepBufs{(double*)(w + L.ctrl), w + L.s1, w + L.s2, w + L.base};
+}
+
 struct RunStep {
   template <typename T, int PHYS, int DIM>
   // take_next: stage-1 speeds come from the previous step's stage 3 (the state
   // has not changed since); fold_next: this step's stage 3 provides them
   // (multi-step calls: the previous step's k_finish already began this one when
-  // take_next, and this one's k_finish begins the next when fold_next)
-  static hweno_status run(const hweno_problem* p, void* state, void* ws, double dt_fixed,
+  // take_next, and this one's k_finish begins the next when fold_next).
+  // may_time: stage launches may be bracketed by the diagnostic timer's events
+  static hweno_status run(const hweno_problem* p, void* state, StepBufs b, double dt_fixed,
                           double t_end, double* tape, const double* replay, bool take_next,
-                          bool fold_next, hipStream_t s) {
-    const WsLayout L = ws_layout(p);
-    char* w = (char*)ws;
-    double* ctrl = (double*)(w + L.ctrl);
+                          bool fold_next, bool may_time, hipStream_t s) {
+    double* ctrl = b.ctrl;
+    auto timed = [&](hipStream_t st, auto&& launch) {
+      if (may_time)
+        ::timed(st, launch);
+      else
+        launch();
+    };
     const long long n = cells_of(p);
     const Consts<T> k = make_consts<T>(p);
     if (!(take_next && !replay)) k_begin<<<1, 64, 0, s>>>(ctrl, replay);
@@ -1982,13 +2009,13 @@ struct RunStep {
     a.ctrl = ctrl;
     a.status = (unsigned long long*)(ctrl + 8);
     a.st0 = (const T*)state;
-    a.base = (T*)(w + L.base);
+    a.base = (T*)b.base;
     a.dt_fixed = dt_fixed;
     a.t_end = t_end;
     a.replay = replay ? 1 : 0;
     a.fold_next = (fold_next && !replay) ? 1 : 0;
-    T* s1 = (T*)(w + L.s1);
-    T* s2 = (T*)(w + L.s2);
+    T* s1 = (T*)b.s1;
+    T* s2 = (T*)b.s2;
     constexpr int TX = Tile<DIM>::TX, TY = Tile<DIM>::TY, NT = Tile<DIM>::NT;
     const dim3 grid = stage_grid(DIM, a.nx, a.ny);
     auto stages = [&](auto cl) {
@@ -2259,6 +2286,38 @@ hweno_status batch_common_ok(const hweno_problem* common) {
   return validate(&q);
 }
 
+// device address of `scratch` on every device, looked up once per device
+// with that device current (each device holds its own copy of the array)
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hweno_status static_scratch(hipStream_t s, void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(HWENO_ERR_LAUNCH, "hipGetDevice: %s", hipGetErrorString(e));
+  if (s) {
+    hipDevice_t sdev = -1;
+    e = hipStreamGetDevice(s, &sdev);
+    if (e != hipSuccess) return fail(HWENO_ERR_LAUNCH, "hipStreamGetDevice: %s", hipGetErrorString(e));
+    if ((int)sdev != dev)
+      return fail(HWENO_ERR_INVALID_ARG, "the stream belongs to device %d but device %d is current",
+                  (int)sdev, dev);
+  }
+  if (dev < 0 || dev >= kMaxDevices) return fail(HWENO_ERR_UNSUPPORTED, "device index %d", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(HWENO_ERR_LAUNCH, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return HWENO_OK;
+}
+
 }  // namespace
 
 // ===========================================================================
@@ -2320,8 +2379,8 @@ hweno_status hweno_rk3_step(const hweno_problem* prob, void* state, void* ws, si
   if (((uintptr_t)ws & 255u) != 0) return fail(HWENO_ERR_WORKSPACE, "workspace must be 256-byte aligned");
   if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
     return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
-  st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end, tape, replay, false, false,
-                         (hipStream_t)stream);
+  st = dispatch<RunStep>(prob, state, ws_bufs(prob, ws), dt_fixed, t_end, tape, replay, false,
+                         false, true, (hipStream_t)stream);
   if (st) return st;
   return ok();
 }
@@ -2341,11 +2400,41 @@ hweno_status hweno_rk3_steps(const hweno_problem* prob, void* state, void* ws, s
   if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
     return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
   for (int32_t q = 0; q < n_steps; ++q) {
-    st = dispatch<RunStep>(prob, state, ws, dt_fixed, t_end,
+    st = dispatch<RunStep>(prob, state, ws_bufs(prob, ws), dt_fixed, t_end,
                            tapes ? tapes + (size_t)q * HWENO_CTRL_LEN : (double*)nullptr,
-                           (const double*)nullptr, q > 0, q + 1 < n_steps, (hipStream_t)stream);
+                           (const double*)nullptr, q > 0, q + 1 < n_steps, true,
+                           (hipStream_t)stream);
     if (st) return st;
   }
+  return ok();
+}
+
+hweno_status hweno_rk3_step_static(const hweno_problem* prob, void* state, double* ctrl,
+                                   double dt_fixed, double t_end, double* tape,
+                                   const double* replay, void* stream) {
+  hweno_status st = validate(prob);
+  if (st) return st;
+  if (empty(prob)) return ok();
+  if (!state || !ctrl) return fail(HWENO_ERR_INVALID_ARG, "state and ctrl must be non-NULL");
+  if (((uintptr_t)ctrl & 7u) != 0) return fail(HWENO_ERR_INVALID_ARG, "ctrl must be 8-byte aligned");
+  if (!std::isfinite(dt_fixed) || !std::isfinite(t_end))
+    return fail(HWENO_ERR_INVALID_ARG, "dt_fixed and t_end must be finite");
+  // the stage states and base derivatives, laid out as in a workspace but
+  // without its control block
+  const WsLayout L = ws_layout(prob);
+  const size_t need = L.total - L.s1;
+  if (need > (size_t)HWENO_STATIC_SCRATCH_BYTES)
+    return fail(HWENO_ERR_WORKSPACE,
+                "grid too large for the static scratch: needs %zu bytes, the maximum is %zu",
+                need, (size_t)HWENO_STATIC_SCRATCH_BYTES);
+  void* base = nullptr;
+  st = static_scratch((hipStream_t)stream, &base);
+  if (st) return st;
+  char* w = (char*)base;
+  const StepBufs b{ctrl, w, w + (L.s2 - L.s1), w + (L.base - L.s1)};
+  st = dispatch<RunStep>(prob, state, b, dt_fixed, t_end, tape, replay, false, false, false,
+                         (hipStream_t)stream);
+  if (st) return st;
   return ok();
 }
 

@@ -106,6 +106,8 @@ def lib() -> ctypes.CDLL:
                                 vp, vp, vp], ctypes.c_int),
             "hweno_rk3_steps": ([P, vp, vp, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_double, vp, vp], ctypes.c_int),
+            "hweno_rk3_step_static": ([P, vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp],
+                                      ctypes.c_int),
             "hweno_adjoint_workspace_bytes": ([P], ctypes.c_size_t),
             "hweno_rhs_adjoint": ([P, vp, vp, vp, vp, vp, vp, ctypes.c_size_t, vp], ctypes.c_int),
             "hweno_rk3_step_adjoint": ([P, vp, vp, ctypes.c_size_t, vp, vp, vp, ctypes.c_size_t,
@@ -386,6 +388,26 @@ def timing_end() -> Tuple[int, float]:
     ms = ctypes.c_double(0.0)
     _check(lib().hweno_timing_end(ctypes.byref(n), ctypes.byref(ms)), "hweno_timing_end")
     return int(n.value), float(ms.value)
+
+
+STATIC_SCRATCH_BYTES = 64 * 1024 * 1024
+
+
+def rk3_step_static(S: torch.Tensor, prob: Problem, ctrl: torch.Tensor, dt: Optional[float] = None,
+                    t_end: Optional[float] = None, tape: Optional[torch.Tensor] = None,
+                    replay: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """One SSP-RK3 step of S in place through hweno_rk3_step_static: the stage states live
+    in the library's static device array, so the call allocates nothing (for code under
+    graph capture).  ``ctrl``: the caller's float64[16] control block on the device.
+    Calls on one GPU share that array: do not overlap them."""
+    _require(S, prob, prob.nf, "state")
+    for t, name in ((ctrl, "ctrl"), (tape, "tape"), (replay, "replay")):
+        if t is not None and (t.dtype != torch.float64 or t.numel() < CTRL_LEN or not t.is_cuda):
+            raise ValueError(f"{name} must be a float64 GPU tensor of >= {CTRL_LEN} values")
+    _check(lib().hweno_rk3_step_static(ctypes.byref(prob.c()), _ptr(S), _ptr(ctrl),
+                                       float(dt or 0.0), float(t_end or 0.0), _ptr(tape),
+                                       _ptr(replay), _stream()), "hweno_rk3_step_static")
+    return S
 
 
 def rk3_step_(S: torch.Tensor, prob: Problem, dt: Optional[float] = None) -> torch.Tensor:
