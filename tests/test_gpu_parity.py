@@ -487,8 +487,17 @@ def test_full_size_quadrants_sampled(n, dtype):
     alphas = [(float(ctrl[0]), float(ctrl[1])), (float(ctrl[2]), float(ctrl[3])),
               (float(ctrl[4]), float(ctrl[5]))]
     dt = float(ctrl[6])
-    ax, ay = o.max_speeds(P.exact_input(S0[:4]), o.Problem(dim=2, physics="euler"))
-    assert abs(alphas[0][0] - ax) <= 1e-6 * ax and abs(alphas[0][1] - ay) <= 1e-6 * ay
+    # every stage's speeds are the maxima over the whole grid of the state that
+    # stage read (S^n, then the stage states S1, S2 the kernels left in the
+    # workspace); FP32 kernels evaluate |u| + c in FP32
+    tol_a = 1e-14 if dtype == torch.float64 else 1e-6
+    oprob = o.Problem(dim=2, physics="euler")
+    inputs = [S0] + [_stage_state(st, prob, q) for q in (1, 2)]
+    for q, Sq in enumerate(inputs):
+        ax, ay = o.max_speeds(P.exact_input(Sq[:4]), oprob)
+        assert abs(alphas[q][0] - ax) <= tol_a * ax and abs(alphas[q][1] - ay) <= tol_a * ay, \
+            (q, alphas[q], (ax, ay))
+    assert abs(dt - o.cfl_dt(alphas[0], P.oracle_problem(w))) <= 1e-14 * dt
     half, m, k = n // 2, 8, 24
     rng = np.random.default_rng(0)
     spots = [(half - k // 2, half - k // 2), (0, 0), (n - k, n - k), (0, half - k // 2),
@@ -507,6 +516,48 @@ def test_full_size_quadrants_sampled(n, dtype):
     S1 = S0.clone()
     h.Stepper(prob).step(S1)
     assert torch.equal(S1, Sg)
+
+
+def _stage_state(st, prob, q):
+    """Stage state S_q (q = 1, 2) that the last step left in a stepper's workspace
+    (layout of hweno_workspace_bytes: control block, S1, S2, base derivatives,
+    each 256-byte aligned)."""
+    es = 8 if prob.dtype == torch.float64 else 4
+    nbytes = prob.nf * prob.ny * prob.nx * es
+    off = 256 + (q - 1) * ((nbytes + 255) // 256 * 256)
+    return st.ws[off:off + nbytes].view(prob.dtype).view(prob.nf, prob.ny, prob.nx)
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_whole_1024_grid_two_steps_with_the_oracles_own_speeds(dtype):
+    """Two whole SSP-RK3 steps of the 1024^2 four-quadrant workload in one multi-step
+    call, as the benchmark launches them (the second step's stage-1 speeds folded by
+    the first step's third stage), against two oracle steps that compute every
+    stage's speeds and each dt themselves from the same input: every cell, both
+    steps' tapes (speeds of the three stages, dt)."""
+    n = 1024
+    w = hi.euler2d_quadrants(n, n, 0)
+    announce("whole grid", n, dtype)
+    Sg = P.to_gpu(w, dtype)
+    S = P.exact_input(Sg)
+    prob = P.gpu_problem(w, dtype)
+    st = h.Stepper(prob)
+    tapes = torch.zeros(2, h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    st.steps(Sg, 2, tapes=tapes)
+    tapes = tapes.cpu()
+    assert int(st.ctrl[8:9].view(torch.int64).item()) == 0
+    oprob = P.oracle_problem(w)
+    tol_a = 1e-14 if dtype == torch.float64 else 1e-6
+    for k in range(2):
+        S, dt, alphas = o.rk3_step(S, oprob)
+        for q in range(3):
+            for d in range(2):
+                got = float(tapes[k, 2 * q + d])
+                assert abs(got - alphas[q][d]) <= tol_a * alphas[q][d], (k, q, d, got, alphas[q][d])
+        assert abs(float(tapes[k, 6]) - dt) <= tol_a * dt, (k, float(tapes[k, 6]), dt)
+    errs = P.step_errors(Sg, S, w)
+    print("whole 1024^2, two steps:", {kk: f"{v:.2e}" for kk, v in errs.items()}, flush=True)
+    P.assert_within(errs, P.TOL[dtype], f"whole {n}^2 grid, two steps")
 
 
 def test_state_beyond_32_bit_element_indices():
