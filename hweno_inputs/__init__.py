@@ -378,6 +378,30 @@ def euler2d_rough(nx: int, ny: int, seed: int, bc=OUTFLOW) -> Workload:
                     name=f"euler2d_rough_{nx}x{ny}_s{seed}")
 
 
+def roughened(w: Workload, seed: int, amp: float = 0.2, slope: float = 0.05) -> Workload:
+    """A copy of a 2D Euler workload with seeded cell-by-cell noise (stress input
+    with structure in every stencil and next to every side): rho and p multiplied
+    by U[1 - amp, 1 + amp], each velocity component shifted by amp * U[-1, 1] times
+    the local sound speed, and random derivative fields of size slope * n as in
+    euler2d_rough.  Geometry, boundaries, edges and obstacle are kept."""
+    g = rng(seed)
+    ny, nx = w.ny, w.nx
+    rho, mx, my, E = (w.S[c] for c in range(4))
+    u, v = mx / rho, my / rho
+    p = (w.gamma_gas - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(w.gamma_gas * p / rho)
+    rho = rho * g.uniform(1.0 - amp, 1.0 + amp, size=(ny, nx))
+    p = p * g.uniform(1.0 - amp, 1.0 + amp, size=(ny, nx))
+    u = u + amp * c * g.uniform(-1.0, 1.0, size=(ny, nx))
+    v = v + amp * c * g.uniform(-1.0, 1.0, size=(ny, nx))
+    U = conserved_2d(rho, u, v, p, w.gamma_gas)
+    D1 = g.uniform(-1.0, 1.0, size=U.shape) * nx * slope
+    D2 = g.uniform(-1.0, 1.0, size=U.shape) * ny * slope
+    return Workload(np.concatenate([U, D1, D2]), 2, "euler", w.dx, w.dy, w.bc_x, w.bc_y,
+                    w.lo, w.hi, w.gamma_gas, w.adv_speed, name=f"{w.name}_rough_s{seed}",
+                    info=dict(w.info), edges=w.edges, obstacle=w.obstacle)
+
+
 # ---------------------------------------------------------------------------
 # batched uneven 2D Euler instances
 # ---------------------------------------------------------------------------

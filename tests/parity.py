@@ -2,21 +2,25 @@
 and the error norms.
 
 Norm of one step (per conserved component c):
-  err_U[c] = max |U_gpu - U_ref| / max |U_ref|
-  err_D[c] = max |dx (Ux_gpu - Ux_ref)| / max |U_ref|   (dy for U_y)
+  err_U[c] = max |U_gpu - U_ref| / max |U_ref,c|
+  err_D[c] = max |dx (Ux_gpu - Ux_ref)| / max |U_ref,c|   (dy for U_y)
 i.e. derivative fields are compared in cell-size-scaled units, which is the
 scale in which they enter the reconstruction (H = dx h).  Raw derivative
 increments carry an intrinsic rounding of order eps_machine * N, so they are
-gated in these units.  The right-hand side is compared as a step increment:
-dx * L_U and dx^2 * L_D against the larger of max |U_c| and max |dx * L_U,c|
-of the reference.  The increment is a flux difference, whose rounding scales
-with the flux; for a component that is zero everywhere (the momentum of a
-fluid at rest, as in the blast-wave problem) the flux is carried by the
-pressure alone and only the increment itself sets the scale.
-The two momenta of 2D Euler are one vector and share one scale, the larger of
-their two maxima: the characteristic projection mixes them, so a component
-that nearly vanishes (flow along a wall) carries rounding at the scale of
-the other.
+gated in these units.  The right-hand side is compared as a step increment,
+dx * L_U and dx^2 * L_D against max |U_c|.
+
+One relaxation exists, used only by the case where the oracle measured
+against itself (a one-ulp perturbation of its input) already reaches the 1e-12
+gate under the strict norm, so that no correct implementation could meet it
+(tests/test_oracle_noise_floor.py measures it):
+  flux_scale     the operator increment is scaled by the larger of max |U_c|
+                 and max |dx L_U,c| of the reference: the increment is a flux
+                 difference whose rounding scales with the flux, and for a
+                 component that vanishes everywhere (the momentum of the
+                 blast-wave state at rest, Example 3.7) the pressure alone
+                 carries it (oracle floor under the strict norm 1.4e-12,
+                 under this one 1.6e-14).
 """
 from __future__ import annotations
 
@@ -59,11 +63,8 @@ def exact_input(Sg: torch.Tensor) -> torch.Tensor:
 
 
 def _scales(U, w: hi.Workload):
-    """Per-component scales max |U_c|, the two momenta of 2D Euler sharing theirs."""
-    sc = [float(U[c].abs().max()) for c in range(w.m)]
-    if w.physics == "euler" and w.dim == 2:
-        sc[1] = sc[2] = max(sc[1], sc[2])
-    return sc
+    """Per-component scales max |U_c|."""
+    return [float(U[c].abs().max()) for c in range(w.m)]
 
 
 def step_errors(out, ref, w: hi.Workload):
@@ -81,7 +82,7 @@ def step_errors(out, ref, w: hi.Workload):
     return errs
 
 
-def rhs_errors(L, Lref, U, w: hi.Workload):
+def rhs_errors(L, Lref, U, w: hi.Workload, flux_scale=False):
     L = L.detach().cpu().to(torch.float64)
     Lref = Lref.detach().cpu().to(torch.float64)
     U = U.detach().cpu().to(torch.float64)
@@ -89,7 +90,10 @@ def rhs_errors(L, Lref, U, w: hi.Workload):
     errs = {}
     sc = _scales(U, w)
     for c in range(m):
-        scale = max(sc[c], w.dx * float(Lref[c].abs().max())) or 1.0
+        scale = sc[c]
+        if flux_scale:
+            scale = max(scale, w.dx * float(Lref[c].abs().max()))
+        scale = scale or 1.0
         errs[f"LU{c}"] = w.dx * float((L[c] - Lref[c]).abs().max()) / scale
         errs[f"LUx{c}"] = w.dx * w.dx * float((L[m + c] - Lref[m + c]).abs().max()) / scale
         if w.dim == 2:

@@ -283,81 +283,36 @@ def test_forward_step_componentwise_limiter_loses_admissibility():
     assert flags[False][0] & h.hweno.ST_PRESSURE, flags
 
 
-def _window_problem(w, j0, j1, i0, i1, **kw):
-    """Oracle problem of the window [j0, j1) x [i0, i1) of workload w: a window side on
-    the domain's side keeps that side's description (splits shifted to the window's
-    origin), an interior window side is an outflow copy (its cells within 8 of it
-    are not compared); the obstacle moves to window coordinates."""
-    out = o.Edge((o.SEG_OUTFLOW, o.SEG_OUTFLOW))
-    dom = P.oracle_problem(w, **kw)
-
-    def shifted(e, by):
-        return o.Edge(kind=e.kind, split=(e.split[0] - by, e.split[1], e.split[2]), state=e.state)
-
-    def plain(bc):   # a plain boundary as an edge description
-        k = o.SEG_REFLECT if bc == o.REFLECT else o.SEG_OUTFLOW
-        return o.Edge((k, k))
-    ex = dom.edges if dom.bc_x == o.EDGES else (plain(dom.bc_x),) * 2
-    ey = dom.edges[2:] if dom.bc_y == o.EDGES else (plain(dom.bc_y),) * 2
-    sides = (shifted(ex[0], j0 * w.dy) if i0 == 0 else out,
-             shifted(ex[1], j0 * w.dy) if i1 == w.nx else out,
-             shifted(ey[0], i0 * w.dx) if j0 == 0 else out,
-             shifted(ey[1], i0 * w.dx) if j1 == w.ny else out)
-    obstacle = None
-    if w.obstacle is not None:
-        si, sj = w.obstacle[0] - i0, w.obstacle[1] - j0
-        if sj > 0 and si < i1 - i0:
-            obstacle = (max(si, 0), sj)
-    import dataclasses
-    return dataclasses.replace(dom, bc_x=o.EDGES, bc_y=o.EDGES, edges=sides, obstacle=obstacle)
-
-
 @pytest.mark.parametrize("case", ["double_mach_1920x480", "forward_step_960x320"])
-def test_full_size_windows_match_the_oracle(case):
-    """At the sizes the benchmark runs (FP64, its limiter choice), after some steps: one
-    more step on the device against the oracle on windows around the moving top split,
-    the start of the bottom wall, the inflow and outflow sides, the step's corner and
-    front face, and random interior spots (device speeds and dt)."""
+def test_full_size_whole_grid_matches_the_oracle(case):
+    """At the sizes the benchmark runs (FP64, its limiter choice): one device step of
+    a roughened copy of the problem's data (seeded noise in every cell and random
+    derivatives; the edges, walls and obstacle kept), at a time that puts the moving
+    split away from its initial place, against one oracle step that computes its own
+    speeds of every stage and its own dt: every cell, and the tape."""
     if case.startswith("double"):
-        w, kw, before = hi.double_mach(1920, 480), {}, 30
+        w0, kw, t0 = hi.double_mach(1920, 480), {}, 0.1
     else:
-        w, kw, before = hi.forward_step(960, 320), dict(limiter_characteristic=True), 200
-    announce("full-size windows", case)
+        w0, kw, t0 = hi.forward_step(960, 320), dict(limiter_characteristic=True), 1.0
+    w = hi.roughened(w0, 7)
+    announce("full-size whole grid", case)
     prob = P.gpu_problem(w, torch.float64, **kw)
     Sg = P.to_gpu(w, torch.float64)
-    st = h.Stepper(prob)
-    st.steps(Sg, before)
-    t = st.t
-    S0 = Sg.clone()
-    st.step(Sg)
+    S0 = P.exact_input(Sg)
+    st = h.Stepper(prob, t0=t0)
+    tape = torch.zeros(h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    st.step(Sg, tape=tape)
     assert st.status == 0
-    ctrl = st.ctrl.cpu()
-    alphas = [(float(ctrl[0]), float(ctrl[1])), (float(ctrl[2]), float(ctrl[3])),
-              (float(ctrl[4]), float(ctrl[5]))]
-    dt = float(ctrl[6])
-    nx, ny, k, m = w.nx, w.ny, 24, 8
-    if case.startswith("double"):
-        xs = 1.0 / 6.0 + (1.0 + 20.0 * t) / math.sqrt(3.0)     # shock on the top side
-        i_top = min(max(int(xs / w.dx) - k // 2, 0), nx - k)
-        spots = [(ny - k, i_top), (0, max(int((1.0 / 6.0) / w.dx) - k // 2, 0)), (ny // 2, 0),
-                 (ny // 2, nx - k), (0, 0), (ny - k, nx - k)]
-    else:
-        si, sj = w.obstacle
-        spots = [(sj - k // 2, si - k // 2), (0, si - k), (sj, nx - k), (ny - k, si),
-                 (ny // 2, 0), (0, 0)]
-    rng = np.random.default_rng(1)
-    spots += [tuple(int(v) for v in (rng.integers(m, ny - k - m), rng.integers(m, nx - k - m)))
-              for _ in range(2)]
-    for (j, i) in spots:
-        j0, j1 = max(j - m, 0), min(j + k + m, ny)
-        i0, i1 = max(i - m, 0), min(i + k + m, nx)
-        Sw = P.exact_input(P.window(S0, j0, j1, i0, i1))
-        pw = _window_problem(w, j0, j1, i0, i1, **kw)
-        ref, _, _ = o.rk3_step(Sw, pw, dt, alphas, t)
-        got = P.window(Sg, j0, j1, i0, i1).cpu()
-        sj_, si_ = j - j0, i - i0
-        errs = P.step_errors(got[:, sj_:sj_ + k, si_:si_ + k], ref[:, sj_:sj_ + k, si_:si_ + k], w)
-        P.assert_within(errs, P.TOL[torch.float64], f"{case} window {(j, i)}")
+    ref, dt, alphas = o.rk3_step(S0, P.oracle_problem(w, **kw), None, None, t0)
+    tape = tape.cpu()
+    for q in range(3):
+        for d in range(2):
+            assert abs(float(tape[2 * q + d]) - alphas[q][d]) <= 1e-14 * alphas[q][d], (q, d)
+    assert abs(float(tape[6]) - dt) <= 1e-14 * dt
+    assert float(tape[7]) == pytest.approx(t0 + dt, rel=1e-15)
+    errs = P.step_errors(Sg, ref, w)
+    print(case, {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
+    P.assert_within(errs, P.TOL[torch.float64], f"{case} whole grid")
 
 
 def test_graph_replays_with_moving_splits_equal_eager_steps():
