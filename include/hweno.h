@@ -349,6 +349,33 @@ hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_ins
                                     int32_t total_tiles, int32_t variant, int32_t blocks,
                                     void* stream);
 
+/* Autotuner of the batched stepper: the tile variant and the persistent grid
+ * size of hweno_rk3_step_batched for one batch, chosen by measurement.  For
+ * every tile variant (0 = 16 x 15 cells, 1 = 32 x 7 cells) and every grid
+ * candidate -- the stage kernel's resident capacity (blocks = 0), 2 and 4
+ * workgroups per compute unit, and one workgroup per tile -- it runs one
+ * warm-up step and then `trials` steps between two hipEvents on `stream`,
+ * and returns the fastest pair in *variant, *blocks (pass them to
+ * hweno_rk3_step_batched; *blocks is the workgroup count the fastest
+ * candidate launched, the resident capacity resolved, never 0).  The steps are real steps of the instances that
+ * inst_dev describes, so give it descriptors of scratch copies (states and
+ * workspaces) of the batch to tune; their control blocks follow the usual
+ * rules.  tile_maps_dev: host array of HWENO_BATCH_VARIANTS device tile maps;
+ * total_tiles: host int32[HWENO_BATCH_VARIANTS], the prepared tile counts.
+ * times_ms (may be NULL): host double[HWENO_BATCH_VARIANTS *
+ * HWENO_AUTOTUNE_CANDIDATES], the mean step time of each (variant, candidate),
+ * variant-major; grid_sizes (may be NULL): host int32[same], the workgroups
+ * each candidate launched.  Unlike the other entry points this one
+ * synchronises on its events (and creates and destroys two of them); it
+ * allocates no device memory, and the stage timer does not see its launches.
+ * trials in [1, 1000]. */
+#define HWENO_AUTOTUNE_CANDIDATES 4
+hweno_status hweno_autotune(const hweno_problem* common, const hweno_instance* inst_dev,
+                            const int32_t* const* tile_maps_dev, int32_t n_inst,
+                            const int32_t* total_tiles, int32_t trials, void* stream,
+                            int32_t* variant, int32_t* blocks, double* times_ms,
+                            int32_t* grid_sizes);
+
 /* Diagnostics: kernel timing of the Runge-Kutta stage kernels.
  * hweno_timing_begin(1) makes subsequent hweno_rk3_step calls (on this
  * thread) record a hipEvent pair around every stage-kernel launch on the

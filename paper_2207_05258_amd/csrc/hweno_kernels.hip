@@ -2235,12 +2235,12 @@ int tiles_of(int nx, int ny) {
          ((ny + BatchTile<V>::TY - 1) / BatchTile<V>::TY);
 }
 
+// workgroups of one batched stage launch: `blocks`, or (0) exactly the
+// workgroups that can be resident at once, never more than the tiles
 template <typename T, int V>
-hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, const int* map, int n,
-                         int total, int blocks, hipStream_t s) {
-  const Consts<T> k = make_consts<T>(p);
+int batched_grid(int blocks, int total) {
   int grid = blocks;
-  if (grid <= 0) {  // default: exactly the workgroups that can be resident at once
+  if (grid <= 0) {
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_stage_batched<T, V, 1, false, false>, 256, 0) !=
             hipSuccess ||
@@ -2248,7 +2248,14 @@ hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, con
       per_cu = 1;
     grid = per_cu * device_cus();
   }
-  grid = std::min(grid, total);
+  return std::min(grid, total);
+}
+
+template <typename T, int V>
+hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, const int* map, int n,
+                         int total, int blocks, hipStream_t s) {
+  const Consts<T> k = make_consts<T>(p);
+  const int grid = batched_grid<T, V>(blocks, total);
   const unsigned small = (unsigned)((n + 255) / 256);
   k_begin_batched<<<small, 256, 0, s>>>(inst, n);
   k_alpha_batched<T, V><<<std::min(total, 4 * device_cus()), 256, 0, s>>>(inst, map, total, k);
@@ -2273,6 +2280,40 @@ hweno_status run_batched(const hweno_problem* p, const hweno_instance* inst, con
   k_finish_batched<<<small, 256, 0, s>>>(inst, n);
   return launch_check("rk3_step_batched");
 }
+
+hweno_status run_batched_any(const hweno_problem* p, const hweno_instance* inst, const int* map,
+                             int n, int total, int variant, int blocks, hipStream_t s) {
+  if (p->dtype == HWENO_F64)
+    return variant == 0 ? run_batched<double, 0>(p, inst, map, n, total, blocks, s)
+                        : run_batched<double, 1>(p, inst, map, n, total, blocks, s);
+  return variant == 0 ? run_batched<float, 0>(p, inst, map, n, total, blocks, s)
+                      : run_batched<float, 1>(p, inst, map, n, total, blocks, s);
+}
+
+int batched_grid_any(const hweno_problem* p, int variant, int blocks, int total) {
+  if (p->dtype == HWENO_F64)
+    return variant == 0 ? batched_grid<double, 0>(blocks, total) : batched_grid<double, 1>(blocks, total);
+  return variant == 0 ? batched_grid<float, 0>(blocks, total) : batched_grid<float, 1>(blocks, total);
+}
+
+// the autotuner's grid-size candidates for one tile variant: the resident
+// capacity (0), two and four workgroups per compute unit, one per tile
+void autotune_candidates(int total, int out[HWENO_AUTOTUNE_CANDIDATES]) {
+  const int cus = device_cus();
+  out[0] = 0;
+  out[1] = 2 * cus;
+  out[2] = 4 * cus;
+  out[3] = total;
+}
+
+// timing of the autotuner's steps: two events, destroyed on every path
+struct EventPair {
+  hipEvent_t a = nullptr, b = nullptr;
+  ~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+  }
+};
 
 hweno_status batch_common_ok(const hweno_problem* common) {
   if (!common) return fail(HWENO_ERR_INVALID_ARG, "problem pointer is NULL");
@@ -2563,17 +2604,77 @@ hweno_status hweno_rk3_step_batched(const hweno_problem* common, const hweno_ins
   if (variant < 0 || variant >= HWENO_BATCH_VARIANTS)
     return fail(HWENO_ERR_INVALID_ARG, "variant must be in [0, %d)", HWENO_BATCH_VARIANTS);
   if (blocks < 0) return fail(HWENO_ERR_INVALID_ARG, "blocks must be >= 0");
-  hipStream_t s = (hipStream_t)stream;
-  if (common->dtype == HWENO_F64) {
-    st = variant == 0
-             ? run_batched<double, 0>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s)
-             : run_batched<double, 1>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s);
-  } else {
-    st = variant == 0
-             ? run_batched<float, 0>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s)
-             : run_batched<float, 1>(common, inst_dev, tile_map_dev, n_inst, total_tiles, blocks, s);
-  }
+  st = run_batched_any(common, inst_dev, tile_map_dev, n_inst, total_tiles, variant, blocks,
+                       (hipStream_t)stream);
   if (st) return st;
+  return ok();
+}
+
+hweno_status hweno_autotune(const hweno_problem* common, const hweno_instance* inst_dev,
+                            const int32_t* const* tile_maps_dev, int32_t n_inst,
+                            const int32_t* total_tiles, int32_t trials, void* stream,
+                            int32_t* variant, int32_t* blocks, double* times_ms,
+                            int32_t* grid_sizes) {
+  hweno_status st = batch_common_ok(common);
+  if (st) return st;
+  if (!inst_dev || !tile_maps_dev || !total_tiles || !variant || !blocks || n_inst < 1)
+    return fail(HWENO_ERR_INVALID_ARG,
+                "inst_dev, tile_maps_dev, total_tiles, variant, blocks must be non-NULL, n_inst >= 1");
+  if (trials < 1 || trials > 1000) return fail(HWENO_ERR_INVALID_ARG, "trials must be in [1, 1000]");
+  for (int v = 0; v < HWENO_BATCH_VARIANTS; ++v) {
+    if (!tile_maps_dev[v]) return fail(HWENO_ERR_INVALID_ARG, "tile map of variant %d is NULL", v);
+    if (total_tiles[v] < n_inst)
+      return fail(HWENO_ERR_INVALID_ARG, "variant %d: total_tiles must be >= n_inst", v);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  // the diagnostic stage timer must not see the autotuner's launches
+  const bool timing_was_on = g_timing.on;
+  g_timing.on = false;
+  struct Restore {
+    bool on;
+    ~Restore() { g_timing.on = on; }
+  } restore{timing_was_on};
+  EventPair ev;
+  hipError_t e = hipEventCreate(&ev.a);
+  if (e == hipSuccess) e = hipEventCreate(&ev.b);
+  if (e != hipSuccess) return fail(HWENO_ERR_LAUNCH, "hipEventCreate: %s", hipGetErrorString(e));
+  double best = 0.0;
+  int best_v = -1, best_b = 0;
+  for (int v = 0; v < HWENO_BATCH_VARIANTS; ++v) {
+    int cand[HWENO_AUTOTUNE_CANDIDATES];
+    autotune_candidates(total_tiles[v], cand);
+    for (int c = 0; c < HWENO_AUTOTUNE_CANDIDATES; ++c) {
+      const int b = cand[c];
+      // one warm-up step, then `trials` timed steps between two events
+      st = run_batched_any(common, inst_dev, tile_maps_dev[v], n_inst, total_tiles[v], v, b, s);
+      if (st) return st;
+      if ((e = hipEventRecord(ev.a, s)) != hipSuccess)
+        return fail(HWENO_ERR_LAUNCH, "hipEventRecord: %s", hipGetErrorString(e));
+      for (int q = 0; q < trials; ++q) {
+        st = run_batched_any(common, inst_dev, tile_maps_dev[v], n_inst, total_tiles[v], v, b, s);
+        if (st) return st;
+      }
+      if ((e = hipEventRecord(ev.b, s)) != hipSuccess ||
+          (e = hipEventSynchronize(ev.b)) != hipSuccess)
+        return fail(HWENO_ERR_LAUNCH, "event: %s", hipGetErrorString(e));
+      float ms = 0.f;
+      if ((e = hipEventElapsedTime(&ms, ev.a, ev.b)) != hipSuccess)
+        return fail(HWENO_ERR_LAUNCH, "hipEventElapsedTime: %s", hipGetErrorString(e));
+      const double per = (double)ms / trials;
+      const int k = v * HWENO_AUTOTUNE_CANDIDATES + c;
+      if (times_ms) times_ms[k] = per;
+      if (grid_sizes) grid_sizes[k] = batched_grid_any(common, v, b, total_tiles[v]);
+      if (best_v < 0 || per < best) {
+        best = per;
+        best_v = v;
+        best_b = b;
+      }
+    }
+  }
+  *variant = best_v;
+  // the grid size itself (the resident capacity resolved), which launches the
+  // same kernels as the candidate when passed back as `blocks`
+  *blocks = batched_grid_any(common, best_v, best_b, total_tiles[best_v]);
   return ok();
 }
 

@@ -118,6 +118,10 @@ def lib() -> ctypes.CDLL:
                                       ctypes.POINTER(ctypes.c_int32), ctypes.c_int32], ctypes.c_int),
             "hweno_rk3_step_batched": ([P, vp, vp, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                         ctypes.c_int32, vp], ctypes.c_int),
+            "hweno_autotune": ([P, vp, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, vp,
+                                ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                dp, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
             "hweno_timing_begin": ([ctypes.c_int32], ctypes.c_int),
             "hweno_timing_end": ([ctypes.POINTER(ctypes.c_int64), dp], ctypes.c_int),
             "hweno_status_string": ([ctypes.c_int32], ctypes.c_char_p),
@@ -505,44 +509,44 @@ class BatchedStepper:
 
 
 _AUTOTUNE_CACHE = {}
+AUTOTUNE_CANDIDATES = 4
 
 
 def autotune_batched(stepper: BatchedStepper, trials: int = 2):
-    """Choose tile variant and persistent grid size by timing steps on scratch copies.
+    """Tile variant and persistent grid size of ``stepper`` chosen by hweno_autotune.
 
-    Runs on clones of the states (the originals are untouched), keeps the
-    fastest configuration in ``stepper`` and in a process-wide cache keyed by
-    the batch's dtype and its instances' shapes and boundary conditions.
+    The library times every (variant, grid) candidate on clones of the states
+    (the originals are untouched) with hipEvents and returns the fastest; this
+    wrapper only prepares the clones, keeps the choice in ``stepper`` and caches it
+    per process, keyed by the batch's dtype and its instances' shapes and boundary
+    conditions.  Returns ((variant, blocks), {(variant, blocks): ms per step}), or
+    the cached choice and None.
     """
     key = (stepper.common.dtype,
            tuple((int(I.nx), int(I.ny), int(I.bc_x), int(I.bc_y)) for I in stepper._host))
     if key in _AUTOTUNE_CACHE:
         stepper.variant, stepper.blocks = _AUTOTUNE_CACHE[key]
         return _AUTOTUNE_CACHE[key], None
-    cus = torch.cuda.get_device_properties(stepper.states[0].device).multi_processor_count
     scratch_states = [S.clone() for S in stepper.states]
     grids = [dict(nx=int(stepper._host[q].nx), dx=stepper._host[q].dx, dy=stepper._host[q].dy,
                   bc_x=stepper._host[q].bc_x, bc_y=stepper._host[q].bc_y,
                   dt_fixed=stepper._host[q].dt_fixed, t_end=stepper._host[q].t_end)
              for q in range(stepper.n)]
     scratch = BatchedStepper(scratch_states, grids, stepper.common)
+    maps = (ctypes.c_void_p * BATCH_VARIANTS)(*[m.data_ptr() for m in scratch.maps])
+    totals = (ctypes.c_int32 * BATCH_VARIANTS)(*scratch.total_tiles)
+    n_cand = BATCH_VARIANTS * AUTOTUNE_CANDIDATES
+    times = (ctypes.c_double * n_cand)()
+    sizes = (ctypes.c_int32 * n_cand)()
+    v, b = ctypes.c_int32(-1), ctypes.c_int32(0)
+    _check(lib().hweno_autotune(ctypes.byref(scratch._c), scratch.desc.data_ptr(), maps, scratch.n,
+                                totals, int(trials), _stream(), ctypes.byref(v), ctypes.byref(b),
+                                times, sizes), "hweno_autotune")
     results = {}
-    for v in range(BATCH_VARIANTS):
-        # 0 = the resident capacity of the stage kernel (persistent), or one
-        # workgroup per tile, or over-subscribed persistent grids
-        for b in (0, 2 * cus, 4 * cus, scratch.total_tiles[v]):
-            scratch.step(v, b)  # warm-up
-            torch.cuda.synchronize()
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record()
-            for _ in range(trials):
-                scratch.step(v, b)
-            e1.record()
-            torch.cuda.synchronize()
-            results[(v, b)] = e0.elapsed_time(e1) / trials
-    best = min(results, key=results.get)
+    for k in range(n_cand):
+        results[(k // AUTOTUNE_CANDIDATES, int(sizes[k]))] = float(times[k])
     del scratch, scratch_states
+    best = (int(v.value), int(b.value))
     stepper.variant, stepper.blocks = best
     _AUTOTUNE_CACHE[key] = best
     return best, results
@@ -635,6 +639,10 @@ class Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, S0, prob: Problem, n_steps: int, ckpt: Optional[int] = None,
                 dt: Optional[float] = None):
+        # the step adjoint has no edge-described sides (whose splits also move
+        # with the time each step reads): refuse before stepping
+        if prob.bc_x == EDGES or (prob.dim == 2 and prob.bc_y == EDGES):
+            raise HwenoError(2, "Rollout", "the adjoint has no edge-described sides")
         S = S0.detach().clone().contiguous()
         if ckpt is None:
             free, _ = torch.cuda.mem_get_info(S.device)

@@ -290,3 +290,41 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(st, "size")] == ctypes.sizeof(cls), st
         for f in fields[st]:
             assert got[(st, f)] == getattr(cls, f).offset, (st, f)
+
+
+def test_autotune_rejects_bad_arguments_before_any_hip_call():
+    """hweno_autotune validates its batch description on the host."""
+    L = _lib_or_skip()
+    common = _prob(nx=1, ny=1).c()
+    maps = (ctypes.c_void_p * 2)(4096, 8192)      # never dereferenced on these paths
+    totals = (ctypes.c_int32 * 2)(10, 12)
+    v, b = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    fake = ctypes.c_void_p(4096)
+
+    def call(c=common, inst=fake, mp=maps, n=2, tot=totals, trials=2, vv=v, bb=b):
+        return L.hweno_autotune(ctypes.byref(c), inst, mp, n, tot, trials, None,
+                                None if vv is None else ctypes.byref(vv),
+                                None if bb is None else ctypes.byref(bb), None, None)
+    assert call(inst=None) == 1
+    assert call(n=0) == 1
+    assert call(trials=0) == 1
+    assert call(trials=1001) == 1
+    assert call(vv=None) == 1
+    assert call(bb=None) == 1
+    assert call(mp=(ctypes.c_void_p * 2)(4096, None)) == 1
+    assert "variant 1" in L.hweno_last_error().decode()
+    assert call(tot=(ctypes.c_int32 * 2)(10, 1)) == 1
+    assert call(c=_prob(dim=1, ny=1, nx=1).c()) == 2          # batched is 2D Euler only
+    assert call(c=_prob(nx=1, ny=1, eps=0.0).c()) == 1
+    assert v.value == -1 and b.value == -1                    # outputs untouched on error
+
+
+def test_rollout_refuses_edge_described_sides_before_stepping():
+    """The differentiable rollout refuses problems its backward cannot differentiate
+    before any step is taken (no GPU needed to reach the refusal)."""
+    _lib_or_skip()
+    edges = (h.Edge(),) * 4
+    prob = _prob(nx=8, ny=8, bc_x=h.EDGES, bc_y=h.OUTFLOW, edges=edges)
+    with pytest.raises(h.HwenoError) as e:
+        h.Rollout.apply(torch.zeros(12, 8, 8, dtype=torch.float64), prob, 3, 0, None)
+    assert e.value.code == 2 and "edge-described" in str(e.value)

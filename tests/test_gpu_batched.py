@@ -154,6 +154,58 @@ def test_batched_graph_replays_match_eager():
         del junk
 
 
+def test_autotune_through_the_c_abi():
+    """hweno_autotune times every (tile variant, grid) candidate on the instances it
+    is given and returns the fastest: times are finite and positive, the choice is
+    their minimum, the grid sizes are the documented candidates (resident capacity,
+    2 and 4 workgroups per compute unit, one per tile), and the tuned instances have
+    advanced by the steps it took (2 variants x 4 candidates x (1 + trials)).  The
+    Python wrapper runs it on clones, leaving the batch untouched, and the stepper
+    then steps with the chosen configuration exactly as per-instance steps do."""
+    import ctypes
+    ws = [hi.euler2d_quadrants(70, 41, 1), hi.euler2d_random_smooth(33, 90, 2),
+          hi.euler2d_quadrants(128, 128, 3, bc=hi.PERIODIC)]
+    announce("autotune C ABI")
+    states, grids, common = _batch(ws, torch.float32)
+    b = h.BatchedStepper(states, grids, common)
+    before = [S.clone() for S in states]
+    maps = (ctypes.c_void_p * 2)(*[m.data_ptr() for m in b.maps])
+    totals = (ctypes.c_int32 * 2)(*b.total_tiles)
+    times = (ctypes.c_double * 8)()
+    sizes = (ctypes.c_int32 * 8)()
+    v, blk = ctypes.c_int32(-1), ctypes.c_int32(-1)
+    trials = 2
+    rc = h.lib().hweno_autotune(ctypes.byref(b._c), b.desc.data_ptr(), maps, b.n, totals, trials,
+                                ctypes.c_void_p(torch.cuda.current_stream().cuda_stream),
+                                ctypes.byref(v), ctypes.byref(blk), times, sizes)
+    assert rc == 0, h.lib().hweno_last_error().decode()
+    t = list(times)
+    assert all(np.isfinite(x) and x > 0 for x in t)
+    k = int(np.argmin(t))
+    assert (v.value, blk.value) == (k // 4, sizes[k])
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for var in range(2):
+        tot = b.total_tiles[var]
+        got = [sizes[var * 4 + c] for c in range(4)]
+        assert got[1:] == [min(2 * cus, tot), min(4 * cus, tot), tot]
+        assert 1 <= got[0] <= tot
+    # the instances it tuned on took 2 x 4 x (1 + trials) steps
+    steps = [int(b.ctrl(q)[9]) for q in range(b.n)]
+    assert steps == [2 * 4 * (1 + trials)] * b.n
+    # the wrapper: clones only, cached, and the chosen configuration steps correctly
+    states2 = [S.clone() for S in before]
+    b2 = h.BatchedStepper(states2, grids, common)
+    h.hweno._AUTOTUNE_CACHE.clear()
+    best, res = h.autotune_batched(b2)
+    assert best in res and (b2.variant, b2.blocks) == best
+    assert all(torch.equal(x, y) for x, y in zip(states2, before))
+    assert h.autotune_batched(b2) == (best, None)
+    b2.step()
+    ref, _ = _individual(ws, torch.float32)
+    for q in range(len(ws)):
+        assert torch.equal(states2[q], ref[q]), q
+
+
 def test_batched_full_config_256_instances():
     """The configured batch: 256 instances, sides ~ U{64..512}, FP32, autotuned."""
     ws = hi.batched_instances(256, 0)
