@@ -22,12 +22,17 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic floating-point work of one 2D Euler cell-stage of the fused
-# stage kernel, characteristic-wise with the limiter (operation count of the
-# formulation: +, -, *, /, sqrt, |.| each 1, fused multiply-add 2):
-# two interfaces (x, y) of ~1740 each, flux differences 72, limiter 8 x ~64,
-# Runge-Kutta combination ~48, wave speeds ~15.
-FLOP_PER_CELL_STAGE = 4130.0
+# Algorithmic floating-point work of one 2D Euler cell-stage (characteristic-wise
+# with the limiter), counted per step of the method: pointwise physics
+# ~85, per direction Roe average, eigenvectors and projections ~660, eight
+# nonlinear reconstructions ~760, linear and mixed fluxes ~160, flux differences
+# ~60, limiter ~510, Runge-Kutta combination ~36 -- about 3.8k.  This count sets
+# `achieved` and `frac` of the roofline object.
+FLOP_PER_CELL_STAGE = 3800.0
+# The same work counted term by term on the formulation the kernel evaluates
+# (+, -, *, /, sqrt, |.| each 1, fused multiply-add 2): two interfaces of ~1740,
+# flux differences 72, limiter 8 x ~64, Runge-Kutta ~48, wave speeds ~15.
+FLOP_PER_CELL_STAGE_DERIVED = 4130.0
 
 # MI355X published peaks (dense vector FP64 / FP32, HBM3E)
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3}
@@ -37,6 +42,10 @@ PEAK_HBM_GBS = 8000.0
 # stage 1 reads S^n (12) and writes S1 (12) + limited base derivatives (8);
 # stages 2, 3 read S_k (12), U^n (4), base (8) and write 12  -> 104 / 3 fields.
 FIELDS_PER_CELL_STAGE = 104.0 / 3.0
+# The compulsory count when the base derivatives are recomputed instead of
+# stored: stage 1 reads 12 and writes 12, stages 2, 3 read 12 + 12 and write
+# 12 -> 32 fields (256 B FP64, 128 B FP32).
+FIELDS_PER_CELL_STAGE_SCOPE = 32.0
 
 # HBM traffic of one stage-kernel launch from rocprofv3 --pmc FETCH_SIZE /
 # WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the hash of the built
@@ -53,6 +62,13 @@ MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
     ("2b7563538fa8c656", "f64", 4096): 9.511e8,
     ("2b7563538fa8c656", "f32", 4096): 8.624e8,
+}
+# Floating-point operations per FP64 cell-stage that the SQ counters of the same
+# device code count (SQ_INSTS_VALU_{ADD,MUL,TRANS}_F64 + 2 x FMA over cells x
+# stages), keyed like MEASURED_TRAFFIC.
+MEASURED_FLOP_PER_CELL_STAGE = {
+    # profiles/k_stage_euler2d_4096_sq_counters.md
+    ("2b7563538fa8c656", "f64", 4096): 4590.0,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
 # x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
@@ -80,38 +96,59 @@ def kernel_sha() -> str:
     return "unknown"
 
 
-def cpu_baseline(n: int = 1024, n1: int = 768):
-    """The CPU oracle, as it stands, on one SSP-RK3 step of an n x n grid with all
-    host threads, and of an n1 x n1 grid with one thread."""
+def cpu_baseline(n: int = 1024, strip: int = 128, c2_steps: int = 300):
+    """The CPU oracle, as it stands (float64, torch CPU), timed on the host:
+    one SSP-RK3 step of the n x n four-quadrant workload with all host threads;
+    the same step on a strip of `strip` rows through the middle of that grid (both
+    discontinuities cross it) with one thread; and the first `c2_steps` steps of
+    the 1D Euler piecewise-constant run (N = 4000, T = 0.2) with one thread (the
+    faster setting for 4000 cells: thread start-up dominates small tensors)."""
     import torch
 
     import hweno_inputs as hi
     from oracle import hweno_ref as o
 
-    def one_step(m):
-        w = hi.euler2d_quadrants(m, m, 0)
-        prob = o.problem_from_workload(w)
-        S = o.as_tensor(w.S)
-        t0 = time.perf_counter()
-        o.rk3_step(S, prob)
-        return time.perf_counter() - t0
-
+    w = hi.euler2d_quadrants(n, n, 0)
+    prob = o.problem_from_workload(w)
+    S = o.as_tensor(w.S)
     cores = torch.get_num_threads()
-    dt = one_step(n)
-    single = None
-    if n1 > 0:
-        torch.set_num_threads(1)
-        try:
-            dt1 = one_step(n1)
-        finally:
-            torch.set_num_threads(cores)
-        single = {"value": n1 * n1 * 3 / dt1, "cores": 1,
-                  "sample": f"one step at {n1}x{n1}, {dt1:.1f} s"}
-    return {"value": n * n * 3 / dt, "unit": "cell-stage updates/s",
+    t0 = time.perf_counter()
+    o.rk3_step(S, prob)
+    dt_all = time.perf_counter() - t0
+    j0 = (n - strip) // 2
+    Ss = S[:, j0:j0 + strip, :].contiguous()
+    torch.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        o.rk3_step(Ss, prob)
+        dt_one = time.perf_counter() - t0
+        w1 = hi.euler1d_piecewise(4000, 0)
+        p1 = o.problem_from_workload(w1)
+        S1 = o.as_tensor(w1.S)
+        t = 0.0
+        steps = 0
+        t0 = time.perf_counter()
+        while steps < c2_steps and t < 0.2:
+            a0 = o.max_speeds(S1, p1)
+            dt = min(o.cfl_dt(a0, p1), 0.2 - t)
+            S1, _, _ = o.rk3_step(S1, p1, dt, [a0, None, None], t)
+            t += dt
+            steps += 1
+        dt_c2 = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(cores)
+    return {"value": n * n * 3 / dt_all, "unit": "cell-stage updates/s",
             "cores": cores, "kind": "oracle",
             "sample": f"one SSP-RK3 step (3 cell-stages per cell) of the four-quadrant 2D Euler "
-                      f"workload at {n}x{n} in float64 (torch CPU), {dt:.1f} s",
-            "single_thread": single}
+                      f"workload at {n}x{n} in float64 (torch CPU, {cores} threads), {dt_all:.1f} s",
+            "single_thread": {"value": n * strip * 3 / dt_one, "cores": 1,
+                              "sample": f"the same step on rows {j0}..{j0 + strip - 1} of the "
+                                        f"{n}x{n} grid ({n}x{strip} cells), {dt_one:.1f} s"},
+            "euler1d_4000": {"value": 4000 * 3 * steps / dt_c2, "cores": 1,
+                             "unit": "cell-stage updates/s",
+                             "sample": f"first {steps} steps (t = {t:.3e} of 0.2) of the 1D Euler "
+                                       f"piecewise-constant run, N = 4000, seed 0, "
+                                       f"{dt_c2:.1f} s"}}
 
 
 def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
@@ -148,11 +185,15 @@ def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
     per_launch_s = stage_ms / 1e3 / max(launches, 1)
     flops = FLOP_PER_CELL_STAGE * cells
     achieved = flops / per_launch_s / 1e12
+    achieved_derived = FLOP_PER_CELL_STAGE_DERIVED * cells / per_launch_s / 1e12
     byt = FIELDS_PER_CELL_STAGE * cells * (8 if dtype_name == "f64" else 4)
     return {
         "rate": rate, "wall_s": wall, "event_ms": ev_ms, "ms_per_step": wall * 1e3 / steps,
         "stage_launches": launches, "stage_ms_avg": per_launch_s * 1e3,
-        "achieved_tflops": achieved, "algorithmic_hbm_gbs": byt / per_launch_s / 1e9,
+        "achieved_tflops": achieved, "achieved_tflops_derived": achieved_derived,
+        "algorithmic_hbm_gbs": byt / per_launch_s / 1e9,
+        "scope_hbm_gbs": FIELDS_PER_CELL_STAGE_SCOPE * cells * (8 if dtype_name == "f64" else 4)
+        / per_launch_s / 1e9,
         "t": st.t, "status": status, "finite_ok": ok,
     }
 
@@ -229,10 +270,11 @@ def run_small(n: int = 4000, steps: int = 200):
             "status": st.status}
 
 
-def _time_to_solution(w, **kw):
+def _time_to_solution(w, max_steps: int = 0, **kw):
     """Whole run of a 2D Euler workload with edge-described sides to its T in FP64:
     device-side time steps in multi-step calls of 256, the last one clipped to T.  A
-    warm-up of a few steps on a copy first; the time covers the whole run."""
+    warm-up of a few steps on a copy first; the time covers the whole run.  With
+    max_steps > 0 only that many steps are taken (for profiling runs)."""
     import torch
 
     import paper_2207_05258_amd as h
@@ -248,9 +290,11 @@ def _time_to_solution(w, **kw):
     torch.cuda.synchronize()
     st = h.Stepper(prob)
     t0 = time.perf_counter()
-    chunk = 256
-    while st.t < T * (1 - 1e-13):
+    chunk = 256 if max_steps <= 0 else min(256, max_steps)
+    taken = 0
+    while st.t < T * (1 - 1e-13) and (max_steps <= 0 or taken < max_steps):
         st.steps(S, chunk, t_end=T)
+        taken += chunk
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     steps = int(st.ctrl[9])
@@ -258,20 +302,20 @@ def _time_to_solution(w, **kw):
             "unit": "cell-stage updates/s", "t": st.t, "status": st.status & ~h.hweno.ST_SKIPPED}
 
 
-def run_double_mach(nx: int = 1920, ny: int = 480):
+def run_double_mach(nx: int = 1920, ny: int = 480, max_steps: int = 0):
     """Double Mach reflection (Example 3.11) on [0, 4] x [0, 1] to T = 0.2: post-shock
     inflow, a wall from x = 1/6 on the bottom, the exact shock motion on the top."""
     import hweno_inputs as hi
-    r = _time_to_solution(hi.double_mach(nx, ny))
+    r = _time_to_solution(hi.double_mach(nx, ny), max_steps)
     return {"workload": f"double Mach reflection (Example 3.11), {nx}x{ny}, T = 0.2, FP64", **r}
 
 
-def run_forward_step(nx: int = 960, ny: int = 320):
+def run_forward_step(nx: int = 960, ny: int = 320, max_steps: int = 0):
     """Forward-facing step (Example 3.12) at the paper's 960 x 320 cells to T = 4, with the
     limiter on characteristic fields (with the component-wise limiter the pressure turns
     negative near t = 1.1)."""
     import hweno_inputs as hi
-    r = _time_to_solution(hi.forward_step(nx, ny), limiter_characteristic=True)
+    r = _time_to_solution(hi.forward_step(nx, ny), max_steps, limiter_characteristic=True)
     return {"workload": f"forward-facing step (Example 3.12), {nx}x{ny}, T = 4, FP64, "
                         "characteristic limiter", **r}
 
@@ -317,6 +361,35 @@ def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 0, dtype_name: str =
             "grad_finite": bool(torch.isfinite(g).all()), "grad_norm_U": float(g[:4].norm())}
 
 
+def summarize_pmc(root: str, match: str = "") -> str:
+    """Markdown table of the mean value per dispatch of every rocprofv3 --pmc counter,
+    per kernel, from the counter_collection.csv files under `root` (kernels whose
+    name contains `match`).  Used to turn raw counter dumps into short summaries."""
+    import csv
+    import glob
+    sums, counts, kernels, names = {}, {}, [], []
+    for path in sorted(glob.glob(os.path.join(root, "**", "*counter_collection.csv"), recursive=True)):
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                k, c = row.get("Kernel_Name", ""), row.get("Counter_Name", "")
+                if match not in k:
+                    continue
+                key = (k, c)
+                sums[key] = sums.get(key, 0.0) + float(row.get("Counter_Value", 0.0))
+                counts[key] = counts.get(key, 0) + 1
+                if k not in kernels:
+                    kernels.append(k)
+                if c not in names:
+                    names.append(c)
+    lines = ["| kernel | dispatches | " + " | ".join(names) + " |",
+             "|---|---|" + "---|" * len(names)]
+    for k in kernels:
+        n = max(counts.get((k, c), 0) for c in names)
+        vals = [f"{sums[(k, c)] / counts[(k, c)]:.4g}" if (k, c) in counts else "" for c in names]
+        lines.append(f"| {k[:90]} | {n} | " + " | ".join(vals) + " |")
+    return "\n".join(lines)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -327,9 +400,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the secondary run in the other precision")
-    ap.add_argument("--cpu-n", type=int, default=2048)
-    ap.add_argument("--cpu-n1", type=int, default=768,
-                    help="grid side of the one-thread oracle sample (0 = skip)")
+    ap.add_argument("--cpu-n", type=int, default=1024)
+    ap.add_argument("--cpu-strip", type=int, default=128,
+                    help="rows of the one-thread oracle sample of the cpu-n grid")
+    ap.add_argument("--cpu-c2-steps", type=int, default=300,
+                    help="steps of the 1D Euler N = 4000 run timed on one thread")
+    ap.add_argument("--no-1024", action="store_true", help="skip the 1024^2 rows")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
     ap.add_argument("--no-small", action="store_true",
@@ -340,9 +416,19 @@ def main():
                     default=None,
                     help="run only this part and print its JSON object (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
+    ap.add_argument("--summarize-pmc", metavar="DIR", default=None,
+                    help="print a markdown table of the rocprofv3 counters under DIR and exit")
+    ap.add_argument("--match", default="", help="kernel-name filter of --summarize-pmc")
+    ap.add_argument("--edge-steps", type=int, default=0,
+                    help="run only this many steps of the double Mach and forward-step legs "
+                         "(0 = to their end times)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain device copy of 1 GiB (for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc, args.match))
+        return
 
     if args.copy_calibration:
         import torch
@@ -374,10 +460,10 @@ def main():
         print(json.dumps(run_adjoint(steps=args.adjoint_steps)), flush=True)
         return
     if args.only == "double_mach":
-        print(json.dumps(run_double_mach()), flush=True)
+        print(json.dumps(run_double_mach(max_steps=args.edge_steps)), flush=True)
         return
     if args.only == "forward_step":
-        print(json.dumps(run_forward_step()), flush=True)
+        print(json.dumps(run_forward_step(max_steps=args.edge_steps)), flush=True)
         return
 
     main_run = run_gpu(args.n, args.dtype, args.steps, args.warmup)
@@ -393,6 +479,18 @@ def main():
                    "roofline_frac": v["achieved_tflops"] / PEAK_TFLOPS[other],
                    "status": v["status"]}
 
+    rows_1024 = None
+    if not args.no_1024 and args.n != 1024:
+        rows_1024 = {}
+        for dt_name in ("f64", "f32"):
+            r = run_gpu(1024, dt_name, args.steps, args.warmup)
+            rows_1024[dt_name] = {"value": r["rate"], "ms_per_step": r["ms_per_step"],
+                                  "stage_ms_avg": r["stage_ms_avg"],
+                                  "roofline_frac": r["achieved_tflops"] / PEAK_TFLOPS[dt_name],
+                                  "status": r["status"]}
+        print(f"# 1024^2: f64 {rows_1024['f64']['value']:.4e}, f32 {rows_1024['f32']['value']:.4e} "
+              "cell-stage/s", file=sys.stderr, flush=True)
+
     batched = None
     if not args.no_batched:
         batched = run_batched(args.steps, max(args.warmup, 1))
@@ -404,10 +502,14 @@ def main():
 
     adjoint = None
     if not args.no_adjoint:
-        adjoint = run_adjoint(steps=args.adjoint_steps, ckpt=0)
-        adjoint["checkpointed"] = run_adjoint(steps=args.adjoint_steps, ckpt=20)
-        print(f"# adjoint: backward/forward {adjoint['backward_over_forward']:.2f} (every step kept), "
-              f"{adjoint['checkpointed']['backward_over_forward']:.2f} (checkpoint every 20)",
+        # the configured rollout checkpoints every 20 steps; the target is a backward
+        # of at most 3x the forward
+        adjoint = run_adjoint(steps=args.adjoint_steps, ckpt=20)
+        adjoint["target_backward_over_forward"] = 3.0
+        adjoint["meets_target"] = adjoint["backward_over_forward"] <= 3.0
+        adjoint["every_step_kept"] = run_adjoint(steps=args.adjoint_steps, ckpt=0)
+        print(f"# adjoint: backward/forward {adjoint['backward_over_forward']:.2f} (checkpoint every "
+              f"20), {adjoint['every_step_kept']['backward_over_forward']:.2f} (every step kept)",
               file=sys.stderr, flush=True)
 
     dmr = None if args.no_double_mach else run_double_mach()
@@ -432,6 +534,10 @@ def main():
         valu = {"lane_instr_per_s": float(f"{rate:.4g}"), "peak": peak_issue,
                 "frac": round(rate / peak_issue, 4),
                 "source": "SQ_INSTS_VALU per launch (rocprofv3) over the live launch time"}
+    cells = args.n * args.n
+    esize = 8 if args.dtype == "f64" else 4
+    counted = MEASURED_FLOP_PER_CELL_STAGE.get((sha, args.dtype, args.n))
+    per_launch_s = main_run["stage_ms_avg"] * 1e-3
     roofline = {
         "bound": "alu",
         "achieved": round(main_run["achieved_tflops"], 3),
@@ -441,12 +547,25 @@ def main():
         "traffic": traffic,
         "kernel": "k_stage (fused SSP-RK3 stage)",
         "flop_per_cell_stage": FLOP_PER_CELL_STAGE,
-        "algorithmic_hbm_GBps": round(main_run["algorithmic_hbm_gbs"], 1),
-        "hbm_frac": round(main_run["algorithmic_hbm_gbs"] / PEAK_HBM_GBS, 4),
+        "derived": {"flop_per_cell_stage": FLOP_PER_CELL_STAGE_DERIVED,
+                    "achieved": round(main_run["achieved_tflops_derived"], 3),
+                    "frac": round(main_run["achieved_tflops_derived"] / PEAK_TFLOPS[args.dtype], 4)},
+        "counted": None if counted is None else {
+            "flop_per_cell_stage": counted,
+            "achieved": round(counted * cells / per_launch_s / 1e12, 3),
+            "frac": round(counted * cells / per_launch_s / 1e12 / PEAK_TFLOPS[args.dtype], 4),
+            "source": "SQ_INSTS_VALU_*_F64 counters of the same device code"},
+        "hbm_bytes_per_cell_stage": 32 * esize,
+        "algorithmic_hbm_GBps": round(main_run["scope_hbm_gbs"], 1),
+        "hbm_frac": round(main_run["scope_hbm_gbs"] / PEAK_HBM_GBS, 4),
+        "stored_base_hbm_GBps": round(main_run["algorithmic_hbm_gbs"], 1),
+        "traffic_over_algorithmic": None if traffic is None else
+        round(traffic / (32 * esize * cells), 3),
         "stage_launch_ms": round(main_run["stage_ms_avg"], 4),
         "valu_issue": valu,
     }
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n, args.cpu_n1)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.cpu_n, args.cpu_strip,
+                                                          args.cpu_c2_steps)
     out = {
         # value: the cell-stage rate; the %HBM roofline is roofline.hbm_frac, and the
         # adjoint/forward time is adjoint.backward_over_forward
@@ -470,6 +589,7 @@ def main():
         "paper_timings": "none published: the paper shows efficiency only as error-versus-CPU-time "
                          "figures, without numbers or stated hardware",
         "variant": variant,
+        "c3_1024": rows_1024,
         "batched": batched,
         "adjoint": adjoint,
         "small_grid": small,

@@ -18,8 +18,8 @@ def test_bench_reduced_run_prints_one_valid_json_line():
         pytest.skip("no GPU")
     print("\n[case] bench.py reduced", flush=True)
     cmd = [sys.executable, os.path.join(ROOT, "bench.py"), "--n", "512", "--steps", "3",
-           "--warmup", "1", "--cpu-n", "64", "--cpu-n1", "32", "--adjoint-steps", "4",
-           "--no-batched"]
+           "--warmup", "1", "--cpu-n", "64", "--cpu-strip", "16", "--cpu-c2-steps", "3",
+           "--adjoint-steps", "4", "--no-batched"]
     r = subprocess.run(cmd, capture_output=True, text=True, timeout=280, cwd=ROOT)
     assert r.returncode == 0, r.stderr[-3000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.strip()]
@@ -37,8 +37,16 @@ def test_bench_reduced_run_prints_one_valid_json_line():
     for k in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert k in rf, k
     assert 0 < rf["frac"] < 1 and rf["traffic"] is None    # traffic is measured at 4096^2 only
+    assert rf["flop_per_cell_stage"] == 3800.0 and rf["derived"]["flop_per_cell_stage"] == 4130.0
+    assert rf["hbm_bytes_per_cell_stage"] == 256
     cb = d["cpu_baseline"]
     assert cb["kind"] == "oracle" and cb["value"] > 0 and cb["cores"] >= 1
+    assert cb["single_thread"]["value"] > 0 and cb["euler1d_4000"]["value"] > 0
+    for dt_name in ("f64", "f32"):
+        assert d["c3_1024"][dt_name]["value"] > 0 and d["c3_1024"][dt_name]["status"] == 0
+    # the headline adjoint figure is the configured checkpointed rollout
+    assert d["adjoint"]["checkpoint_every"] == 20 and "meets_target" in d["adjoint"]
+    assert d["adjoint"]["every_step_kept"]["grad_finite"]
     assert d["adjoint"]["grad_finite"] and d["small_grid"]["status"] == 0
     # time-to-solution runs of Examples 3.11 and 3.12: reached T with a clean status word
     for leg, T in (("double_mach", 0.2), ("forward_step", 4.0)):
