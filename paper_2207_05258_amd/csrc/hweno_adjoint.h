@@ -141,7 +141,7 @@ HW_HD void point_fluxes_vjp(const T* U, const T* Dn, const T* Dt, const Consts<T
                             const T* gF, const T* gA, const T* gB, T* gU, T* gDn, T* gDt) {
   if constexpr (PHYS == PH_EULER) {
     const T rho = U[0], mn = U[1], mt = (M == 4) ? U[2] : T(0), E = U[M - 1];
-    const T ir = T(1) / rho;
+    const T ir = fast_rcp(rho);
     const T un = mn * ir, ut = mt * ir;
     const T q2 = un * un + ut * ut;
     const T p = k.gm1 * (E - T(0.5) * rho * q2);
@@ -311,19 +311,23 @@ HW_HD void back_eigen_adj(const Eigen<T, M>& e, const T* w, const T* gy, EigenAd
 // reverse of Eigen::roe(): eigen-system adjoints -> adjoints of UL, UR (accumulated)
 template <typename T, int M>
 HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL, T* gUR) {
-  const T irL = T(1) / UL[0], irR = T(1) / UR[0];
-  const T sL = sqrt(UL[0]), sR = sqrt(UR[0]);
+  // the forward's arithmetic (Eigen::roe): sqrt(rho) and 1/rho from one
+  // reciprocal square root per side
+  const T qL = fast_rsq(UL[0]), qR = fast_rsq(UR[0]);
+  const T sL = UL[0] * qL, sR = UR[0] * qR;
+  const T irL = qL * qL, irR = qR * qR;
   const T uL = UL[1] * irL, uR = UR[1] * irR;
   const T tL = (M == 4) ? UL[2] * irL : T(0), tR = (M == 4) ? UR[2] * irR : T(0);
   const T pL = gm1 * (UL[M - 1] - T(0.5) * UL[0] * (uL * uL + tL * tL));
   const T pR = gm1 * (UR[M - 1] - T(0.5) * UR[0] * (uR * uR + tR * tR));
   const T HL = (UL[M - 1] + pL) * irL, HR = (UR[M - 1] + pR) * irR;
-  const T iw = T(1) / (sL + sR);
+  const T iw = fast_rcp(sL + sR);
   const T wL = sL * iw, wR = sR * iw;
   const T un = wL * uL + wR * uR, ut = wL * tL + wR * tR, H = wL * HL + wR * HR;
   const T hq2 = T(0.5) * (un * un + ut * ut);
-  const T c = sqrt(gm1 * (H - hq2));
-  const T ic = T(1) / c;
+  const T c2 = gm1 * (H - hq2);
+  const T ic = fast_rsq(c2);
+  const T c = c2 * ic;
   const T b1 = gm1 * ic * ic;
   // b2 = b1 hq2, b1 = gm1 ic^2, ic = 1/c, c = sqrt(gm1 (H - hq2))
   const T gb1 = g.b1 + hq2 * g.b2;
@@ -338,7 +342,8 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
   const T gwL = uL * gun + tL * gut + HL * gH, gwR = uR * gun + tR * gut + HR * gH;
   const T giw = sL * gwL + sR * gwR;
   const T gsL = iw * gwL - iw * iw * giw, gsR = iw * gwR - iw * iw * giw;
-  auto side = [&](const T* U, T ir, T s, T u, T t, T p, T w, T gs, T* gU) {
+  // q = 1 / sqrt(rho): d sqrt(rho) / d rho = q / 2
+  auto side = [&](const T* U, T ir, T q, T u, T t, T p, T w, T gs, T* gU) {
     const T gHs = w * gH, gu = w * gun, gt = w * gut;
     T gE = ir * gHs, gp = ir * gHs, gir = (U[M - 1] + p) * gHs;
     gE += gm1 * gp;
@@ -352,14 +357,14 @@ HW_HD void roe_vjp(const T* UL, const T* UR, T gm1, const EigenAdj<T>& g, T* gUL
       gn = ir * gt2;
       gir += U[2] * gt2;
     }
-    grho += T(0.5) * gs / s - ir * ir * gir;
+    grho += T(0.5) * gs * q - ir * ir * gir;
     gU[0] += grho;
     gU[1] += gm;
     if constexpr (M == 4) gU[2] += gn;
     gU[M - 1] += gE;
   };
-  side(UL, irL, sL, uL, tL, pL, wL, gsL, gUL);
-  side(UR, irR, sR, uR, tR, pR, wR, gsR, gUR);
+  side(UL, irL, qL, uL, tL, pL, wL, gsL, gUL);
+  side(UR, irR, qR, uR, tR, pR, wR, gsR, gUR);
 }
 
 // reverse of limit_char(): the adjoint gout of the limited derivative (normal
@@ -422,9 +427,9 @@ HW_HD void limit_char_vjp(const T* um, const T* u0, const T* up, const T* vm, co
 // ---------------------------------------------------------------------------
 enum { EMIT_SET = 0, EMIT_ADD = 1, EMIT_ADD_U = 2 };
 
-template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Emit>
+template <typename T, int PHYS, int M, bool MIXED, typename Loader, typename Emit, typename GH>
 HW_HD void interface_vjp(const Loader& ld, T alpha, T h, T ih, T an, const Consts<T>& k,
-                         const T* gfh, const T* ghh, const T* gxh, const Emit& emit) {
+                         const T* gfh, const GH& ghh, const GH& gxh, const Emit& emit) {
   constexpr bool CHARW = (PHYS == PH_EULER);
   const bool proj = CHARW && k.characteristic;
   Eigen<T, M> eg;

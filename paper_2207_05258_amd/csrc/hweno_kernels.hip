@@ -1048,18 +1048,34 @@ struct AdjArgs {
   FoldArgs<T> fo;
 };
 
+// a lane's column of an LDS buffer, read as an array
+template <typename T>
+struct Col {
+  const T* p;
+  int stride;
+  __device__ T operator[](int c) const { return p[c * stride]; }
+};
+
 template <typename T>
 struct AdjOcc {
-  static constexpr int WAVES = sizeof(T) == 4 ? 2 : 1;
+  static constexpr int WAVES = sizeof(T) == 4 ? 3 : 1;
 };
 
 constexpr int cmax(int x, int y) { return x > y ? x : y; }
 
 // One output tile of E per workgroup (TX x TY entries, ghost entries
 // included).  Every interface and limiter stencil that touches the tile is
-// differentiated by one lane, which writes its contributions to the stencil's
-// cells into lane-private LDS slots (no atomics); after a barrier the owner
-// of each output entry gathers the slots that point at it.  The state tile is
+// differentiated by one lane.  Its contributions to the stencil's cells are
+// handed over point by point: at each emit every lane writes the values for
+// one stencil point (or one group of points) into its own column of a small
+// LDS buffer, and after a barrier the owner of each output entry adds the
+// column that points at it to its accumulators, which live in registers.
+// No atomics, and the buffer holds one point's contributions instead of a
+// whole stencil's, so several workgroups fit on a compute unit.  The barriers
+// also keep the compiler from holding the staged stencil in registers across
+// the reverse pass (loads after a barrier are reloads).  Lanes without an
+// interface or with a zero adjoint run the same code on a valid stencil (every
+// lane takes part in every barrier) and emit exact zeros.  The state tile is
 // staged cell-interleaved ([row][col][field]) so that one stencil point's
 // fields are read with a few wide LDS loads.
 // CL: the characteristic limiter variant (Euler), a separate instantiation.
@@ -1074,11 +1090,13 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
   constexpr int NIY = (DIM == 2) ? TX * (TY + 3) : 0;  // y-interfaces
   constexpr int NLX = TY * (TX + 2);                   // cells whose x-limiter touches it
   constexpr int NLY = (DIM == 2) ? TX * (TY + 2) : 0;
-  constexpr int GB = cmax(4 * NF * cmax(NIX, NIY), 5 * M * cmax(NLX, NLY));
+  constexpr int NR = cmax(NF, 3 * M);                  // rows of the hand-over buffer
   static_assert(TX * TY <= NT, "one output entry per thread");
+  static_assert(NIX <= NT && NIY <= NT && NLX <= NT && NLY <= NT, "one stencil per lane");
   __shared__ __align__(16) T sm[HR * W * NF];
-  __shared__ T acc[NF * TY * TX];
-  __shared__ T gb[GB];
+  __shared__ T pt[NR * NT];
+  __shared__ T accs[NF * TX * TY];
+  __shared__ T gin[2 * M * NT];  // this lane's adjoints of h-hat and of the mixed flux
   const int nx = a.nx, ny = a.ny;
   const long long fs = a.fs;
   const int ntx = (a.nxe + TX - 1) / TX;
@@ -1115,28 +1133,38 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
   const bool owner = tid < TX * TY;
   const int lx = tid % TX, ly = tid / TX;
   const T idx = T(1.0 / a.dx), hx = T(a.dx);
+  T* acc = accs + (owner ? tid : 0);
+  constexpr int AS = TX * TY;  // stride of the accumulator fields
+  if (owner) {
+#pragma unroll
+    for (int f = 0; f < NF; ++f) acc[f * AS] = T(0);
+  }
+  // row r of this lane's column of the hand-over buffer
+  auto put = [&](int r, T v) { pt[r * NT + tid] = v; };
+  auto col = [&](int r, int q) -> T { return pt[r * NT + q]; };
 
   // ---- x-interfaces I (between cells I and I+1) that touch the tile ----
-  for (int q = tid; q < NIX; q += NT) {
+  {
+    // lanes past the last interface take the last one, with a zero adjoint
+    const int q = tid < NIX ? tid : NIX - 1;
     const int r = q / (TX + 3), ii = q - r * (TX + 3);
     const int j = ry0 + r, I = rx0 - 2 + ii;
-    T* slot = gb + q;  // contribution to field f of point s: slot[(s * NF + f) * NIX]
     T gf[M], gh[M], gx[M];
     bool any = false;
-    if (j >= 0 && j < ny && I >= -1 && I <= nx - 1) {
+    const bool live = tid < NIX && j >= 0 && j < ny && I >= -1 && I <= nx - 1;
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        gf[c] = cr * (xl(c, I + 1, j) - xl(c, I, j)) * idx;
-        gh[c] = cr * (xl(M + c, I + 1, j) - xl(M + c, I, j)) * idx;
-        gx[c] = (DIM == 2) ? cr * (xl(2 * M + c, I + 1, j) - xl(2 * M + c, I, j)) * idx : T(0);
-        any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
-      }
+    for (int c = 0; c < M; ++c) {
+      gf[c] = live ? cr * (xl(c, I + 1, j) - xl(c, I, j)) * idx : T(0);
+      gh[c] = live ? cr * (xl(M + c, I + 1, j) - xl(M + c, I, j)) * idx : T(0);
+      gx[c] = (DIM == 2 && live) ? cr * (xl(2 * M + c, I + 1, j) - xl(2 * M + c, I, j)) * idx : T(0);
+      any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
     }
-    if (!any) {
 #pragma unroll
-      for (int e = 0; e < 4 * NF; ++e) slot[e * NIX] = T(0);
-      continue;
+    for (int c = 0; c < M; ++c) {
+      gin[c * NT + tid] = gh[c];
+      gin[(M + c) * NT + tid] = gx[c];
     }
+    const Col<T> ghc{gin + tid, NT}, gxc{gin + M * NT + tid, NT};
     const T* row = cell(I - 1, j);
     auto ld = [&](int s, T* U, T* Dn, T* Dt) {
       const T* p = row + s * NF;
@@ -1147,122 +1175,129 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
         Dt[c] = (DIM == 2) ? p[2 * M + c] : T(0);
       }
     };
+    // entry (lx, ly) is point s of interface ii = lx + 3 - s in its row
+    const int qo = ly * (TX + 3) + lx + 3;
     auto emit = [&](int s, int mode, const T* gU, const T* gDn, const T* gDt) {
-      auto put = [&](int f, T v) {
-        T& d = slot[(s * NF + f) * NIX];
-        d = (mode == EMIT_SET) ? v : d + v;
-      };
+      if (mode == EMIT_ADD_U) {
+        // the Roe-average contributions to points 1 and 2 share one hand-over
 #pragma unroll
-      for (int c = 0; c < M; ++c) {
-        put(c, gU[c]);
-        if (mode != EMIT_ADD_U) {
-          put(M + c, gDn[c]);
-          if constexpr (DIM == 2) put(2 * M + c, gDt[c]);
+        for (int c = 0; c < M; ++c) put((s == 1 ? 0 : M) + c, any ? gU[c] : T(0));
+        if (s == 1) return;
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          put(c, any ? gU[c] : T(0));
+          put(M + c, any ? gDn[c] : T(0));
+          if constexpr (DIM == 2) put(2 * M + c, any ? gDt[c] : T(0));
         }
       }
+      __syncthreads();
+      if (owner) {
+        if (mode == EMIT_ADD_U) {
+#pragma unroll
+          for (int c = 0; c < M; ++c) acc[(c) * AS] += col(c, qo - 1) + col(M + c, qo - 2);
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[(f) * AS] += col(f, qo - s);
+        }
+      }
+      __syncthreads();
     };
-    interface_vjp<T, PHYS, M, DIM == 2>(ld, T(a.alpha[0]), hx, idx, k.ax, k, gf, gh, gx, emit);
-  }
-  __syncthreads();
-  if (owner) {
-    // entry (lx, ly) is point s of interface ii = lx + 3 - s in its row
-    const T* b = gb + ly * (TX + 3) + lx + 3;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-      T v = T(0);
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2) v += b[(s2 * NF + f) * NIX - s2];
-      acc[(f * TY + ly) * TX + lx] = v;
-    }
+    interface_vjp<T, PHYS, M, DIM == 2>(ld, T(a.alpha[0]), hx, idx, k.ax, k, gf, ghc, gxc, emit);
   }
 
   if constexpr (DIM == 2) {
     const T idy = T(1.0 / a.dy), hy = T(a.dy);
-    __syncthreads();
     // ---- y-interfaces J (between rows J and J+1) that touch the tile ----
-    for (int q = tid; q < NIY; q += NT) {
-      const int jj = q / TX, cc = q - jj * TX;
-      const int i = rx0 + cc, J = ry0 - 2 + jj;
-      T* slot = gb + q;
-      T gf[M], gh[M], gx[M];
-      bool any = false;
-      if (i >= 0 && i < nx && J >= -1 && J <= ny - 1) {
+    const int q = tid < NIY ? tid : NIY - 1;
+    const int jj = q / TX, cc = q - jj * TX;
+    const int i = rx0 + cc, J = ry0 - 2 + jj;
+    T gf[M], gh[M], gx[M];
+    bool any = false;
+    const bool live = tid < NIY && i >= 0 && i < nx && J >= -1 && J <= ny - 1;
 #pragma unroll
-        for (int c = 0; c < M; ++c) {
-          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-          gf[c] = cr * (xl(cs, i, J + 1) - xl(cs, i, J)) * idy;
-          gh[c] = cr * (xl(2 * M + cs, i, J + 1) - xl(2 * M + cs, i, J)) * idy;  // theta-hat
-          gx[c] = cr * (xl(M + cs, i, J + 1) - xl(M + cs, i, J)) * idy;          // xi-hat
-          any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
-        }
-      }
-      if (!any) {
-#pragma unroll
-        for (int e = 0; e < 4 * NF; ++e) slot[e * NIY] = T(0);
-        continue;
-      }
-      const T* col = cell(i, J - 1);
-      auto ld = [&](int s, T* U, T* Dn, T* Dt) {
-        const T* p = col + s * (W * NF);
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          // normal frame: swap the two momenta; Dn = U_y, Dt = U_x
-          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-          U[c] = p[cs];
-          Dn[c] = p[2 * M + cs];
-          Dt[c] = p[M + cs];
-        }
-      };
-      auto emit = [&](int s, int mode, const T* gU, const T* gDn, const T* gDt) {
-        auto put = [&](int f, T v) {
-          T& d = slot[(s * NF + f) * NIY];
-          d = (mode == EMIT_SET) ? v : d + v;
-        };
-#pragma unroll
-        for (int c = 0; c < M; ++c) {
-          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
-          put(cs, gU[c]);
-          if (mode != EMIT_ADD_U) {
-            put(2 * M + cs, gDn[c]);
-            put(M + cs, gDt[c]);
-          }
-        }
-      };
-      interface_vjp<T, PHYS, M, true>(ld, T(a.alpha[1]), hy, idy, k.ay, k, gf, gh, gx, emit);
+    for (int c = 0; c < M; ++c) {
+      const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+      gf[c] = live ? cr * (xl(cs, i, J + 1) - xl(cs, i, J)) * idy : T(0);
+      gh[c] = live ? cr * (xl(2 * M + cs, i, J + 1) - xl(2 * M + cs, i, J)) * idy : T(0);  // theta-hat
+      gx[c] = live ? cr * (xl(M + cs, i, J + 1) - xl(M + cs, i, J)) * idy : T(0);          // xi-hat
+      any = any || gf[c] != T(0) || gh[c] != T(0) || gx[c] != T(0);
     }
-    __syncthreads();
-    if (owner) {
-      // entry (lx, ly) is point s of interface jj = ly + 3 - s in its column
-      const T* b = gb + (ly + 3) * TX + lx;
+    __syncthreads();  // the x pass's last readers of gin are done
 #pragma unroll
-      for (int f = 0; f < NF; ++f) {
-        T v = T(0);
-#pragma unroll
-        for (int s2 = 0; s2 < 4; ++s2) v += b[(s2 * NF + f) * NIY - s2 * TX];
-        acc[(f * TY + ly) * TX + lx] += v;
-      }
+    for (int c = 0; c < M; ++c) {
+      gin[c * NT + tid] = gh[c];
+      gin[(M + c) * NT + tid] = gx[c];
     }
+    const Col<T> ghc{gin + tid, NT}, gxc{gin + M * NT + tid, NT};
+    const T* colp = cell(i, J - 1);
+    auto ld = [&](int s, T* U, T* Dn, T* Dt) {
+      const T* p = colp + s * (W * NF);
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        // normal frame: swap the two momenta; Dn = U_y, Dt = U_x
+        const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+        U[c] = p[cs];
+        Dn[c] = p[2 * M + cs];
+        Dt[c] = p[M + cs];
+      }
+    };
+    // entry (lx, ly) is point s of interface jj = ly + 3 - s in its column
+    const int qo = (ly + 3) * TX + lx;
+    auto emit = [&](int s, int mode, const T* gU, const T* gDn, const T* gDt) {
+      if (mode == EMIT_ADD_U) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          put((s == 1 ? 0 : M) + cs, any ? gU[c] : T(0));
+        }
+        if (s == 1) return;
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const int cs = (PHYS == PH_EULER && (c == 1 || c == 2)) ? 3 - c : c;
+          put(cs, any ? gU[c] : T(0));
+          put(2 * M + cs, any ? gDn[c] : T(0));
+          put(M + cs, any ? gDt[c] : T(0));
+        }
+      }
+      __syncthreads();
+      if (owner) {
+        if (mode == EMIT_ADD_U) {
+#pragma unroll
+          for (int c = 0; c < M; ++c) acc[(c) * AS] += col(c, qo - TX) + col(M + c, qo - 2 * TX);
+        } else {
+#pragma unroll
+          for (int f = 0; f < NF; ++f) acc[(f) * AS] += col(f, qo - s * TX);
+        }
+      }
+      __syncthreads();
+    };
+    interface_vjp<T, PHYS, M, true>(ld, T(a.alpha[1]), hy, idy, k.ay, k, gf, ghc, gxc, emit);
   }
 
   // ---- limiter: U_x along x (and U_y along y) of cells near the tile ----
-  // contributions of the limiter at cell C, component c, slot k:
-  //   0: U at C-1, 1: U at C, 2: U at C+1, 3: derivative at C-1, 4: derivative at C+1
+  // contributions of the limiter at cell C, component c: U at C-1, C, C+1
+  // (handed over together), then the derivative at C-1 and C+1
   if (a.XM) {
-    __syncthreads();
-    for (int q = tid; q < NLX; q += NT) {
+    {
+      const int q = tid < NLX ? tid : NLX - 1;
       const int r = q / (TX + 2), ii = q - r * (TX + 2);
       const int j = ry0 + r, C = rx0 - 1 + ii;
-      const bool live = j >= 0 && j < ny && C >= 0 && C < nx;
-      const T* p = live ? cell(C, j) : sm;
+      const bool live = tid < NLX && j >= 0 && j < ny && C >= 0 && C < nx;
+      const T* p = live ? cell(C, j) : sm + NF;
+      T g[5][M];
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
       if constexpr (CL && PHYS == PH_EULER) {
-        T mu[M], g[5][M];
+        T mu[M];
         bool any = false;
 #pragma unroll
         for (int c = 0; c < M; ++c) {
           mu[c] = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
           any = any || mu[c] != T(0);
-#pragma unroll
-          for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
         }
         if (any) {
           T um[M], u0[M], up[M], vm[M], vp[M];
@@ -1274,119 +1309,126 @@ __global__ __launch_bounds__(NT, AdjOcc<T>::WAVES) void k_adjoint(AdjArgs<T> a, 
           limit_char_vjp<T, M>(um, u0, up, vm, vp, hx, idx, k.lw, k.gm1, mu, g[0], g[1], g[2],
                                g[3], g[4]);
         }
-#pragma unroll
-        for (int c = 0; c < M; ++c)
-#pragma unroll
-          for (int s5 = 0; s5 < 5; ++s5) gb[(s5 * M + c) * NLX + q] = g[s5][c];
       } else {
 #pragma unroll
         for (int c = 0; c < M; ++c) {
           const T mu = live ? cl * a.XM[c * fs + (long long)j * nx + C] : T(0);
-          T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
           if (mu != T(0))
             limit1_vjp(p[-NF + c], p[c], p[NF + c], p[-NF + M + c], p[NF + M + c], hx, idx, k.lw,
-                       mu, g0, g1, g2, g3, g4);
-          gb[(0 * M + c) * NLX + q] = g0;
-          gb[(1 * M + c) * NLX + q] = g1;
-          gb[(2 * M + c) * NLX + q] = g2;
-          gb[(3 * M + c) * NLX + q] = g3;
-          gb[(4 * M + c) * NLX + q] = g4;
+                       mu, g[0][c], g[1][c], g[2][c], g[3][c], g[4][c]);
         }
       }
-    }
-    __syncthreads();
-    if (owner) {
       // entry P = rx0 + lx: the limiter of cell C sits at ii = C - rx0 + 1
-      const T* b = gb + ly * (TX + 2) + lx + 1;  // ii of C = P
+      const int qb = ly * (TX + 2) + lx + 1;
 #pragma unroll
       for (int c = 0; c < M; ++c) {
-        acc[(c * TY + ly) * TX + lx] += b[(0 * M + c) * NLX + 1] + b[(1 * M + c) * NLX] +
-                                        b[(2 * M + c) * NLX - 1];
-        acc[((M + c) * TY + ly) * TX + lx] += b[(3 * M + c) * NLX + 1] + b[(4 * M + c) * NLX - 1];
-      }
-    }
-    if constexpr (DIM == 2) {
-      const T idy = T(1.0 / a.dy), hy = T(a.dy);
-      __syncthreads();
-      for (int q = tid; q < NLY; q += NT) {
-        const int jj = q / TX, cc = q - jj * TX;
-        const int i = rx0 + cc, C = ry0 - 1 + jj;
-        const bool live = i >= 0 && i < nx && C >= 0 && C < ny;
-        const T* p = live ? cell(i, C) : sm;
-        constexpr int S = W * NF;
-        if constexpr (CL && PHYS == PH_EULER) {
-          // normal frame: the two momenta swap places (as in the forward)
-          T mu[M], g[5][M];
-          bool any = false;
-#pragma unroll
-          for (int c = 0; c < M; ++c) {
-            const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
-            mu[c] = live ? cl * a.XM[(M + qc) * fs + (long long)C * nx + i] : T(0);
-            any = any || mu[c] != T(0);
-#pragma unroll
-            for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
-          }
-          if (any) {
-            T um[M], u0[M], up[M], vm[M], vp[M];
-#pragma unroll
-            for (int c = 0; c < M; ++c) {
-              const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
-              um[c] = p[-S + qc], u0[c] = p[qc], up[c] = p[S + qc];
-              vm[c] = p[-S + 2 * M + qc], vp[c] = p[S + 2 * M + qc];
-            }
-            limit_char_vjp<T, M>(um, u0, up, vm, vp, hy, idy, k.lw, k.gm1, mu, g[0], g[1], g[2],
-                                 g[3], g[4]);
-          }
-#pragma unroll
-          for (int c = 0; c < M; ++c) {
-            const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
-#pragma unroll
-            for (int s5 = 0; s5 < 5; ++s5) gb[(s5 * M + qc) * NLY + q] = g[s5][c];
-          }
-        } else {
-#pragma unroll
-          for (int c = 0; c < M; ++c) {
-            const T mu = live ? cl * a.XM[(M + c) * fs + (long long)C * nx + i] : T(0);
-            T g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0;
-            if (mu != T(0))
-              limit1_vjp(p[-S + c], p[c], p[S + c], p[-S + 2 * M + c], p[S + 2 * M + c], hy, idy,
-                         k.lw, mu, g0, g1, g2, g3, g4);
-            gb[(0 * M + c) * NLY + q] = g0;
-            gb[(1 * M + c) * NLY + q] = g1;
-            gb[(2 * M + c) * NLY + q] = g2;
-            gb[(3 * M + c) * NLY + q] = g3;
-            gb[(4 * M + c) * NLY + q] = g4;
-          }
-        }
+        put(c, g[0][c]);
+        put(M + c, g[1][c]);
+        put(2 * M + c, g[2][c]);
       }
       __syncthreads();
       if (owner) {
-        const T* b = gb + (ly + 1) * TX + lx;  // jj of C = P
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          acc[(c) * AS] += col(c, qb + 1) + col(M + c, qb) + col(2 * M + c, qb - 1);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        put(c, g[3][c]);
+        put(M + c, g[4][c]);
+      }
+      __syncthreads();
+      if (owner) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[(M + c) * AS] += col(c, qb + 1) + col(M + c, qb - 1);
+      }
+      __syncthreads();
+    }
+    if constexpr (DIM == 2) {
+      const T idy = T(1.0 / a.dy), hy = T(a.dy);
+      const int q = tid < NLY ? tid : NLY - 1;
+      const int jj = q / TX, cc = q - jj * TX;
+      const int i = rx0 + cc, C = ry0 - 1 + jj;
+      const bool live = tid < NLY && i >= 0 && i < nx && C >= 0 && C < ny;
+      const T* p = live ? cell(i, C) : sm + W * NF;
+      constexpr int S = W * NF;
+      T g[5][M];
+#pragma unroll
+      for (int c = 0; c < M; ++c)
+#pragma unroll
+        for (int s5 = 0; s5 < 5; ++s5) g[s5][c] = T(0);
+      if constexpr (CL && PHYS == PH_EULER) {
+        // normal frame: the two momenta swap places (as in the forward); the
+        // gradients come back in that frame and are swapped on hand-over
+        T mu[M];
+        bool any = false;
 #pragma unroll
         for (int c = 0; c < M; ++c) {
-          acc[(c * TY + ly) * TX + lx] += b[(0 * M + c) * NLY + TX] + b[(1 * M + c) * NLY] +
-                                          b[(2 * M + c) * NLY - TX];
-          acc[((2 * M + c) * TY + ly) * TX + lx] +=
-              b[(3 * M + c) * NLY + TX] + b[(4 * M + c) * NLY - TX];
+          const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
+          mu[c] = live ? cl * a.XM[(M + qc) * fs + (long long)C * nx + i] : T(0);
+          any = any || mu[c] != T(0);
         }
+        if (any) {
+          T um[M], u0[M], up[M], vm[M], vp[M];
+#pragma unroll
+          for (int c = 0; c < M; ++c) {
+            const int qc = (c == 1) ? 2 : (c == 2) ? 1 : c;
+            um[c] = p[-S + qc], u0[c] = p[qc], up[c] = p[S + qc];
+            vm[c] = p[-S + 2 * M + qc], vp[c] = p[S + 2 * M + qc];
+          }
+          limit_char_vjp<T, M>(um, u0, up, vm, vp, hy, idy, k.lw, k.gm1, mu, g[0], g[1], g[2],
+                               g[3], g[4]);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < M; ++c) {
+          const T mu = live ? cl * a.XM[(M + c) * fs + (long long)C * nx + i] : T(0);
+          if (mu != T(0))
+            limit1_vjp(p[-S + c], p[c], p[S + c], p[-S + 2 * M + c], p[S + 2 * M + c], hy, idy,
+                       k.lw, mu, g[0][c], g[1][c], g[2][c], g[3][c], g[4][c]);
+        }
+      }
+      auto fc = [&](int c) { return (CL && PHYS == PH_EULER) ? ((c == 1) ? 2 : (c == 2) ? 1 : c) : c; };
+      const int qb = (ly + 1) * TX + lx;  // jj of C = P
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        put(fc(c), g[0][c]);
+        put(M + fc(c), g[1][c]);
+        put(2 * M + fc(c), g[2][c]);
+      }
+      __syncthreads();
+      if (owner) {
+#pragma unroll
+        for (int c = 0; c < M; ++c)
+          acc[(c) * AS] += col(c, qb + TX) + col(M + c, qb) + col(2 * M + c, qb - TX);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int c = 0; c < M; ++c) {
+        put(fc(c), g[3][c]);
+        put(M + fc(c), g[4][c]);
+      }
+      __syncthreads();
+      if (owner) {
+#pragma unroll
+        for (int c = 0; c < M; ++c) acc[(2 * M + c) * AS] += col(c, qb + TX) + col(M + c, qb - TX);
       }
     }
   }
-  // each owner wrote and reads only its own acc entries: no barrier needed
   if (owner) {
     const int ex = btx * TX + lx, ey = bty * TY + ly;
     if (ex < a.nxe && ey < a.nye) {
       const int i = ex - GX, j = ey - GY;
       const bool inner = i >= 2 && i < nx - 2 && (DIM == 1 || (j >= 2 && j < ny - 2));
-      if (a.fused && inner) {
-        T v[NF];
+      T v[NF];
 #pragma unroll
-        for (int f = 0; f < NF; ++f) v[f] = acc[(f * TY + ly) * TX + lx];
+      for (int f = 0; f < NF; ++f) v[f] = acc[f * AS];
+      if (a.fused && inner) {
         fold_finish<T, NF>(a.fo, (long long)j * nx + i, v);
       } else {
 #pragma unroll
-        for (int f = 0; f < NF; ++f)
-          a.E[((long long)f * a.nye + ey) * a.nxe + ex] = acc[(f * TY + ly) * TX + lx];
+        for (int f = 0; f < NF; ++f) a.E[((long long)f * a.nye + ey) * a.nxe + ex] = v[f];
       }
     }
   }
