@@ -52,23 +52,23 @@ FIELDS_PER_CELL_STAGE_SCOPE = 32.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("75c69249111a9aba", "f64", 4096): 5.0817e+09,
-    ("75c69249111a9aba", "f32", 4096): 2.6225e+09,
+    ("9e2689c84947f2ba", "f64", 4096): 5.0817e+09,
+    ("9e2689c84947f2ba", "f32", 4096): 2.6225e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("75c69249111a9aba", "f64", 4096): 9.511e8,
-    ("75c69249111a9aba", "f32", 4096): 8.624e8,
+    ("9e2689c84947f2ba", "f64", 4096): 9.511e8,
+    ("9e2689c84947f2ba", "f32", 4096): 8.624e8,
 }
 # Floating-point operations per FP64 cell-stage that the SQ counters of the same
 # device code count (SQ_INSTS_VALU_{ADD,MUL,TRANS}_F64 + 2 x FMA over cells x
 # stages), keyed like MEASURED_TRAFFIC.
 MEASURED_FLOP_PER_CELL_STAGE = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("75c69249111a9aba", "f64", 4096): 4591.0,
+    ("9e2689c84947f2ba", "f64", 4096): 4591.0,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
 # x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
@@ -77,23 +77,58 @@ MEASURED_FLOP_PER_CELL_STAGE = {
 PEAK_VALU_LANE_INSTR = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9}
 
 
-def kernel_sha() -> str:
-    """sha256[:16] of the device code embedded in the built library (its .hip_fatbin
-    section): it changes with the kernels, not with host-side code, so a traffic
-    figure measured for one build stays attached to exactly that device code."""
+def kernel_sha(prefix: str = "_ZN5hweno7k_stageI") -> str:
+    """sha256[:16] of the machine code of the kernels whose mangled names start with
+    `prefix` (default: the fused stage kernels k_stage) in the gfx950 code object that
+    libhweno.so embeds.  It changes with those kernels' code and with nothing else, so a
+    traffic or counter figure measured for one build stays attached to exactly the code
+    it was measured on, across changes to other kernels."""
     import struct
     from paper_2207_05258_amd import hweno as hw
     with open(hw.LIB_PATH, "rb") as fh:
         b = fh.read()
-    shoff = struct.unpack_from("<Q", b, 0x28)[0]
-    shentsize, shnum, shstrndx = struct.unpack_from("<HHH", b, 0x3A)
-    secs = [struct.unpack_from("<IIQQQQ", b, shoff + i * shentsize) for i in range(shnum)]
-    names = secs[shstrndx]
-    strtab = b[names[4]:names[4] + names[5]]
-    for name, _typ, _flags, _addr, off, size in secs:
-        if strtab[name:strtab.index(b"\0", name)] == b".hip_fatbin":
-            return hashlib.sha256(b[off:off + size]).hexdigest()[:16]
-    return "unknown"
+
+    def sections(elf):
+        shoff = struct.unpack_from("<Q", elf, 0x28)[0]
+        shentsize, shnum, shstrndx = struct.unpack_from("<HHH", elf, 0x3A)
+        secs = [struct.unpack_from("<IIQQQQIIQQ", elf, shoff + i * shentsize) for i in range(shnum)]
+        names = secs[shstrndx]
+        strtab = elf[names[4]:names[4] + names[5]]
+        return [(strtab[x[0]:strtab.index(b"\0", x[0])], x) for x in secs]
+
+    fatbin = next((elf_sec for n, elf_sec in sections(b) if n == b".hip_fatbin"), None)
+    if fatbin is None:
+        return "unknown"
+    fb = b[fatbin[4]:fatbin[4] + fatbin[5]]
+    if not fb.startswith(b"__CLANG_OFFLOAD_BUNDLE__"):
+        return "unknown"
+    n, p = struct.unpack_from("<Q", fb, 24)[0], 32
+    code = None
+    for _ in range(n):
+        off, size, tl = struct.unpack_from("<QQQ", fb, p)
+        triple = fb[p + 24:p + 24 + tl]
+        p += 24 + tl
+        if triple.endswith(b"gfx950"):
+            code = fb[off:off + size]
+    if code is None or not code.startswith(b"\x7fELF"):
+        return "unknown"
+    secs = sections(code)
+    symtab = next(x for nm, x in secs if nm == b".symtab")
+    strtab = code[secs[symtab[6]][1][4]:][:secs[symtab[6]][1][5]]
+    h = hashlib.sha256()
+    found = []
+    for i in range(symtab[5] // 24):
+        st_name, st_info, _o, st_shndx, st_value, st_size = struct.unpack_from(
+            "<IBBHQQ", code, symtab[4] + 24 * i)
+        name = strtab[st_name:strtab.index(b"\0", st_name)]
+        if (st_info & 0xF) == 2 and name.startswith(prefix.encode()) and st_size > 0:
+            sec = secs[st_shndx][1]
+            off = sec[4] + (st_value - sec[3])
+            found.append((name, code[off:off + st_size]))
+    for name, body in sorted(found):
+        h.update(name)
+        h.update(body)
+    return h.hexdigest()[:16] if found else "unknown"
 
 
 def cpu_baseline(n: int = 1024, strip: int = 128, c2_steps: int = 300):
