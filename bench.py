@@ -131,13 +131,13 @@ def kernel_sha(prefix: str = "_ZN5hweno7k_stageI") -> str:
     return h.hexdigest()[:16] if found else "unknown"
 
 
-def cpu_baseline(n: int = 1024, strip: int = 128, c2_steps: int = 300):
+def cpu_baseline(n: int = 1024, strip: int = 1024, c2_steps: int = 1000):
     """The CPU oracle, as it stands (float64, torch CPU), timed on the host:
     one SSP-RK3 step of the n x n four-quadrant workload with all host threads;
-    the same step on a strip of `strip` rows through the middle of that grid (both
-    discontinuities cross it) with one thread; and the first `c2_steps` steps of
-    the 1D Euler piecewise-constant run (N = 4000, T = 0.2) with one thread (the
-    faster setting for 4000 cells: thread start-up dominates small tensors)."""
+    the same step on `strip` rows through the middle of that grid (the whole grid
+    by default) with one thread; and the first `c2_steps` steps of the 1D Euler
+    piecewise-constant run (N = 4000, T = 0.2) with one thread (the faster setting
+    for 4000 cells: thread start-up dominates small tensors)."""
     import torch
 
     import hweno_inputs as hi
@@ -436,9 +436,9 @@ def main():
     ap.add_argument("--no-variant", action="store_true",
                     help="skip the secondary run in the other precision")
     ap.add_argument("--cpu-n", type=int, default=1024)
-    ap.add_argument("--cpu-strip", type=int, default=128,
+    ap.add_argument("--cpu-strip", type=int, default=1024,
                     help="rows of the one-thread oracle sample of the cpu-n grid")
-    ap.add_argument("--cpu-c2-steps", type=int, default=300,
+    ap.add_argument("--cpu-c2-steps", type=int, default=1000,
                     help="steps of the 1D Euler N = 4000 run timed on one thread")
     ap.add_argument("--no-1024", action="store_true", help="skip the 1024^2 rows")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
