@@ -616,6 +616,28 @@ def rollout_bytes_kept(prob: Problem, n_steps: int) -> int:
     return n_steps * (_ws_stride(prob) + state)
 
 
+def _kept_steps(S: torch.Tensor, prob: Problem, n0: int, n1: int, dt: Optional[float],
+                tapes: torch.Tensor):
+    """Steps n0..n1-1 of S in place, each from its own workspace, keeping every step's
+    input state and workspace (its stage states) for the backward: two allocations,
+    control blocks zeroed by one fill.  Returns (inputs, steppers)."""
+    validate(prob)
+    n = n1 - n0
+    stride = _ws_stride(prob)
+    rows = max(n, 1)
+    raw = torch.empty(rows * stride + 256, dtype=torch.uint8, device=S.device)
+    off = (-raw.data_ptr()) % 256
+    wsall = raw[off:off + rows * stride].view(rows, stride)
+    wsall[:, :CTRL_LEN * 8].zero_()
+    states = torch.empty((n,) + tuple(S.shape), dtype=S.dtype, device=S.device)
+    c = prob.c()
+    steppers = [Stepper._over(prob, c, wsall[q], stride) for q in range(n)]
+    for q in range(n):
+        states[q].copy_(S)
+        steppers[q].step(S, dt=dt, tape=tapes[n0 + q])
+    return [states[q] for q in range(n)], steppers
+
+
 class Rollout(torch.autograd.Function):
     """n_steps SSP-RK3 steps as a differentiable function of the initial state.
 
@@ -625,7 +647,9 @@ class Rollout(torch.autograd.Function):
     device memory for every step (``ckpt=0``), or kept as a checkpoint every
     ``ckpt`` steps and recomputed segment by segment, newest first, with the
     tape replayed; the replay of the next older segment runs on a side stream,
-    overlapped with the adjoints of the current one.  ``ckpt=None`` keeps every
+    overlapped with the adjoints of the current one.  The newest segment, whose
+    adjoints come first, keeps its steps' states from the forward and is not
+    replayed.  ``ckpt=None`` keeps every
     step when that takes at most half of the free device memory, else
     checkpoints every ~sqrt(n_steps) steps.  The backward applies the
     hand-written step adjoints in reverse.  Speeds and time steps are held
@@ -655,30 +679,18 @@ class Rollout(torch.autograd.Function):
         tapes = torch.zeros(n_steps, CTRL_LEN, dtype=torch.float64, device=S.device)
         ckpts, kept = [], None
         if ckpt == 0:
-            # two allocations for the whole rollout: the input state of every step
-            # and every step's workspace (its stage states), control blocks zeroed
-            # by one fill
-            validate(prob)
-            stride = _ws_stride(prob)
-            rows = max(n_steps, 1)
-            raw = torch.empty(rows * stride + 256, dtype=torch.uint8, device=S.device)
-            off = (-raw.data_ptr()) % 256
-            wsall = raw[off:off + rows * stride].view(rows, stride)
-            wsall[:, :CTRL_LEN * 8].zero_()
-            states = torch.empty((n_steps,) + tuple(S.shape), dtype=S.dtype, device=S.device)
-            c = prob.c()
-            steppers = [Stepper._over(prob, c, wsall[n], stride) for n in range(n_steps)]
-            for n in range(n_steps):
-                states[n].copy_(S)
-                steppers[n].step(S, dt=dt, tape=tapes[n])
-            kept = ([states[n] for n in range(n_steps)], steppers)
+            kept = _kept_steps(S, prob, 0, n_steps, dt, tapes)
         else:
-            # one multi-step call per segment between checkpoints
+            # one multi-step call per segment between checkpoints; the newest
+            # segment, whose adjoints the backward takes first, keeps its steps'
+            # states as the kept mode does, so it needs no replay
             st = Stepper(prob, device=S.device)
-            for n0 in range(0, n_steps, ckpt):
+            last0 = ((n_steps - 1) // ckpt) * ckpt if n_steps > 0 else 0
+            for n0 in range(0, last0, ckpt):
                 n1 = min(n0 + ckpt, n_steps)
                 ckpts.append(S.clone())
                 st.steps(S, n1 - n0, dt=dt, tapes=tapes[n0:n1])
+            kept = _kept_steps(S, prob, last0, n_steps, dt, tapes)
         ctx.prob, ctx.n_steps, ctx.ckpt = prob, n_steps, ckpt
         ctx.ckpts, ctx.tapes, ctx.kept = ckpts, tapes, kept
         Rollout.last_tapes = tapes
@@ -688,6 +700,9 @@ class Rollout(torch.autograd.Function):
     def backward(ctx, g):
         prob, n_steps, ckpt = ctx.prob, ctx.n_steps, ctx.ckpt
         lam = g.detach().contiguous().clone()
+        if n_steps == 0:
+            ctx.kept = None
+            return lam, None, None, None, None
         dev = lam.device
         ws = adjoint_workspace(prob, dev)
         if ckpt == 0:
@@ -703,10 +718,11 @@ class Rollout(torch.autograd.Function):
         # Two buffer sets of replayed segments: while the adjoints of one segment
         # run on the caller's stream, the next older segment is replayed on a
         # side stream (it depends only on its checkpoint), so the replay's
-        # partly filled waves of workgroups overlap the adjoint kernels.
+        # partly filled waves of workgroups overlap the adjoint kernels.  The
+        # newest segment's states were kept by the forward.
         main = torch.cuda.current_stream(dev)
         side = torch.cuda.Stream(device=dev)
-        steppers = [[Stepper(prob, device=dev) for _ in range(per)] for _ in range(2)]
+        steppers = [[Stepper(prob, device=dev) for _ in range(per)] for _ in range(2 if nseg > 1 else 0)]
         inputs = [[None] * per, [None] * per]
         free = [None, None]  # event: the adjoints that last read buffer set b are done
         side.wait_stream(main)
@@ -726,8 +742,13 @@ class Rollout(torch.autograd.Function):
                 done.record(side)
             return done
 
-        ready = replay(nseg - 1, (nseg - 1) % 2)
-        for seg in reversed(range(nseg)):
+        ready = replay(nseg - 2, (nseg - 2) % 2) if nseg > 1 else None
+        last0 = (nseg - 1) * ckpt
+        kin, ksteppers = ctx.kept
+        for n in reversed(range(last0, n_steps)):
+            step_adjoint(prob, kin[n - last0], ksteppers[n - last0], ctx.tapes[n], lam, ws)
+        ctx.kept = None
+        for seg in reversed(range(nseg - 1)):
             b = seg % 2
             main.wait_event(ready)
             if seg > 0:

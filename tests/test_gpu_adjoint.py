@@ -240,12 +240,14 @@ def test_rollout_keep_all_equals_checkpointed_replay():
     prob = P.gpu_problem(base, torch.float64)
     tgt = P.to_gpu(target, torch.float64)
     grads, finals = {}, {}
-    for ck in (0, 4, 1, None):
+    # 4: segments of 4, 4, 3 (the newest kept by the forward); 1: ten replayed
+    # single steps and one kept; 20: one segment, kept whole
+    for ck in (0, 4, 1, 20, None):
         X = P.to_gpu(base, torch.float64).requires_grad_(True)
         SN = h.Rollout.apply(X, prob, 11, ck, None)
         _loss(SN, tgt, base.dx, base.dy).backward()
         grads[ck], finals[ck] = X.grad.clone(), SN.detach().clone()
-    for ck in (4, 1, None):
+    for ck in (4, 1, 20, None):
         assert torch.equal(finals[ck], finals[0]), ck
         assert torch.equal(grads[ck], grads[0]), (ck, rel_err(grads[ck], grads[0]))
     stride = (h.workspace_bytes(prob) + 255) // 256 * 256
