@@ -52,23 +52,23 @@ FIELDS_PER_CELL_STAGE_SCOPE = 32.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("9e2689c84947f2ba", "f64", 4096): 5.0817e+09,
-    ("9e2689c84947f2ba", "f32", 4096): 2.6225e+09,
+    ("273b1acf440d496e", "f64", 4096): 5.0819e+09,
+    ("273b1acf440d496e", "f32", 4096): 2.6216e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("9e2689c84947f2ba", "f64", 4096): 9.511e8,
-    ("9e2689c84947f2ba", "f32", 4096): 8.624e8,
+    ("273b1acf440d496e", "f64", 4096): 9.511e8,
+    ("273b1acf440d496e", "f32", 4096): 8.624e8,
 }
 # Floating-point operations per FP64 cell-stage that the SQ counters of the same
 # device code count (SQ_INSTS_VALU_{ADD,MUL,TRANS}_F64 + 2 x FMA over cells x
 # stages), keyed like MEASURED_TRAFFIC.
 MEASURED_FLOP_PER_CELL_STAGE = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("9e2689c84947f2ba", "f64", 4096): 4591.0,
+    ("273b1acf440d496e", "f64", 4096): 4592.0,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
 # x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
@@ -425,6 +425,49 @@ def summarize_pmc(root: str, match: str = "") -> str:
     return "\n".join(lines)
 
 
+def summarize_trace(root: str, match: str = "k_stage<", last: int = 0) -> str:
+    """Markdown summary of a rocprofv3 --kernel-trace --stats run under `root`: the
+    kernel_stats.csv table, and from kernel_trace.csv the average duration of the last
+    `last` dispatches whose name contains `match` (the timed region of a bench run:
+    3 x steps stage launches), the GPU kernel time of every dispatch from the first of
+    them on, and their launch shape."""
+    import csv
+    import glob
+    out = []
+    for path in sorted(glob.glob(os.path.join(root, "**", "*kernel_stats.csv"), recursive=True)):
+        out += ["| kernel | calls | average ns | min ns | max ns | % of GPU time |",
+                "|---|---|---|---|---|---|"]
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                out.append(f"| {row['Name'][:78]} | {row['Calls']} | {float(row['AverageNs']):.0f} | "
+                           f"{float(row['MinNs']):.0f} | {float(row['MaxNs']):.0f} | "
+                           f"{float(row['Percentage']):.2f} |")
+    recs = []
+    for path in sorted(glob.glob(os.path.join(root, "**", "*kernel_trace.csv"), recursive=True)):
+        with open(path, newline="") as fh:
+            recs += list(csv.DictReader(fh))
+    recs.sort(key=lambda r: int(r["Start_Timestamp"]))
+    sel = [i for i, r in enumerate(recs) if match in r["Kernel_Name"]]
+    if last and len(sel) >= last:
+        sel = sel[-last:]
+        dur = [int(recs[i]["End_Timestamp"]) - int(recs[i]["Start_Timestamp"]) for i in sel]
+        tail = recs[sel[0]:]
+        busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tail)
+        r0 = recs[sel[0]]
+
+        def col(*names):
+            return next((r0[n] for n in names if r0.get(n) not in (None, "")), "?")
+        out += ["", f"Last {last} dispatches matching `{match}`: average duration "
+                    f"{sum(dur) / len(dur) / 1e6:.4f} ms (min {min(dur) / 1e6:.4f}, max "
+                    f"{max(dur) / 1e6:.4f}); GPU kernel time of all {len(tail)} dispatches from the "
+                    f"first of them on: {busy / 1e6:.4f} ms.",
+                f"Launch shape: grid {col('Grid_Size', 'Grid_Size_X')} work-items in workgroups of "
+                f"{col('Workgroup_Size', 'Workgroup_Size_X')}; LDS {col('LDS_Block_Size', 'Lds_Size')} B "
+                f"per workgroup, scratch {col('Scratch_Size')} B per lane; VGPRs "
+                f"{col('VGPR_Count', 'Arch_VGPR_Count')}."]
+    return "\n".join(out)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -454,6 +497,10 @@ def main():
     ap.add_argument("--summarize-pmc", metavar="DIR", default=None,
                     help="print a markdown table of the rocprofv3 counters under DIR and exit")
     ap.add_argument("--match", default="", help="kernel-name filter of --summarize-pmc")
+    ap.add_argument("--summarize-trace", metavar="DIR", default=None,
+                    help="print a markdown summary of the rocprofv3 kernel trace under DIR and exit")
+    ap.add_argument("--trace-last", type=int, default=0,
+                    help="with --summarize-trace: average the last this many matching dispatches")
     ap.add_argument("--edge-steps", type=int, default=0,
                     help="run only this many steps of the double Mach and forward-step legs "
                          "(0 = to their end times)")
@@ -463,6 +510,9 @@ def main():
 
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc, args.match))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.match or "k_stage<", args.trace_last))
         return
 
     if args.copy_calibration:

@@ -306,6 +306,16 @@ __device__ __forceinline__ void obstacle_mirror(const StageArgs<T>& a, const Edg
   }
 }
 
+// Where the stage kernels sum the linear derivative fluxes of an x-interface
+// over its four stencil points: in registers in FP64 (two waves per SIMD leave
+// room; the sums of the y-interfaces stay in LDS, as the x results held there
+// leave none), in their flux-buffer slots in FP32 (at five waves per SIMD the
+// registers spill 136-144 B per lane).
+template <typename T>
+struct LinReg {
+  static constexpr bool value = sizeof(T) == 8;
+};
+
 // ---------------------------------------------------------------------------
 // One tile of one stage (K = 1, 2, 3) or of the right-hand side (K = 0).
 // NT threads; TX x TY cells (TX*TY <= NT); sm, fb: LDS staging buffers.
@@ -327,6 +337,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
   constexpr int HR = TY + 2 * HY;     // LDS rows
   constexpr int FW = TX + 1;          // flux buffer row length
   constexpr int FR = TY + 1;          // flux buffer rows
+  constexpr bool LR = LinReg<T>::value;
   static_assert(TX * TY <= NT, "one cell per thread");
 
   const int tid = threadIdx.x;
@@ -443,13 +454,22 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T>& a, const Consts<T
         if constexpr (DIM == 2) Dt[c] = row[((2 * M + c) * HR) * W + s];
       }
     };
-    // linear fluxes accumulate in their flux-buffer slots (owned by this lane)
+    // linear fluxes: their flux-buffer slots belong to this lane; the last
+    // stencil point (s = 3) completes them
+    T ha[M], xa[M];
     auto lin = [&](int s, int c, T dh, T dx) {
       T& h1 = fb[((M + c) * FR + r) * FW + ix];
-      h1 = (s == 0) ? dh : h1 + dh;
-      if constexpr (DIM == 2) {
-        T& x1 = fb[((2 * M + c) * FR + r) * FW + ix];
-        x1 = (s == 0) ? dx : x1 + dx;
+      T* x1 = DIM == 2 ? &fb[((2 * M + c) * FR + r) * FW + ix] : nullptr;  // 2D only
+      if constexpr (LR) {
+        if (s == 0) ha[c] = dh, xa[c] = dx;
+        else if (s < 3) ha[c] += dh, xa[c] += dx;
+        else {
+          h1 = ha[c] + dh;
+          if constexpr (DIM == 2) *x1 = xa[c] + dx;
+        }
+      } else {
+        h1 = (s == 0) ? dh : h1 + dh;
+        if constexpr (DIM == 2) *x1 = (s == 0) ? dx : *x1 + dx;
       }
     };
     T fh[M];
