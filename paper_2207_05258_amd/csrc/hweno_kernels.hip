@@ -1855,8 +1855,10 @@ WsLayout ws_layout(const hweno_problem* p) {
 template <typename T>
 Consts<T> make_consts(const hweno_problem* p) {
   Consts<T> k;
-  k.rw = {T(p->lin_w[0]), T(p->lin_w[1]), T(p->lin_w[2]), T(p->eps)};
-  k.lw = {T(p->lim_w[0]), T(p->lim_w[1]), T(p->lim_w[2]), T(p->eps)};
+  k.rw = {T(p->lin_w[0]), T(p->lin_w[1]), T(p->lin_w[2]), T(p->eps),
+          T(p->lin_w[0]) + T(p->lin_w[1]) + T(p->lin_w[2])};
+  k.lw = {T(p->lim_w[0]), T(p->lim_w[1]), T(p->lim_w[2]), T(p->eps),
+          T(p->lim_w[0]) + T(p->lim_w[1]) + T(p->lim_w[2])};
   k.gm1 = T(p->gamma_gas - 1.0);
   k.gam = T(p->gamma_gas);
   k.ax = T(p->adv_speed[0]);

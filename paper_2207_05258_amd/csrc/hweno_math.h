@@ -33,6 +33,7 @@ template <typename T>
 struct Weights {
   T g0, g1, g2;  // linear weights, positive, summing to one
   T eps;         // epsilon of the nonlinear weights
+  T gs;          // g0 + g1 + g2
 };
 
 template <typename T>
@@ -112,28 +113,37 @@ HW_HD double fast_rsq<double>(double x) {
 // limiter (Section 2.2):
 //   tau = (|b0-b1| + |b0-b2|)^2 / 4,  wbar_l = g_l (1 + tau/(b_l + eps)),
 //   result = w0 (P0/g0 - g1/g0 P1 - g2/g0 P2) + w1 P1 + w2 P2, w = wbar/sum.
-// With e_l = 1 + tau/(b_l+eps) this is
+// With c_l = b_l + eps and e_l = 1 + tau/c_l this is
 //   (e0 P0 + g1 P1 (e1-e0) + g2 P2 (e2-e0)) / (g0 e0 + g1 e1 + g2 e2).
+// combine_c takes the c_l (FP64: callers fold eps into the sums that form the
+// indicators), combine the b_l.
 // ---------------------------------------------------------------------------
 template <typename T>
-HW_HD T combine(T P0, T P1, T P2, T b0, T b1, T b2,
-                                     const Weights<T>& w) {
-  T tau = fabs(b0 - b1) + fabs(b0 - b2);
+HW_HD T combine_c(T P0, T P1, T P2, T c0, T c1, T c2, const Weights<T>& w) {
+  T tau = fabs(c0 - c1) + fabs(c0 - c2);
   tau = T(0.25) * tau * tau;
-  const T c0 = b0 + w.eps, c1 = b1 + w.eps, c2 = b2 + w.eps;
+  // numerator and denominator times P = c0 c1 c2 (one division):
+  //   num = P P0 + tau (c1 c2 P0 + g1 P1 c2 (c0 - c1) + g2 P2 c1 (c0 - c2)),
+  //   den = (g0 + g1 + g2) P + tau (g0 c1 c2 + g1 c0 c2 + g2 c0 c1)
+  const T c12 = c1 * c2;
+  const T P = c0 * c12;
+  const T N = fma(c12, P0, fma(w.g1 * P1 * c2, c0 - c1, w.g2 * P2 * c1 * (c0 - c2)));
+  const T D = fma(w.g0, c12, fma(w.g1, c0 * c2, w.g2 * (c0 * c1)));
+  return fast_div(fma(P, P0, tau * N), fma(w.gs, P, tau * D));
+}
+
+template <typename T>
+HW_HD T combine(T P0, T P1, T P2, T b0, T b1, T b2, const Weights<T>& w) {
   if constexpr (sizeof(T) == 8) {
-    // multiply numerator and denominator by c0 c1 c2: one division
-    const T E0 = (c0 + tau) * (c1 * c2);
-    const T E1 = (c1 + tau) * (c0 * c2);
-    const T E2 = (c2 + tau) * (c0 * c1);
-    const T num = E0 * P0 + tau * (w.g1 * P1 * c2 * (c0 - c1) +
-                                   w.g2 * P2 * c1 * (c0 - c2));
-    const T den = w.g0 * E0 + w.g1 * E1 + w.g2 * E2;
-    return fast_div(num, den);
+    return combine_c(P0, P1, P2, b0 + w.eps, b1 + w.eps, b2 + w.eps, w);
   } else {
-    const T e0 = T(1) + tau * fast_rcp(c0);
-    const T e1 = T(1) + tau * fast_rcp(c1);
-    const T e2 = T(1) + tau * fast_rcp(c2);
+    // FP32: one reciprocal per weight (the products of the single-division
+    // form lose FP32 accuracy when the indicators span many decades)
+    T tau = fabs(b0 - b1) + fabs(b0 - b2);
+    tau = T(0.25) * tau * tau;
+    const T e0 = T(1) + tau * fast_rcp(b0 + w.eps);
+    const T e1 = T(1) + tau * fast_rcp(b1 + w.eps);
+    const T e2 = T(1) + tau * fast_rcp(b2 + w.eps);
     const T num = e0 * P0 + w.g1 * P1 * (e1 - e0) + w.g2 * P2 * (e2 - e0);
     const T den = w.g0 * e0 + w.g1 * e1 + w.g2 * e2;
     return num * fast_rcp(den);
@@ -150,8 +160,15 @@ HW_HD T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
   const T s = fm + fp, dl = fm - fp, lap = s - T(2) * f0;
   const T Hs = Hm + Hp, Hd = Hm - Hp;
   const T p0 = T(11.0 / 60.0) * s + T(19.0 / 30.0) * f0 + T(0.05) * Hd + T(0.5) * H0;
-  const T p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
-  const T p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
+  T p1, p2;
+  if constexpr (sizeof(T) == 8) {
+    const T q = T(5.0 / 6.0) * f0 + T(1.0 / 3.0) * H0;  // shared by p1 and p2
+    p1 = T(1.0 / 6.0) * fm + (T(1.0 / 3.0) * H0 + q);
+    p2 = T(1.0 / 6.0) * fp + q;
+  } else {
+    p1 = T(1.0 / 6.0) * (fm + T(5) * f0) + T(2.0 / 3.0) * H0;
+    p2 = T(1.0 / 6.0) * (T(5) * f0 + fp) + T(1.0 / 3.0) * H0;
+  }
   // beta_0 from the monomial coefficients a1..a5 of p0 in (x - x_i)/dx, i.e.
   //   (a1 + a3/4 + a5/16)^2 + 13/3 (a2 + 63/130 a4)^2 + 781/20 (a3 + 8825/10934 a5)^2
   //   + 1421461/2275 a4^2 + 21520059541/1377684 a5^2,
@@ -164,11 +181,19 @@ HW_HD T hw_plus(T fm, T f0, T fp, T Hm, T H0, T Hp,
   const T x4 = T(-6.249090043648465) * Hd + T(-12.49818008729693) * lap;  // sqrt(1421461/2275) a4
   const T x5 = T(31.24546092343706) * Hs + T(124.98184369374825) * H0 +
                T(93.73638277031118) * dl;                               // sqrt(21520059541/1377684) a5
-  const T b0 = H0 * H0 + x1 * x1 + x2 * x2 + x4 * x4 + x5 * x5;
-  const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp, h2 = H0 * H0;
-  const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
-  const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
-  return combine(p0, p1, p2, b0, b1, b2, w);
+  const T u1 = H0 - f0 + fm, u2 = H0 + f0 - fp;
+  if constexpr (sizeof(T) == 8) {
+    // the indicators with eps added, eps starting the sums
+    const T h2e = H0 * H0 + w.eps;
+    return combine_c(p0, p1, p2, h2e + x1 * x1 + x2 * x2 + x4 * x4 + x5 * x5,
+                     h2e + T(13.0 / 3.0) * u1 * u1, h2e + T(13.0 / 3.0) * u2 * u2, w);
+  } else {
+    const T h2 = H0 * H0;
+    const T b0 = h2 + x1 * x1 + x2 * x2 + x4 * x4 + x5 * x5;
+    const T b1 = h2 + T(13.0 / 3.0) * u1 * u1;
+    const T b2 = h2 + T(13.0 / 3.0) * u2 * u2;
+    return combine(p0, p1, p2, b0, b1, b2, w);
+  }
 }
 
 // HWENO limiter value v~_i (Section 2.2) from u_{i-1}, u_i, u_{i+1},
@@ -188,10 +213,15 @@ HW_HD T limit1(T um, T u0, T up, T vm, T vp, T h, T ih,
   const T x1 = T(0.2682146576235209) * Vd + T(1.5772623149801082) * lap;  // sqrt(13/3)(a2 + 63/130 a4)
   const T x3 = T(1.5622499799967993) * (Vs - D);                         // sqrt(781/20) a3
   const T x4 = T(-6.249090043648465) * Vd + T(-12.49818008729693) * lap;  // sqrt(1421461/2275) a4
-  const T b0 = x0 * x0 + x1 * x1 + x3 * x3 + x4 * x4;
   const T d1 = u0 - um, d2 = up - u0;
   // the combination is linear in the candidates q_l' = (a1, d1, d2) / dx
-  return ih * combine(a1, d1, d2, b0, d1 * d1, d2 * d2, w);
+  if constexpr (sizeof(T) == 8) {
+    // the indicators with eps added, eps starting the sums
+    return ih * combine_c(a1, d1, d2, x0 * x0 + w.eps + x1 * x1 + x3 * x3 + x4 * x4,
+                          d1 * d1 + w.eps, d2 * d2 + w.eps, w);
+  } else {
+    return ih * combine(a1, d1, d2, x0 * x0 + x1 * x1 + x3 * x3 + x4 * x4, d1 * d1, d2 * d2, w);
+  }
 }
 
 // ---------------------------------------------------------------------------
