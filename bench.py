@@ -52,23 +52,23 @@ FIELDS_PER_CELL_STAGE_SCOPE = 32.0
 # device code it was measured on (kernel_sha; other builds report null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("273b1acf440d496e", "f64", 4096): 5.0819e+09,
-    ("273b1acf440d496e", "f32", 4096): 2.6216e+09,
+    ("2b7b55f18c2286ad", "f64", 4096): 5.0817e+09,
+    ("2b7b55f18c2286ad", "f32", 4096): 2.6212e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("273b1acf440d496e", "f64", 4096): 9.511e8,
-    ("273b1acf440d496e", "f32", 4096): 8.624e8,
+    ("2b7b55f18c2286ad", "f64", 4096): 8.950e8,
+    ("2b7b55f18c2286ad", "f32", 4096): 8.624e8,
 }
 # Floating-point operations per FP64 cell-stage that the SQ counters of the same
 # device code count (SQ_INSTS_VALU_{ADD,MUL,TRANS}_F64 + 2 x FMA over cells x
 # stages), keyed like MEASURED_TRAFFIC.
 MEASURED_FLOP_PER_CELL_STAGE = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("273b1acf440d496e", "f64", 4096): 4592.0,
+    ("2b7b55f18c2286ad", "f64", 4096): 4393.0,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
 # x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
