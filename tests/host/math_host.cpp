@@ -1,11 +1,12 @@
 // Host build of the device math (hweno_math.h), driven from
-// tests/test_host_math.py: each input line is
-//   <op> <prec> <a> <b> <c> <d> <e> <f>
-// op 'r': hw_plus(fm, f0, fp, Hm, H0, Hp) with the reconstruction weights;
-// op 'l': limit1(um, u0, up, vm, vp, h = f, 1/h) with the limiter weights;
-// prec 'd' or 'f'.  The weights come first on the command line:
-//   math_host g0 g1 g2 d0 d1 d2 eps
-// One result per line, printed with 17 significant digits.
+// tests/test_host_math.py.  The weights come first on the command line:
+//   math_host g0 g1 g2 d0 d1 d2 eps gamma
+// then each input line is <op> <prec> <values...>, prec 'd' or 'f':
+//   r  fm f0 fp Hm H0 Hp           hw_plus with the reconstruction weights
+//   l  um u0 up vm vp h            limit1 with the limiter weights
+//   p  U[4] Dn[4] Dt[4]            2D Euler point_fluxes: F, A Dn, A Dt
+//   e  UL[4] UR[4] x[4]            Roe-averaged eigen-system: L x, then R (L x)
+// and prints its results on one line, 17 significant digits each.
 #include <cstdio>
 #include <cstdlib>
 
@@ -13,35 +14,64 @@
 
 using namespace hweno;
 
+static double g[6], eps, gam;
+
 template <typename T>
-static Weights<T> weights(double a, double b, double c, double eps) {
-  return Weights<T>{T(a), T(b), T(c), T(eps), T(a) + T(b) + T(c)};
+static Weights<T> weights(int o) {
+  return Weights<T>{T(g[o]), T(g[o + 1]), T(g[o + 2]), T(eps), T(g[o]) + T(g[o + 1]) + T(g[o + 2])};
 }
 
 template <typename T>
-static double run(char op, const double* v, const double* g, double eps) {
-  if (op == 'r')
-    return double(hw_plus<T>(T(v[0]), T(v[1]), T(v[2]), T(v[3]), T(v[4]), T(v[5]),
-                             weights<T>(g[0], g[1], g[2], eps)));
-  const T h = T(v[5]);
-  return double(limit1<T>(T(v[0]), T(v[1]), T(v[2]), T(v[3]), T(v[4]), h, T(1) / h,
-                          weights<T>(g[3], g[4], g[5], eps)));
+static void run(char op, const double* v) {
+  if (op == 'r') {
+    std::printf("%.17g\n", double(hw_plus<T>(T(v[0]), T(v[1]), T(v[2]), T(v[3]), T(v[4]), T(v[5]),
+                                             weights<T>(0))));
+  } else if (op == 'l') {
+    const T h = T(v[5]);
+    std::printf("%.17g\n", double(limit1<T>(T(v[0]), T(v[1]), T(v[2]), T(v[3]), T(v[4]), h,
+                                            T(1) / h, weights<T>(3))));
+  } else if (op == 'p') {
+    Consts<T> k{};
+    k.gm1 = T(gam - 1.0);
+    k.gam = T(gam);
+    T U[4], Dn[4], Dt[4], F[4], A[4], B[4];
+    for (int c = 0; c < 4; ++c) U[c] = T(v[c]), Dn[c] = T(v[4 + c]), Dt[c] = T(v[8 + c]);
+    point_fluxes<T, PH_EULER, 4, true>(U, Dn, Dt, k, T(0), F, A, B);
+    for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(F[c]));
+    for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(A[c]));
+    for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(B[c]));
+    std::printf("\n");
+  } else {
+    T UL[4], UR[4], x[4], w[4], y[4];
+    for (int c = 0; c < 4; ++c) UL[c] = T(v[c]), UR[c] = T(v[4 + c]), x[c] = T(v[8 + c]);
+    Eigen<T, 4> e;
+    e.roe(UL, UR, T(gam - 1.0));
+    e.project(x, w);
+    e.back(w, y);
+    for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(w[c]));
+    for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(y[c]));
+    std::printf("\n");
+  }
 }
 
 int main(int argc, char** argv) {
-  if (argc != 8) {
-    std::fprintf(stderr, "usage: math_host g0 g1 g2 d0 d1 d2 eps\n");
+  if (argc != 9) {
+    std::fprintf(stderr, "usage: math_host g0 g1 g2 d0 d1 d2 eps gamma\n");
     return 2;
   }
-  double g[6];
   for (int i = 0; i < 6; ++i) g[i] = std::atof(argv[1 + i]);
-  const double eps = std::atof(argv[7]);
+  eps = std::atof(argv[7]);
+  gam = std::atof(argv[8]);
   char op, prec;
-  double v[6];
-  while (std::scanf(" %c %c %lf %lf %lf %lf %lf %lf", &op, &prec, &v[0], &v[1], &v[2], &v[3],
-                    &v[4], &v[5]) == 8) {
-    const double r = prec == 'd' ? run<double>(op, v, g, eps) : run<float>(op, v, g, eps);
-    std::printf("%.17g\n", r);
+  while (std::scanf(" %c %c", &op, &prec) == 2) {
+    const int n = (op == 'r' || op == 'l') ? 6 : 12;
+    double v[12];
+    for (int i = 0; i < n; ++i)
+      if (std::scanf("%lf", &v[i]) != 1) return 3;
+    if (prec == 'd')
+      run<double>(op, v);
+    else
+      run<float>(op, v);
   }
   return 0;
 }

@@ -1,12 +1,18 @@
-"""The kernels' reconstruction and limiter arithmetic (hweno_math.h, built for the
-host, where its reciprocals are exact divisions) against the oracle's literal
-Section 2.1 / 2.2 formulas, on seeded data from smooth to discontinuous and over
-many decades of magnitude: the rearranged combinations (FP64: numerator and
-denominator times the product of the three beta_l + eps, epsilon starting the
-indicator sums; FP32: one reciprocal per weight) compute the same function.
-Bounds, relative to the data's scale: FP64 1e-13, FP32 2e-6 (the formulas'
-rounding, a few FP32 ulps of the largest term).  FP32 data stay within six
-decades of their scale: beyond that tau = O(beta^2) leaves the FP32 range."""
+"""The kernels' arithmetic (hweno_math.h, built for the host, where its
+reciprocals and square roots are the exact library ones) against the oracle's
+literal formulas, on seeded data: the reconstruction and the limiter (Sections
+2.1 / 2.2) from smooth to discontinuous data over many decades of magnitude --
+the rearranged combinations (FP64: numerator and denominator times the product
+of the three beta_l + eps, epsilon starting the indicator sums; FP32: one
+reciprocal per weight) compute the same function -- and, for 2D Euler, the
+point fluxes with their chain-rule products (eq. EQ3) and the closed-form
+characteristic projection (Remarks 2.1/2.2: L x solves R w = x for the oracle's
+right eigenvectors at the Roe average, and R L x = x).
+Bounds, relative to the data's scale (for the point fluxes the largest
+component of each output vector, for the projection |x| times the condition
+number of R): FP64 1e-13, FP32 2e-6 (5e-6 for the point fluxes: a few FP32 ulps
+of the largest term).  FP32 data stay within six decades of their scale: beyond
+that tau = O(beta^2) leaves the FP32 range."""
 import hashlib
 import os
 import subprocess
@@ -23,6 +29,7 @@ SRC = ["tests/host/math_host.cpp", "paper_2207_05258_amd/csrc/hweno_math.h"]
 LIN = (0.98, 0.01, 0.01)   # the paper's linear weights gamma
 LIM = (0.98, 0.01, 0.01)   # and d
 EPS = 1e-6
+GAMMA = 1.4
 
 
 def _exe():
@@ -46,11 +53,13 @@ def _exe():
 
 
 def _run(op, prec, rows):
-    args = [_exe()] + [repr(x) for x in LIN + LIM] + [repr(EPS)]
+    args = [_exe()] + [repr(x) for x in LIN + LIM] + [repr(EPS), repr(GAMMA)]
     text = "".join(f"{op} {prec} " + " ".join(repr(float(x)) for x in r) + "\n" for r in rows)
     r = subprocess.run(args, input=text, capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stderr
-    return np.array([float(x) for x in r.stdout.split()])
+    out = np.array([[float(x) for x in ln.split()] for ln in r.stdout.splitlines()])
+    assert out.shape[0] == len(rows)
+    return out[:, 0] if out.shape[1] == 1 else out
 
 
 def _data(seed, n=4000, decades=4, jumps=6):
@@ -105,3 +114,61 @@ def test_limiter_matches_the_oracle(prec, tol):
     scale = np.maximum(np.abs(rows[:, :3]).max(axis=1) / rows[:, 5], np.abs(rows[:, 3:5]).max(axis=1))
     err = np.abs(got - ref) / scale
     assert err.max() <= tol, (err.max(), rows[err.argmax()])
+
+
+def _states(g, n):
+    """Admissible 2D Euler states: density 1e-2..1e2, velocity up to Mach ~3,
+    pressure 1e-2..1e3."""
+    rho = 10.0 ** g.uniform(-2, 2, n)
+    p = 10.0 ** g.uniform(-2, 3, n)
+    c = np.sqrt(GAMMA * p / rho)
+    u = g.uniform(-3, 3, n) * c
+    v = g.uniform(-3, 3, n) * c
+    E = p / (GAMMA - 1.0) + 0.5 * rho * (u * u + v * v)
+    return np.stack([rho, rho * u, rho * v, E], 1)
+
+
+class _Prob:
+    gamma_gas = GAMMA
+    dim = 2
+
+
+@pytest.mark.parametrize("prec,tol", [("d", 1e-13), ("f", 5e-6)])
+def test_point_fluxes_match_the_oracle(prec, tol):
+    g = np.random.default_rng(21)
+    n = 2000
+    U = _states(g, n)
+    D = g.standard_normal((n, 8)) * np.abs(U).max(1, keepdims=True)
+    rows = np.concatenate([U, D], 1)
+    if prec == "f":
+        rows = rows.astype(np.float32).astype(np.float64)
+    got = _run("p", prec, rows)
+    t = torch.as_tensor(rows, dtype=torch.float64)
+    eu = o.Euler(_Prob())
+    ref = torch.cat([eu.flux(t[:, :4], 0), eu.jvp(t[:, :4], t[:, 4:8], 0),
+                     eu.jvp(t[:, :4], t[:, 8:], 0)], 1).numpy()
+    # relative to the largest component of each output vector (F, A Dn, A Dt)
+    scale = np.abs(ref).reshape(-1, 3, 4).max(2, keepdims=True).repeat(4, 2).reshape(-1, 12)
+    err = np.abs(got - ref) / scale
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+@pytest.mark.parametrize("prec,tol", [("d", 1e-13), ("f", 2e-6)])
+def test_characteristic_projection_inverts_the_right_eigenvectors(prec, tol):
+    g = np.random.default_rng(22)
+    n = 2000
+    UL, UR = _states(g, n), _states(g, n)
+    x = g.standard_normal((n, 4)) * np.abs(UL).max(1, keepdims=True)
+    rows = np.concatenate([UL, UR, x], 1)
+    if prec == "f":
+        rows = rows.astype(np.float32).astype(np.float64)
+    got = _run("e", prec, rows)
+    t = torch.as_tensor(rows, dtype=torch.float64)
+    R = o.Euler(_Prob()).right_eigenvectors(t[:, :4], t[:, 4:8], 0)
+    w_ref = torch.linalg.solve(R, t[:, 8:]).numpy()
+    xs = np.abs(rows[:, 8:]).max(1, keepdims=True)
+    cond = torch.linalg.cond(R).numpy()[:, None]
+    err_w = np.abs(got[:, :4] - w_ref) / (xs * cond)
+    err_x = np.abs(got[:, 4:] - rows[:, 8:]) / (xs * cond)
+    assert err_w.max() <= tol, err_w.max()
+    assert err_x.max() <= tol, err_x.max()
