@@ -7,7 +7,9 @@ of the three beta_l + eps, epsilon starting the indicator sums; FP32: one
 reciprocal per weight) compute the same function -- and, for 2D Euler, the
 point fluxes with their chain-rule products (eq. EQ3) and the closed-form
 characteristic projection (Remarks 2.1/2.2: L x solves R w = x for the oracle's
-right eigenvectors at the Roe average, and R L x = x).
+right eigenvectors at the Roe average, and R L x = x); and the hand-written
+reverse-mode derivatives of the reconstruction, the limiter and the point fluxes
+(hweno_adjoint.h) against torch autograd through the oracle's formulas.
 Bounds, relative to the data's scale (for the point fluxes the largest
 component of each output vector, for the projection |x| times the condition
 number of R): FP64 1e-13, FP32 2e-6 (5e-6 for the point fluxes: a few FP32 ulps
@@ -25,7 +27,8 @@ from oracle import hweno_ref as o
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HIPCC = "/opt/rocm/bin/hipcc"
-SRC = ["tests/host/math_host.cpp", "paper_2207_05258_amd/csrc/hweno_math.h"]
+SRC = ["tests/host/math_host.cpp", "paper_2207_05258_amd/csrc/hweno_math.h",
+       "paper_2207_05258_amd/csrc/hweno_adjoint.h"]
 LIN = (0.98, 0.01, 0.01)   # the paper's linear weights gamma
 LIM = (0.98, 0.01, 0.01)   # and d
 EPS = 1e-6
@@ -172,3 +175,44 @@ def test_characteristic_projection_inverts_the_right_eigenvectors(prec, tol):
     err_x = np.abs(got[:, 4:] - rows[:, 8:]) / (xs * cond)
     assert err_w.max() <= tol, err_w.max()
     assert err_x.max() <= tol, err_x.max()
+
+
+def _grad(fn, rows):
+    t = torch.as_tensor(rows, dtype=torch.float64).clone().requires_grad_(True)
+    fn(t).sum().backward()
+    return t.grad.numpy()
+
+
+def test_reconstruction_and_limiter_adjoints_match_autograd():
+    rows = _data(31)
+    got = _run("R", "d", rows)
+    ref = _grad(lambda t: o.hweno_plus(t[:, 0], t[:, 1], t[:, 2], t[:, 3], t[:, 4], t[:, 5], LIN, EPS),
+                rows)
+    # gradients of a function O(1) in the data's units: compare relative to the largest entry
+    err = np.abs(got - ref) / np.abs(ref).max(1, keepdims=True)
+    assert err.max() <= 1e-11, err.max()
+    rows = _data(32)
+    rows[:, 5] = 10.0 ** np.random.default_rng(33).uniform(-3, -1, len(rows))
+    got = _run("L", "d", rows)
+    ref = _grad(lambda t: o.limit_derivative(t[:, 0], t[:, 1], t[:, 2], t[:, 3], t[:, 4],
+                                             t[:, 5].detach(), LIM, EPS), rows)[:, :5]
+    err = np.abs(got - ref) / np.abs(ref).max(1, keepdims=True)
+    assert err.max() <= 1e-11, err.max()
+
+
+def test_point_flux_adjoint_matches_autograd():
+    g = np.random.default_rng(34)
+    n = 2000
+    U = _states(g, n)
+    D = g.standard_normal((n, 8)) * np.abs(U).max(1, keepdims=True)
+    gout = g.standard_normal((n, 12))
+    rows = np.concatenate([U, D, gout], 1)
+    got = _run("P", "d", rows)
+    t = torch.as_tensor(rows[:, :12], dtype=torch.float64).clone().requires_grad_(True)
+    eu = o.Euler(_Prob())
+    out = torch.cat([eu.flux(t[:, :4], 0), eu.jvp(t[:, :4], t[:, 4:8], 0),
+                     eu.jvp(t[:, :4], t[:, 8:], 0)], 1)
+    (out * torch.as_tensor(gout)).sum().backward()
+    ref = t.grad.numpy()
+    err = np.abs(got - ref) / np.abs(ref).max(1, keepdims=True)
+    assert err.max() <= 1e-11, err.max()
