@@ -186,16 +186,18 @@ def cpu_baseline(n: int = 1024, strip: int = 1024, c2_steps: int = 1000):
                                        f"{dt_c2:.1f} s"}}
 
 
-def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
+def run_gpu(n: int, dtype_name: str, steps: int, warmup: int, ny: int = 0):
+    """The four-quadrant workload on an n x n grid (n x ny when ny is given)."""
     import torch
 
     import hweno_inputs as hi
     import paper_2207_05258_amd as h
     dtype = torch.float64 if dtype_name == "f64" else torch.float32
-    w = hi.euler2d_quadrants(n, n, 0)
+    ny = ny or n
+    w = hi.euler2d_quadrants(n, ny, 0)
     S = torch.as_tensor(w.S).to(dtype).cuda().contiguous()
     del w
-    prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=dtype, dx=1.0 / n, dy=1.0 / n,
+    prob = h.Problem(dim=2, nx=n, ny=ny, physics="euler", dtype=dtype, dx=1.0 / n, dy=1.0 / ny,
                      bc_x=h.OUTFLOW, bc_y=h.OUTFLOW)
     st = h.Stepper(prob)
     st.steps(S, warmup)
@@ -215,7 +217,7 @@ def run_gpu(n: int, dtype_name: str, steps: int, warmup: int):
     ev_ms = e0.elapsed_time(e1)
     status = st.status
     ok = status == 0 and bool(torch.isfinite(S).all())
-    cells = n * n
+    cells = n * ny
     rate = cells * 3 * steps / wall
     per_launch_s = stage_ms / 1e3 / max(launches, 1)
     flops = FLOP_PER_CELL_STAGE * cells
@@ -484,6 +486,8 @@ def main():
     ap.add_argument("--cpu-c2-steps", type=int, default=1000,
                     help="steps of the 1D Euler N = 4000 run timed on one thread")
     ap.add_argument("--no-1024", action="store_true", help="skip the 1024^2 rows")
+    ap.add_argument("--no-shard", action="store_true",
+                    help="skip the 4096x512 rows (one GPU's share of 4096^2 in 8 slabs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched-instances run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint rollout run")
     ap.add_argument("--no-small", action="store_true",
@@ -575,6 +579,24 @@ def main():
                                   "status": r["status"]}
         print(f"# 1024^2: f64 {rows_1024['f64']['value']:.4e}, f32 {rows_1024['f32']['value']:.4e} "
               "cell-stage/s", file=sys.stderr, flush=True)
+
+    # one GPU's share of the 4096^2 grid split into eight slabs (section "more than
+    # one GPU" of the design notes): the stage kernel at the shard's own shape,
+    # its halo rows read from the local buffer; the exchange it would add per
+    # stage is 2 sides x 2 rows x 4096 x 12 fields, priced at one xGMI link
+    shard = None
+    if not args.no_shard and args.n == 4096:
+        shard = {"shape": "4096x512", "of": "4096x4096 in 8 slabs",
+                 "halo_bytes_per_stage": {}, "halo_us_per_stage_at_153GBps": {}}
+        for dt_name in ("f64", "f32"):
+            r = run_gpu(4096, dt_name, args.steps, args.warmup, ny=512)
+            shard[dt_name] = {"value": r["rate"], "ms_per_step": r["ms_per_step"],
+                              "stage_ms_avg": r["stage_ms_avg"], "status": r["status"]}
+            hb = 2 * 2 * 4096 * 12 * (8 if dt_name == "f64" else 4)
+            shard["halo_bytes_per_stage"][dt_name] = hb
+            shard["halo_us_per_stage_at_153GBps"][dt_name] = round(hb / 153e9 * 1e6, 2)
+        print(f"# 8-way shard 4096x512: f64 {shard['f64']['value']:.4e}, f32 "
+              f"{shard['f32']['value']:.4e} cell-stage/s", file=sys.stderr, flush=True)
 
     batched = None
     if not args.no_batched:
@@ -678,6 +700,7 @@ def main():
                          "figures, without numbers or stated hardware",
         "variant": variant,
         "c3_1024": rows_1024,
+        "shard_8way": shard,
         "batched": batched,
         "adjoint": adjoint,
         "small_grid": small,
