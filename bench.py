@@ -465,8 +465,8 @@ def summarize_trace(root: str, match: str = "k_stage<", last: int = 0) -> str:
                     f"first of them on: {busy / 1e6:.4f} ms.",
                 f"Launch shape: grid {col('Grid_Size', 'Grid_Size_X')} work-items in workgroups of "
                 f"{col('Workgroup_Size', 'Workgroup_Size_X')}; LDS {col('LDS_Block_Size', 'Lds_Size')} B "
-                f"per workgroup, scratch {col('Scratch_Size')} B per lane; VGPRs "
-                f"{col('VGPR_Count', 'Arch_VGPR_Count')}."]
+                f"per workgroup, scratch {col('Scratch_Size')} B per lane; the trace's VGPR "
+                f"count field {col('VGPR_Count', 'Arch_VGPR_Count')}."]
     return "\n".join(out)
 
 
