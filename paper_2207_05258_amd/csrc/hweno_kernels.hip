@@ -1089,7 +1089,8 @@ constexpr int cmax(int x, int y) { return x > y ? x : y; }
 // handed over point by point: at each emit every lane writes the values for
 // one stencil point (or one group of points) into its own column of a small
 // LDS buffer, and after a barrier the owner of each output entry adds the
-// column that points at it to its accumulators, which live in registers.
+// column that points at it to its accumulators, one LDS slot per field and entry
+// (held in registers they made the kernel spill).
 // No atomics, and the buffer holds one point's contributions instead of a
 // whole stencil's, so several workgroups fit on a compute unit.  The barriers
 // also keep the compiler from holding the staged stencil in registers across
