@@ -311,3 +311,46 @@ def test_rollout_fp32_close_to_fp64():
         _loss(SN, P.to_gpu(target, dtype), base.dx, base.dy).backward()
         grads[dtype] = X.grad[:4].double()
     assert rel_err(grads[torch.float32], grads[torch.float64]) < 1e-3
+
+
+def test_rollout_at_full_size_512_200_steps():
+    """The adjoint configuration as the bench times it: 512^2 2D Euler, 200 steps, a
+    checkpoint every 20, loss = L2 mismatch of the final density.  The FP64 gradient
+    agrees with central differences of the replayed FP64 rollout along random
+    directions to 1e-6 (measured: 2e-10 to 3e-9 at eps = 1e-5); the FP32 gradient
+    is within 1e-3 of the FP64 one, relative to its largest entry (measured: 6.5e-5);
+    and in FP32 keeping every step's states gives bitwise the checkpointed gradient."""
+    base, target = hi.adjoint_pair(512, 0)
+    announce("rollout 512^2, 200 steps, checkpoint every 20")
+    grads = {}
+    for dtype in (torch.float64, torch.float32):
+        prob = P.gpu_problem(base, dtype)
+        X = P.to_gpu(base, dtype).requires_grad_(True)
+        SN = h.Rollout.apply(X, prob, 200, 20, None)
+        if dtype == torch.float64:
+            tapes = h.Rollout.last_tapes.clone()
+        _loss(SN, P.to_gpu(target, dtype), base.dx, base.dy).backward()
+        grads[dtype] = X.grad.detach().clone()
+    assert rel_err(grads[torch.float32], grads[torch.float64]) < 1e-3, \
+        rel_err(grads[torch.float32], grads[torch.float64])
+    prob = P.gpu_problem(base, torch.float64)
+    U0 = P.to_gpu(base, torch.float64)
+    tgt = P.to_gpu(target, torch.float64)
+    g = torch.Generator().manual_seed(9)
+    eps = 1e-5
+    for k in range(2):
+        d = torch.randn(U0.shape, dtype=torch.float64, generator=g).cuda()
+        if k == 0:
+            d[4:] = 0.0     # the solution fields only
+        jp = _loss(h.rollout_replay(U0 + eps * d, prob, tapes), tgt, base.dx, base.dy)
+        jm = _loss(h.rollout_replay(U0 - eps * d, prob, tapes), tgt, base.dx, base.dy)
+        fd = float((jp - jm) / (2 * eps))
+        an = float((grads[torch.float64] * d).sum())
+        print(f"[512^2 rollout] direction {k}: adjoint {an:.12e} central differences {fd:.12e}",
+              flush=True)
+        assert abs(an - fd) <= 1e-6 * abs(fd), (k, an, fd)
+    prob = P.gpu_problem(base, torch.float32)
+    X = P.to_gpu(base, torch.float32).requires_grad_(True)
+    SN = h.Rollout.apply(X, prob, 200, 0, None)
+    _loss(SN, P.to_gpu(target, torch.float32), base.dx, base.dy).backward()
+    assert torch.equal(X.grad, grads[torch.float32])
