@@ -4,6 +4,7 @@ Every case feeds the same seeded input to both sides (FP32 cases give the
 oracle the FP32-rounded values) and compares element by element in the norms
 of tests/parity.py: FP64 within 1e-12, FP32 within 1e-5.
 """
+import math
 import os
 import sys
 
@@ -563,6 +564,63 @@ def test_whole_1024_grid_two_steps_with_the_oracles_own_speeds(dtype):
     errs = P.step_errors(Sg, S, w)
     print("whole 1024^2, two steps:", {kk: f"{v:.2e}" for kk, v in errs.items()}, flush=True)
     P.assert_within(errs, P.TOL[dtype], f"whole {n}^2 grid, two steps")
+
+
+def test_linadv_200_whole_run_matches_the_oracle():
+    """The 1D linear advection configuration whole: N = 200, u0 = 0.5 + sin(pi x) with
+    its derivative on periodic [0, 2], CFL 0.6, device time steps, multi-step calls with
+    the last step clipped at T = 2, against the oracle's own run: the same 334 steps
+    and every cell within 1e-12 (a linear, stable problem: rounding does not grow)."""
+    w = hi.scalar_sine_1d(200, "linadv")
+    announce("linadv 200 whole run to T = 2")
+    S = P.to_gpu(w, torch.float64)
+    st = h.Stepper(P.gpu_problem(w, torch.float64))
+    while st.t < 2.0 * (1 - 1e-13):
+        st.steps(S, 128, t_end=2.0)
+        assert st.status & ~h.hweno.ST_SKIPPED == 0, st.status
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        ref, steps = o.run(P.exact_input(P.to_gpu(w, torch.float64)), P.oracle_problem(w), 2.0)
+    finally:
+        torch.set_num_threads(threads)
+    assert st.t == pytest.approx(2.0, rel=1e-13)
+    assert int(st.ctrl[9]) == steps == 334, (int(st.ctrl[9]), steps)
+    errs = P.step_errors(S, ref, w)
+    print("[linadv 200 to T = 2]", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    P.assert_within(errs, 1e-12, "linadv 200 whole run")
+
+
+def test_euler1d_4000_smooth_whole_run_matches_the_oracle_and_the_exact_wave():
+    """The smooth case of the 1D Euler configuration: rho = 1 + 0.2 sin(pi x), u = 1,
+    p = 1 on periodic [0, 2], N = 4000, to T = 0.2 with device time steps and the last
+    step clipped.  A density wave carried at u = 1: the GPU run takes the oracle's
+    steps (1549) and agrees with its run to 1e-12 in every cell (measured: 1.9e-13), and
+    the density is the exact translate 1 + 0.2 sin(pi (x - T)) to 1e-11 (measured:
+    4.7e-13)."""
+    w = hi.euler1d_smooth(4000)
+    T = 0.2
+    announce("euler1d 4000 smooth whole run to T = 0.2")
+    S = P.to_gpu(w, torch.float64)
+    st = h.Stepper(P.gpu_problem(w, torch.float64))
+    while st.t < T * (1 - 1e-13):
+        st.steps(S, 1024, t_end=T)
+        assert st.status & ~h.hweno.ST_SKIPPED == 0, st.status
+    threads = torch.get_num_threads()
+    torch.set_num_threads(1)
+    try:
+        ref, steps = o.run(P.exact_input(P.to_gpu(w, torch.float64)), P.oracle_problem(w), T)
+    finally:
+        torch.set_num_threads(threads)
+    assert int(st.ctrl[9]) == steps, (int(st.ctrl[9]), steps)
+    errs = P.step_errors(S, ref, w)
+    x = (torch.arange(4000, dtype=torch.float64) + 0.5) * w.dx
+    exact = 1.0 + 0.2 * torch.sin(math.pi * (x - T))
+    e_exact = float((S[0, 0].cpu() - exact).abs().max())
+    print(f"[euler1d 4000 smooth to T] {steps} steps; oracle", {k: f"{v:.2e}" for k, v in errs.items()},
+          f"exact density {e_exact:.2e}", flush=True)
+    P.assert_within(errs, 1e-12, "euler1d 4000 smooth whole run")
+    assert e_exact < 1e-11, e_exact
 
 
 def _golden_euler1d_4000():
