@@ -51,6 +51,26 @@ def test_euler_jvp_is_derivative_of_flux(dim, d):
 
 
 @pytest.mark.parametrize("dim,d", [(1, 0), (2, 0), (2, 1)])
+def test_euler_speed_is_the_spectral_radius_of_the_flux_jacobian(dim, d):
+    """The Lax-Friedrichs speed of a state (Section 2.1: the largest |f'(u)|, for a system
+    the spectral radius of dF_d/dU) equals the largest |eigenvalue| of the flux's Jacobian
+    taken by automatic differentiation and a general eigenvalue solver."""
+    g = torch.Generator().manual_seed(7)
+    prob = o.Problem(dim=dim, physics="euler")
+    phys = o.Euler(prob)
+    n = 40
+    rho = torch.rand(n, generator=g, dtype=torch.float64) * 2 + 0.1
+    vel = torch.rand(n, dim, generator=g, dtype=torch.float64) * 4 - 2
+    p = torch.rand(n, generator=g, dtype=torch.float64) * 3 + 0.1
+    E = p / 0.4 + 0.5 * rho * (vel ** 2).sum(-1)
+    U = torch.cat([rho[:, None], rho[:, None] * vel, E[:, None]], -1)
+    for q in range(n):
+        J = torch.autograd.functional.jacobian(lambda X: phys.flux(X[None], d)[0], U[q])
+        radius = torch.linalg.eigvals(J).abs().max()
+        assert abs(float(phys.speed(U[q:q + 1], d)[0]) - float(radius)) <= 1e-12 * float(radius)
+
+
+@pytest.mark.parametrize("dim,d", [(1, 0), (2, 0), (2, 1)])
 def test_euler_eigensystem_and_roe_property(dim, d):
     """R diag(lambda) R^-1 = A(U_roe) and A(U_roe)(U_R - U_L) = F_R - F_L."""
     g = torch.Generator().manual_seed(6)
