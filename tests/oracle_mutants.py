@@ -101,6 +101,17 @@ MUTANTS = [
     ("outflow_second_cell", "return A.index_select(axis, torch.clamp(k, 0, n - 1))",
      "return A.index_select(axis, torch.clamp(k, 1, n - 2))", 1),
     ("reflect_off_by_one", "mirror = torch.where(k < 0, -1 - k,", "mirror = torch.where(k < 0, -k,", 1),
+    ("wall_parities_not_flipped", "return pu, [-q for q in pu], pu", "return pu, pu, pu", 1),
+    ("wall_normal_momentum", "pu[1 + d] = -1.0", "pu[2 - d] = -1.0", 1),
+    ("edge_split_depth_ignored", "split = e.split[0] + e.split[1] * t + e.split[2] * depth",
+     "split = e.split[0] + e.split[1] * t", 1),
+    ("edge_segments_exchanged", "seg1 = pos >= split", "seg1 = pos < split", 1),
+    ("inflow_derivatives_kept", "val = torch.zeros(A.shape[0], 1, 1, dtype=A.dtype)",
+     "val = torch.ones(A.shape[0], 1, 1, dtype=A.dtype)", 1),
+    ("obstacle_front_mirror_off_by_one", "src_i = jj, (2 * i_s - 1 - ii)", "src_i = jj, (2 * i_s - ii)", 1),
+    ("obstacle_solid_rows", "m[:j_s, i_s:] = True", "m[:j_s + 1, i_s:] = True", 1),
+    ("char_limiter_not_projected_back", "return (R @ z.movedim(0, -1).unsqueeze(-1)).squeeze(-1).movedim(-1, 0)",
+     "return z", 1),
     ("speed_without_sound", "return (u if d == 0 else v).abs() + c", "return (u if d == 0 else v).abs()", 1),
     ("cfl_2d_max", "return prob.cfl / (alpha[0] / prob.dx + alpha[1] / prob.dy)",
      "return prob.cfl / max(alpha[0] / prob.dx, alpha[1] / prob.dy)", 1),
