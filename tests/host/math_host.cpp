@@ -9,6 +9,8 @@
 //   R  fm f0 fp Hm H0 Hp           hw_plus_vjp with a unit adjoint: the gradient
 //   L  um u0 up vm vp h            limit1_vjp with a unit adjoint: the gradient
 //   P  U Dn Dt gF gA gB (4 each)   point_fluxes_vjp: gU, gDn, gDt
+//   c  um u0 up vm vp (4 each) h    2D Euler characteristic limiter (normal frame)
+//   C  um u0 up vm vp (4 each) h g  its reverse with the adjoint g (4): gum gu0 gup gvm gvp
 // and prints its results on one line, 17 significant digits each.
 #include <cstdio>
 #include <cstdlib>
@@ -69,6 +71,23 @@ static void run(char op, const double* v) {
     for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(gDn[c]));
     for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(gDt[c]));
     std::printf("\n");
+  } else if (op == 'c' || op == 'C') {
+    T st[5][4], out[4], g[5][4] = {};
+    for (int q = 0; q < 5; ++q)
+      for (int c = 0; c < 4; ++c) st[q][c] = T(v[4 * q + c]);
+    const T h = T(v[20]);
+    if (op == 'c') {
+      limit_char<T, 4>(st[0], st[1], st[2], st[3], st[4], h, T(1) / h, weights<T>(3), T(gam - 1.0), out);
+      for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(out[c]));
+    } else {
+      T gout[4];
+      for (int c = 0; c < 4; ++c) gout[c] = T(v[21 + c]);
+      limit_char_vjp<T, 4>(st[0], st[1], st[2], st[3], st[4], h, T(1) / h, weights<T>(3),
+                           T(gam - 1.0), gout, g[0], g[1], g[2], g[3], g[4]);
+      for (int q = 0; q < 5; ++q)
+        for (int c = 0; c < 4; ++c) std::printf("%.17g ", double(g[q][c]));
+    }
+    std::printf("\n");
   } else {
     T UL[4], UR[4], x[4], w[4], y[4];
     for (int c = 0; c < 4; ++c) UL[c] = T(v[c]), UR[c] = T(v[4 + c]), x[c] = T(v[8 + c]);
@@ -92,8 +111,9 @@ int main(int argc, char** argv) {
   gam = std::atof(argv[8]);
   char op, prec;
   while (std::scanf(" %c %c", &op, &prec) == 2) {
-    const int n = (op == 'r' || op == 'l' || op == 'R' || op == 'L') ? 6 : op == 'P' ? 24 : 12;
-    double v[24];
+    const int n = (op == 'r' || op == 'l' || op == 'R' || op == 'L') ? 6
+                  : op == 'P' ? 24 : op == 'c' ? 21 : op == 'C' ? 25 : 12;
+    double v[25];
     for (int i = 0; i < n; ++i)
       if (std::scanf("%lf", &v[i]) != 1) return 3;
     if (prec == 'd')

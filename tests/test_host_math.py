@@ -9,7 +9,9 @@ point fluxes with their chain-rule products (eq. EQ3) and the closed-form
 characteristic projection (Remarks 2.1/2.2: L x solves R w = x for the oracle's
 right eigenvectors at the Roe average, and R L x = x); and the hand-written
 reverse-mode derivatives of the reconstruction, the limiter and the point fluxes
-(hweno_adjoint.h) against torch autograd through the oracle's formulas.
+(hweno_adjoint.h) against torch autograd through the oracle's formulas; and the
+characteristic limiter variant and its reverse against the oracle's (one periodic
+3-cell row per stencil).
 Bounds, relative to the data's scale (for the point fluxes the largest
 component of each output vector, for the projection |x| times the condition
 number of R): FP64 1e-13, FP32 2e-6 (5e-6 for the point fluxes: a few FP32 ulps
@@ -216,3 +218,76 @@ def test_point_flux_adjoint_matches_autograd():
     ref = t.grad.numpy()
     err = np.abs(got - ref) / np.abs(ref).max(1, keepdims=True)
     assert err.max() <= 1e-11, err.max()
+
+
+H_CHAR = 1.0 / 64.0
+
+
+def _char_rows(seed, n=1500):
+    """Characteristic-limiter stencils of 2D Euler: three admissible states (the
+    neighbours close to the centre in half the rows, independent in the others)
+    and the two neighbours' x-derivatives, about |U| / h in size."""
+    g = np.random.default_rng(seed)
+    u0 = _states(g, n)
+    um, up = _states(g, n), _states(g, n)
+    near = g.random(n) < 0.5
+    for a in (um, up):
+        a[near] = u0[near] * (1.0 + 0.02 * g.uniform(-1, 1, (int(near.sum()), 1)))
+    sc = np.abs(u0).max(1, keepdims=True) / H_CHAR
+    vm = g.standard_normal((n, 4)) * sc * 0.1
+    vp = g.standard_normal((n, 4)) * sc * 0.1
+    return np.concatenate([um, u0, up, vm, vp, np.full((n, 1), H_CHAR)], 1)
+
+
+def _oracle_char_grid(rows):
+    """One periodic 3-cell row per stencil; cell 1's x-limiter reads exactly it."""
+    n = len(rows)
+    S = torch.zeros(12, n, 3, dtype=torch.float64)
+    t = torch.as_tensor(rows, dtype=torch.float64)
+    for k in range(3):
+        S[:4, :, k] = t[:, 4 * k:4 * k + 4].T
+    S[4:8, :, 0] = t[:, 12:16].T
+    S[4:8, :, 2] = t[:, 16:20].T
+    prob = o.Problem(dim=2, physics="euler", dx=H_CHAR, dy=H_CHAR, lim_w=LIM, eps=EPS,
+                     gamma_gas=GAMMA, limiter_characteristic=True)
+    return S, prob
+
+
+@pytest.mark.parametrize("prec,tol", [("d", 1e-13), ("f", 2e-6)])
+def test_characteristic_limiter_matches_the_oracle(prec, tol):
+    """The characteristic limiter variant (each stencil vector projected on the left
+    eigenvectors of the cell's own state, the scalar Section 2.2 limiter per field,
+    back with the right eigenvectors) against the oracle's, relative to |U| / h times
+    the condition number of the cell's eigenvectors."""
+    rows = _char_rows(41)
+    if prec == "f":
+        rows = rows.astype(np.float32).astype(np.float64)
+    got = _run("c", prec, rows)
+    S, prob = _oracle_char_grid(rows)
+    ref = o.limited_derivatives(S, prob)[:4, :, 1].T.numpy()
+    u0 = torch.as_tensor(rows[:, 4:8])
+    cond = torch.linalg.cond(o.Euler(prob).right_eigenvectors(u0, u0, 0)).numpy()
+    scale = (np.abs(rows[:, :12]).max(1) / H_CHAR + np.abs(rows[:, 12:20]).max(1)) * cond
+    err = np.abs(got - ref) / scale[:, None]
+    assert err.max() <= tol, (err.max(), np.unravel_index(err.argmax(), err.shape))
+
+
+def test_characteristic_limiter_adjoint_matches_autograd():
+    """The reverse of the characteristic limiter (through the cell's eigen-system, the
+    projections and the scalar limiters) against torch autograd through the oracle,
+    relative to the largest entry times the condition number of the cell's right
+    eigenvectors (the oracle inverts them numerically; where the sound speed is small
+    the two sides differ by up to 1e-9 of the largest entry, 3e-12 once scaled)."""
+    rows = _char_rows(42, 800)
+    gout = np.random.default_rng(43).standard_normal((len(rows), 4))
+    got = _run("C", "d", np.concatenate([rows, gout], 1))
+    S, prob = _oracle_char_grid(rows)
+    X = S.clone().requires_grad_(True)
+    (o.limited_derivatives(X, prob)[:4, :, 1] * torch.as_tensor(gout).T).sum().backward()
+    G = X.grad
+    ref = np.concatenate([G[:4, :, 0].T, G[:4, :, 1].T, G[:4, :, 2].T, G[4:8, :, 0].T,
+                          G[4:8, :, 2].T], 1)
+    u0 = torch.as_tensor(rows[:, 4:8])
+    cond = torch.linalg.cond(o.Euler(prob).right_eigenvectors(u0, u0, 0)).numpy()
+    err = np.abs(got - ref) / (np.abs(ref).max(1, keepdims=True) * cond[:, None])
+    assert err.max() <= 1e-11, (err.max(), np.unravel_index(err.argmax(), err.shape))
