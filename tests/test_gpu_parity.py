@@ -623,10 +623,12 @@ def test_euler1d_4000_smooth_whole_run_matches_the_oracle_and_the_exact_wave():
     assert e_exact < 1e-11, e_exact
 
 
-def _golden_euler1d_4000():
-    """The oracle's run of this workload to T = 0.2, written by
-    tests/golden/make_euler1d_4000.py: its step count and every 8th cell."""
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "euler1d_4000_T0.2.txt")
+def _golden_euler1d_4000(char=False):
+    """The oracle's run of this workload to T = 0.2 (limiter component-wise, or in
+    characteristic fields), written by tests/golden/make_euler1d_4000.py: its step count
+    and every 8th cell."""
+    name = "euler1d_4000_char_T0.2.txt" if char else "euler1d_4000_T0.2.txt"
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
     rows, steps = [], None
     with open(path) as fh:
         for ln in fh:
@@ -640,19 +642,21 @@ def _golden_euler1d_4000():
     return steps, t[:, 0].long(), t[:, 1:].T.contiguous()
 
 
-def test_euler1d_4000_whole_run_matches_the_oracle():
+@pytest.mark.parametrize("char", [False, True], ids=["componentwise", "characteristic"])
+def test_euler1d_4000_whole_run_matches_the_oracle(char):
     """The 1D Euler configuration whole: N = 4000 periodic piecewise-constant data in
     FP64, device speeds and time steps, multi-step calls of up to 1 024 steps, the last
-    step clipped at T = 0.2.  After 300 steps every cell agrees with the oracle to 1e-12.
-    Later in this run the scheme amplifies rounding: a perturbation of the input by
-    about one ulp grows to about 1e-13 by step 1 000, 1e-9 by step 3 000 and 1e-4 at
-    T, on the GPU and in the oracle alike; so at T the test asserts the oracle's
-    number of steps and, on every 8th cell of the oracle's stored run, a difference
-    within ten times that floor, measured here with two such perturbations."""
+    step clipped at T = 0.2, with the limiter component by component (the default
+    reading) and in characteristic fields.  After 300 steps every cell agrees with the
+    oracle to 1e-12.  Later in this run the scheme amplifies rounding: a perturbation of
+    the input by about one ulp grows to about 1e-13 by step 1 000, 1e-9 by step 3 000
+    and 1e-4 at T, on the GPU and in the oracle alike; so at T the test asserts the
+    oracle's number of steps and, on every 8th cell of the oracle's stored run, a
+    difference within ten times that floor, measured here with two such perturbations."""
     w = hi.euler1d_piecewise(4000, 0)
     T = 0.2
-    announce("euler1d 4000 whole run to T = 0.2")
-    prob = P.gpu_problem(w, torch.float64)
+    announce("euler1d 4000 whole run to T = 0.2", "characteristic limiter" if char else "")
+    prob = P.gpu_problem(w, torch.float64, limiter_characteristic=char)
     base = P.to_gpu(w, torch.float64)
 
     def run(S, n=None, t_end=None):
@@ -670,7 +674,7 @@ def test_euler1d_4000_whole_run_matches_the_oracle():
     threads = torch.get_num_threads()
     torch.set_num_threads(1)   # 4000-cell tensors: thread start-up would dominate
     try:
-        S, op = P.exact_input(base), P.oracle_problem(w)
+        S, op = P.exact_input(base), P.oracle_problem(w, limiter_characteristic=char)
         for _ in range(300):
             S, _, _ = o.rk3_step(S, op)
     finally:
@@ -679,7 +683,7 @@ def test_euler1d_4000_whole_run_matches_the_oracle():
     print("[euler1d 4000, 300 steps]", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
     P.assert_within(errs, 1e-12, "euler1d 4000, 300 steps")
 
-    steps, cells, ref = _golden_euler1d_4000()
+    steps, cells, ref = _golden_euler1d_4000(char)
     A = base.clone()
     st = run(A, t_end=T)
     assert st.t == pytest.approx(T, rel=1e-13)
