@@ -455,6 +455,7 @@ def summarize_trace(root: str, match: str = "k_stage<", last: int = 0) -> str:
         dur = [int(recs[i]["End_Timestamp"]) - int(recs[i]["Start_Timestamp"]) for i in sel]
         tail = recs[sel[0]:]
         busy = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in tail)
+        span = max(int(r["End_Timestamp"]) for r in tail) - int(tail[0]["Start_Timestamp"])
         r0 = recs[sel[0]]
 
         def col(*names):
@@ -462,7 +463,8 @@ def summarize_trace(root: str, match: str = "k_stage<", last: int = 0) -> str:
         out += ["", f"Last {last} dispatches matching `{match}`: average duration "
                     f"{sum(dur) / len(dur) / 1e6:.4f} ms (min {min(dur) / 1e6:.4f}, max "
                     f"{max(dur) / 1e6:.4f}); GPU kernel time of all {len(tail)} dispatches from the "
-                    f"first of them on: {busy / 1e6:.4f} ms.",
+                    f"first of them on: {busy / 1e6:.4f} ms, over a span of {span / 1e6:.4f} ms "
+                    f"from the first start to the last end.",
                 f"Launch shape: grid {col('Grid_Size', 'Grid_Size_X')} work-items in workgroups of "
                 f"{col('Workgroup_Size', 'Workgroup_Size_X')}; LDS {col('LDS_Block_Size', 'Lds_Size')} B "
                 f"per workgroup, scratch {col('Scratch_Size')} B per lane; the trace's VGPR "
@@ -494,7 +496,7 @@ def main():
                     help="skip the small-grid eager-versus-graph run")
     ap.add_argument("--no-double-mach", action="store_true",
                     help="skip the double Mach reflection and forward-step runs")
-    ap.add_argument("--only", choices=["batched", "adjoint", "double_mach", "forward_step"],
+    ap.add_argument("--only", choices=["batched", "adjoint", "double_mach", "forward_step", "small"],
                     default=None,
                     help="run only this part and print its JSON object (for profiling)")
     ap.add_argument("--adjoint-steps", type=int, default=200)
@@ -547,6 +549,9 @@ def main():
         return
     if args.only == "adjoint":
         print(json.dumps(run_adjoint(steps=args.adjoint_steps)), flush=True)
+        return
+    if args.only == "small":
+        print(json.dumps(run_small()), flush=True)
         return
     if args.only == "double_mach":
         print(json.dumps(run_double_mach(max_steps=args.edge_steps)), flush=True)

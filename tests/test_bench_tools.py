@@ -62,7 +62,7 @@ def test_summarize_trace_averages_the_last_matching_dispatches(tmp_path):
     m = re.search(r"average duration ([0-9.]+) ms \(min ([0-9.]+), max ([0-9.]+)\)", out)
     assert m and [float(x) for x in m.groups()] == [0.25, 0.2, 0.3]
     # the two last stage dispatches and the k_finish after them: 0.2 + 0.3 + 0.01 ms
-    assert "all 3 dispatches from the first of them on: 0.5100 ms" in out
+    assert "all 3 dispatches from the first of them on: 0.5100 ms, over a span of 2.4100 ms" in out
     assert "grid 4096 work-items in workgroups of 256; LDS 31744 B" in out
     assert "scratch 12 B per lane" in out  # the first of the averaged dispatches
     # fewer matching dispatches than asked for: only the kernel_stats table
