@@ -48,27 +48,28 @@ FIELDS_PER_CELL_STAGE = 104.0 / 3.0
 FIELDS_PER_CELL_STAGE_SCOPE = 32.0
 
 # HBM traffic of one stage-kernel launch from rocprofv3 --pmc FETCH_SIZE /
-# WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the hash of the built
-# device code it was measured on (kernel_sha; other builds report null).
+# WRITE_SIZE, scaled by a copy-kernel calibration, keyed by the hash of the 2D
+# Euler stage kernels' machine code it was measured on (kernel_sha; other code
+# reports null).
 MEASURED_TRAFFIC = {
     # profiles/k_stage_euler2d_4096_f64_hbm_bytes.md, profiles/k_stage_euler2d_4096_f32_hbm_bytes.md
-    ("2b7b55f18c2286ad", "f64", 4096): 5.0817e+09,
-    ("2b7b55f18c2286ad", "f32", 4096): 2.6212e+09,
+    ("cd5b3fb9f97aabc9", "f64", 4096): 5.0817e+09,
+    ("cd5b3fb9f97aabc9", "f32", 4096): 2.6212e+09,
 }
 
 # VALU wave-instructions issued by one stage-kernel launch (rocprofv3 --pmc
 # SQ_INSTS_VALU, average of the three stages), keyed like MEASURED_TRAFFIC.
 MEASURED_VALU_WAVE_INSTR = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("2b7b55f18c2286ad", "f64", 4096): 8.950e8,
-    ("2b7b55f18c2286ad", "f32", 4096): 8.624e8,
+    ("cd5b3fb9f97aabc9", "f64", 4096): 8.950e8,
+    ("cd5b3fb9f97aabc9", "f32", 4096): 8.624e8,
 }
 # Floating-point operations per FP64 cell-stage that the SQ counters of the same
 # device code count (SQ_INSTS_VALU_{ADD,MUL,TRANS}_F64 + 2 x FMA over cells x
 # stages), keyed like MEASURED_TRAFFIC.
 MEASURED_FLOP_PER_CELL_STAGE = {
     # profiles/k_stage_euler2d_4096_sq_counters.md
-    ("2b7b55f18c2286ad", "f64", 4096): 4393.0,
+    ("cd5b3fb9f97aabc9", "f64", 4096): 4393.0,
 }
 # VALU issue peak of the chip in lane-instructions/s: 256 CUs x 4 SIMDs x 2.4 GHz
 # x 16 lanes per cycle for FP64, x 32 for FP32 (the FP32 vector peak of 157.3
@@ -77,12 +78,18 @@ MEASURED_FLOP_PER_CELL_STAGE = {
 PEAK_VALU_LANE_INSTR = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9}
 
 
-def kernel_sha(prefix: str = "_ZN5hweno7k_stageI") -> str:
+# the fused stage kernels of 2D Euler, FP64 and FP32: the code the measured figures describe
+STAGE_2D_EULER = ("_ZN5hweno7k_stageIdLi2ELi2E", "_ZN5hweno7k_stageIfLi2ELi2E")
+
+
+def kernel_sha(prefix=STAGE_2D_EULER) -> str:
     """sha256[:16] of the machine code of the kernels whose mangled names start with
-    `prefix` (default: the fused stage kernels k_stage) in the gfx950 code object that
-    libhweno.so embeds.  It changes with those kernels' code and with nothing else, so a
-    traffic or counter figure measured for one build stays attached to exactly the code
-    it was measured on, across changes to other kernels."""
+    `prefix` (a string or a tuple of them; default: the 2D Euler fused stage kernels
+    k_stage in FP64 and FP32) in the gfx950 code object that libhweno.so embeds.  It
+    changes with those kernels' code and with nothing else, so a traffic or counter
+    figure measured for one build stays attached to exactly the code it was measured on,
+    across changes to other kernels."""
+    prefixes = (prefix,) if isinstance(prefix, str) else tuple(prefix)
     import struct
     from paper_2207_05258_amd import hweno as hw
     with open(hw.LIB_PATH, "rb") as fh:
@@ -121,7 +128,7 @@ def kernel_sha(prefix: str = "_ZN5hweno7k_stageI") -> str:
         st_name, st_info, _o, st_shndx, st_value, st_size = struct.unpack_from(
             "<IBBHQQ", code, symtab[4] + 24 * i)
         name = strtab[st_name:strtab.index(b"\0", st_name)]
-        if (st_info & 0xF) == 2 and name.startswith(prefix.encode()) and st_size > 0:
+        if (st_info & 0xF) == 2 and st_size > 0 and any(name.startswith(q.encode()) for q in prefixes):
             sec = secs[st_shndx][1]
             off = sec[4] + (st_value - sec[3])
             found.append((name, code[off:off + st_size]))

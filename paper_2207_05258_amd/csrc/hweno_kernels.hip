@@ -1882,10 +1882,12 @@ hweno_status launch_check(const char* what) {
 }
 
 // 2D tile: 16 x 15 cells on 256 threads gives 255 x-interfaces and 256
-// y-interfaces, i.e. one balanced pass per direction.
+// y-interfaces, i.e. one balanced pass per direction.  1D tile: 255 cells have
+// 256 interfaces, one per thread (with 256 cells the first wave took a second
+// pass for the 257th, doubling the stage's critical path on small grids).
 template <int DIM>
 struct Tile {
-  static constexpr int TX = (DIM == 2) ? 16 : 256;
+  static constexpr int TX = (DIM == 2) ? 16 : 255;
   static constexpr int TY = (DIM == 2) ? 15 : 1;
   static constexpr int NT = 256;
 };
