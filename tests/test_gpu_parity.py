@@ -753,6 +753,59 @@ def test_euler1d_4000_fp32_whole_run_tracks_the_oracle():
     assert bool((far <= len(cells) // 20).all()), far.tolist()
 
 
+def _golden_euler2d_1024():
+    """The oracle's 100-step run of the 1024^2 four-quadrant workload, written by
+    tests/golden/make_euler2d_1024.py: the time reached and six sampled rows."""
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "euler2d_1024_100steps.txt")
+    t, rows = None, []
+    with open(path) as fh:
+        for ln in fh:
+            if ln.startswith("#"):
+                continue
+            if ln.startswith("t "):
+                t = float(ln.split()[1])
+                continue
+            rows.append([float(x) for x in ln.split()])
+    d = torch.tensor(rows, dtype=torch.float64)
+    return t, d[:, 0].long(), d[:, 1].long(), d[:, 2:].T.contiguous()
+
+
+def test_euler2d_1024_100_steps_matches_the_oracle_run():
+    """The 2D Euler configuration at its smaller size as the bench runs it: 1024^2
+    four-quadrant data, outflow, FP64, 100 steps in one multi-step call with device speeds
+    and time steps, against the oracle's own 100-step run (stored by
+    tests/golden/make_euler2d_1024.py, half an hour on the CPU): the time reached to 1e-12
+    and, on six rows at every 16th column, every field within 1e-12 of its scale (max |.|
+    over the samples; measured: 3e-15 to 4e-14, at the level of the GPU run's own change
+    when its input is perturbed by about one ulp).  The same 100 steps in FP32: the time
+    within 1e-5 and the conserved fields within 1e-5 of the oracle in L1 over the samples
+    (measured: 0.9e-6 to 1.7e-6)."""
+    w = hi.euler2d_quadrants(1024, 1024, 0)
+    announce("euler2d 1024^2, 100 steps")
+    t_ref, jj, ii, ref = _golden_euler2d_1024()
+    jg, ig = jj.cuda(), ii.cuda()
+    A = P.to_gpu(w, torch.float64)
+    st = h.Stepper(P.gpu_problem(w, torch.float64))
+    st.steps(A, 100)
+    assert st.status == 0, st.status
+    assert st.t == pytest.approx(t_ref, rel=1e-12), (st.t, t_ref)
+    err = (A[:, jg, ig].cpu() - ref).abs().amax(1)
+    scale = ref.abs().amax(1).clamp_min(1e-300)
+    print("[euler2d 1024^2, 100 steps] |gpu - oracle| / scale",
+          [f"{v:.1e}" for v in (err / scale).tolist()], flush=True)
+    assert bool((err <= 1e-12 * scale).all()), (err / scale).tolist()
+
+    S32 = P.to_gpu(w, torch.float32)
+    st32 = h.Stepper(P.gpu_problem(w, torch.float32))
+    st32.steps(S32, 100)
+    assert st32.status == 0, st32.status
+    assert st32.t == pytest.approx(t_ref, rel=1e-5)
+    d = (S32[:, jg, ig].cpu().double() - ref).abs()[:4]
+    l1 = d.sum(1) / ref[:4].abs().sum(1)
+    print("[euler2d 1024^2, 100 steps, FP32] L1", [f"{v:.1e}" for v in l1.tolist()], flush=True)
+    assert bool((l1 <= 1e-5).all()), l1.tolist()
+
+
 def test_state_beyond_32_bit_element_indices():
     """16384^2 FP32 2D Euler: 12 fields of 2^28 cells are 3.2e9 elements (12.9 GB per
     state), so field offsets pass 2^31; windows at the domain's far corner, in the
