@@ -669,11 +669,13 @@ def test_euler1d_4000_whole_run_matches_the_oracle(char):
     FP64, device speeds and time steps, multi-step calls of up to 1 024 steps, the last
     step clipped at T = 0.2, with the limiter component by component (the default
     reading) and in characteristic fields.  After 300 steps every cell agrees with the
-    oracle to 1e-12.  Later in this run the scheme amplifies rounding: a perturbation of
-    the input by about one ulp grows to about 1e-13 by step 1 000, 1e-9 by step 3 000
-    and 1e-4 at T, on the GPU and in the oracle alike; so at T the test asserts the
-    oracle's number of steps and, on every 8th cell of the oracle's stored run, a
-    difference within ten times that floor, measured here with two such perturbations."""
+    oracle to 1e-12.  With the component-wise limiter the run then amplifies rounding: a
+    perturbation of the input by about one ulp grows to about 1e-13 by step 1 000, 1e-9
+    by step 3 000 and 1e-4 at T, on the GPU and in the oracle alike (with the
+    characteristic limiter it stays near 1e-13).  So at T the test asserts the oracle's
+    number of steps and, on every 8th cell of the oracle's stored run, a difference
+    within ten times that floor, measured here with two such perturbations, plus 1e-12
+    of the field's scale."""
     w = hi.euler1d_piecewise(4000, 0)
     T = 0.2
     announce("euler1d 4000 whole run to T = 0.2", "characteristic limiter" if char else "")
