@@ -808,6 +808,29 @@ def test_euler2d_1024_100_steps_matches_the_oracle_run():
     assert bool((l1 <= 1e-5).all()), l1.tolist()
 
 
+def test_euler2d_4096_100_steps_fp32_tracks_fp64():
+    """The 4096^2 configuration's whole run (100 steps in one multi-step call, as the bench
+    runs it) in both precisions: both stay admissible, reach the same time to 1e-5, and
+    the FP32 conserved fields are within 1e-6 of the FP64 ones in L1 over the grid
+    (measured: 0.7e-7 to 1.0e-7; the FP64 run equals the oracle at 1024^2 over the same
+    100 steps and on full-size windows)."""
+    w = hi.euler2d_quadrants(4096, 4096, 0)
+    announce("euler2d 4096^2, 100 steps, FP32 against FP64")
+    out, ts = {}, {}
+    for dtype in (torch.float64, torch.float32):
+        S = P.to_gpu(w, dtype)
+        st = h.Stepper(P.gpu_problem(w, dtype))
+        st.steps(S, 100)
+        assert st.status == 0, (dtype, st.status)
+        out[dtype], ts[dtype] = S[:4], st.t
+        del st
+    assert ts[torch.float32] == pytest.approx(ts[torch.float64], rel=1e-5)
+    a, b = out[torch.float32].double(), out[torch.float64]
+    l1 = [float((a[c] - b[c]).abs().sum() / b[c].abs().sum()) for c in range(4)]
+    print("[euler2d 4096^2, 100 steps] FP32 against FP64, L1", [f"{v:.1e}" for v in l1], flush=True)
+    assert max(l1) <= 1e-6, l1
+
+
 def test_state_beyond_32_bit_element_indices():
     """16384^2 FP32 2D Euler: 12 fields of 2^28 cells are 3.2e9 elements (12.9 GB per
     state), so field offsets pass 2^31; windows at the domain's far corner, in the
