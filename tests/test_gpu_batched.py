@@ -207,17 +207,23 @@ def test_autotune_through_the_c_abi():
 
 
 def test_batched_full_config_256_instances():
-    """The configured batch: 256 instances, sides ~ U{64..512}, FP32, autotuned."""
+    """The configured batch: 256 instances, sides ~ U{64..512}, FP32, autotuned, for the
+    configured 100 steps (each instance with its own time steps, the steps captured in a
+    graph and replayed as the bench runs them): every instance admissible, and eight
+    sampled instances bitwise equal to their own single-grid runs of 100 steps."""
     ws = hi.batched_instances(256, 0)
-    announce("256 instances")
+    announce("256 instances, 100 steps")
     states, grids, common = _batch(ws, torch.float32)
     b = h.BatchedStepper(states, grids, common)
     best, res = h.autotune_batched(b)
     assert best in res
-    b.step()
+    b.capture(steps=1)
+    for _ in range(100):
+        b.replay()
     torch.cuda.synchronize()
     assert all(s == 0 for s in b.statuses())
     rng = np.random.default_rng(1)
     for q in sorted(rng.choice(256, size=8, replace=False)):
-        ref, ctrls = _individual([ws[q]], torch.float32)
+        ref, ctrls = _individual([ws[q]], torch.float32, steps=100)
         assert torch.equal(states[q], ref[0]), q
+        assert torch.equal(b.ctrl(q)[:10], ctrls[0][:10]), q
