@@ -78,6 +78,15 @@ MEASURED_FLOP_PER_CELL_STAGE = {
 PEAK_VALU_LANE_INSTR = {"f64": 256 * 4 * 16 * 2.4e9, "f32": 256 * 4 * 32 * 2.4e9}
 
 
+# FP32 flops (SQ_INSTS_VALU_FLOPS_FP32 x 64) and VALU wave-instructions per launch of the
+# discrete-adjoint kernel at 512^2 (profiles/k_adjoint_euler2d_512_f32_sq_counters.md),
+# keyed by the hash of the k_adjoint kernels' machine code
+ADJOINT_PREFIX = "_ZN5hweno9k_adjointI"
+MEASURED_ADJOINT = {
+    ("2ec0cebfd3b86215", "f32", 512): {"flop": 5.712e7 * 64, "valu_wave_instr": 4.667e7},
+}
+
+
 # the fused stage kernels of 2D Euler, FP64 and FP32: the code the measured figures describe
 STAGE_2D_EULER = ("_ZN5hweno7k_stageIdLi2ELi2E", "_ZN5hweno7k_stageIfLi2ELi2E")
 
@@ -405,6 +414,50 @@ def run_adjoint(n: int = 512, steps: int = 200, ckpt: int = 0, dtype_name: str =
             "grad_finite": bool(torch.isfinite(g).all()), "grad_norm_U": float(g[:4].norm())}
 
 
+def adjoint_roofline(n: int = 512, steps: int = 20):
+    """The discrete-adjoint kernel against the FP32 peaks: `steps` forward steps keeping
+    their states, then their step adjoints newest first with the library's launch timer
+    on (HIP events around every k_adjoint launch on its stream; the calls run on this
+    thread, which the timer belongs to), and the counted flops and VALU instructions per
+    launch of the same machine code (null for other code)."""
+    import torch
+
+    import hweno_inputs as hi
+    import paper_2207_05258_amd as h
+    base, _ = hi.adjoint_pair(n, 0)
+    prob = h.Problem(dim=2, nx=n, ny=n, physics="euler", dtype=torch.float32, dx=base.dx, dy=base.dy)
+    S = torch.as_tensor(base.S).float().cuda().contiguous()
+    tapes = torch.zeros(steps, h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    inputs, steppers = [], []
+    for q in range(steps):
+        inputs.append(S.clone())
+        steppers.append(h.Stepper(prob))
+        steppers[-1].step(S, tape=tapes[q])
+    lam = torch.randn(S.shape, generator=torch.Generator(device="cuda").manual_seed(0), device="cuda")
+    ws = h.adjoint_workspace(prob)
+    h.step_adjoint(prob, inputs[-1], steppers[-1], tapes[-1], lam.clone(), ws)   # warm-up
+    torch.cuda.synchronize()
+    h.timing_begin()
+    for q in reversed(range(steps)):
+        h.step_adjoint(prob, inputs[q], steppers[q], tapes[q], lam, ws)
+    torch.cuda.synchronize()
+    launches, ms = h.timing_end()
+    sha = kernel_sha(ADJOINT_PREFIX)
+    m = MEASURED_ADJOINT.get((sha, "f32", n))
+    launch_ms = ms / launches if launches else None
+    out = {"kernel": "k_adjoint (transposed stage operator and limiter)", "grid": f"{n}x{n}",
+           "launches": launches, "launch_ms": None if launch_ms is None else round(launch_ms, 4),
+           "bound": "alu", "peak": 157.3, "unit": "TFLOP/s", "achieved": None, "frac": None,
+           "valu_issue": None, "kernel_sha": sha, "finite": bool(torch.isfinite(lam).all())}
+    if m is not None and launch_ms:
+        achieved = m["flop"] / (launch_ms * 1e-3) / 1e12
+        out.update(achieved=round(achieved, 3), frac=round(achieved / 157.3, 4),
+                   flop_per_launch=m["flop"],
+                   valu_issue=round(m["valu_wave_instr"] * 64 / (launch_ms * 1e-3)
+                                    / PEAK_VALU_LANE_INSTR["f32"], 4))
+    return out
+
+
 def summarize_pmc(root: str, match: str = "") -> str:
     """Markdown table of the mean value per dispatch of every rocprofv3 --pmc counter,
     per kernel, from the counter_collection.csv files under `root` (kernels whose
@@ -630,6 +683,7 @@ def main():
         adjoint["target_backward_over_forward"] = 3.0
         adjoint["meets_target"] = adjoint["backward_over_forward"] <= 3.0
         adjoint["every_step_kept"] = kept
+        adjoint["roofline"] = adjoint_roofline()
         print(f"# adjoint: backward/forward {adjoint['backward_over_forward']:.2f} (checkpoint every "
               f"20), {adjoint['every_step_kept']['backward_over_forward']:.2f} (every step kept)",
               file=sys.stderr, flush=True)

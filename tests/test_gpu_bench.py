@@ -48,6 +48,10 @@ def test_bench_reduced_run_prints_one_valid_json_line():
     assert d["adjoint"]["checkpoint_every"] == 20 and "meets_target" in d["adjoint"]
     assert d["adjoint"]["every_step_kept"]["grad_finite"]
     assert d["adjoint"]["grad_finite"] and d["small_grid"]["status"] == 0
+    # the adjoint kernel against its roofline: 20 taped steps' adjoints, 60 timed launches
+    ar = d["adjoint"]["roofline"]
+    assert ar["launches"] == 60 and ar["launch_ms"] > 0 and ar["finite"], ar
+    assert ar["frac"] is None or 0 < ar["frac"] < 1, ar
     # time-to-solution runs of Examples 3.11 and 3.12: reached T with a clean status word
     for leg, T in (("double_mach", 0.2), ("forward_step", 4.0)):
         r_ = d[leg]
