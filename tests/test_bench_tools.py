@@ -79,3 +79,7 @@ def test_kernel_sha_of_the_built_library_is_stable():
     # another kernel family hashes differently, an unknown prefix finds nothing
     assert bench.kernel_sha("_ZN5hweno9k_adjointI") not in (a, "unknown")
     assert bench.kernel_sha("_ZN5hweno_no_such_kernel") == "unknown"
+    # the default key covers exactly the 2D Euler stage kernels of both precisions
+    assert bench.kernel_sha(bench.STAGE_2D_EULER) == a
+    assert bench.kernel_sha(bench.STAGE_2D_EULER[0]) not in (a, "unknown")
+    assert bench.kernel_sha("_ZN5hweno7k_stageI") not in (a, "unknown")
