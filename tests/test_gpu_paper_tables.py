@@ -201,9 +201,10 @@ def test_linear_advection_converges_at_fifth_order():
     assert errs[400][0] < 1e-10, errs[400]
 
 
-@pytest.mark.parametrize("case", ["table1", "table2", "table3", "table4"])
+@pytest.mark.parametrize("case", ["table1", "table2", "table3", "table4", "table5"])
 def test_accuracy_runs_match_the_oracle_whole(case):
-    """The accuracy runs behind Tables 1-4 at N = 20, whole, against the oracle's own runs
+    """The accuracy runs behind Tables 1-5 at N = 20 (Table 5 without the limiter), whole,
+    against the oracle's own runs
     with the same time-step rule (device speeds and steps on the GPU, the oracle's on the
     CPU, the last step clipped at T): the same number of steps and every cell of every
     field within 1e-12 (smooth data: rounding does not grow)."""
@@ -213,11 +214,12 @@ def test_accuracy_runs_match_the_oracle_whole(case):
     announce(case, "N = 20 whole run against the oracle")
     cfl = 0.6 * w.dx ** (2.0 / 3.0)
     S = P.to_gpu(w, torch.float64)
-    st = h.Stepper(P.gpu_problem(w, torch.float64, cfl=cfl))
+    st = h.Stepper(P.gpu_problem(w, torch.float64, cfl=cfl, limiter_on=lim))
     while st.t < T * (1 - 1e-13):
         st.steps(S, 256, t_end=T)
         assert st.status & ~h.hweno.ST_SKIPPED == 0, st.status
-    ref, steps = o.run(P.exact_input(P.to_gpu(w, torch.float64)), P.oracle_problem(w, cfl=cfl), T)
+    ref, steps = o.run(P.exact_input(P.to_gpu(w, torch.float64)),
+                       P.oracle_problem(w, cfl=cfl, limiter_on=lim), T)
     assert int(st.ctrl[9]) == steps, (int(st.ctrl[9]), steps)
     errs = P.step_errors(S, ref, w)
     print(f"[{case} N = 20, {steps} steps]", {k: f"{v:.1e}" for k, v in errs.items()}, flush=True)
