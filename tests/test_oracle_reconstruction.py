@@ -114,6 +114,22 @@ def test_nonlinear_weights_sum_to_one_and_are_positive():
     assert all((x > 0).all() for x in w)
 
 
+def test_nonlinear_weights_see_each_indicator_plus_epsilon():
+    """In the weights of Section 2.1 (eq. tau-fh and the normalised bar-omega) an
+    indicator enters only as beta_l + eps, and tau only through differences of
+    indicators; so raising every beta_l by s and lowering eps by s changes no weight.
+    Indicators near eps, where eps matters, on three weight sets."""
+    g = torch.Generator().manual_seed(5)
+    eps = 1e-6
+    b = 10.0 ** (torch.rand(3, 2000, generator=g, dtype=torch.float64) * 4 - 8)   # 1e-8..1e-4
+    for lin in ((0.98, 0.01, 0.01), (0.5, 0.3, 0.2), (0.1, 0.45, 0.45)):
+        w = o.nonlinear_weights(b[0], b[1], b[2], lin, eps)
+        for shift in (2e-7, 7e-7):
+            v = o.nonlinear_weights(b[0] + shift, b[1] + shift, b[2] + shift, lin, eps - shift)
+            for x, y in zip(w, v):
+                assert torch.allclose(x, y, rtol=1e-12, atol=0), (lin, shift)
+
+
 def test_mirror_reconstruction_is_reflection():
     """f-hat^- from data at i..i+2 equals the '+' value of the reflected data (Section 2.1)."""
     rnd = random.Random(11)
