@@ -119,6 +119,12 @@ MUTANTS = [
     ("rk3_stage3_weights", "S3 = keep(H0 / 3.0 + 2.0 / 3.0 * (", "S3 = keep(H0 / 2.0 + 1.0 / 2.0 * (", 1),
     ("rk3_stage2_unlimited", "hat(S1, prob, t1)", "S1", 1),
     ("stage_times", "t1, t2 = t + dt, t + 0.5 * dt", "t1, t2 = t + dt, t + dt", 1),
+    ("rk3_stage3_unlimited", "hat(S2, prob, t2) + dt", "S2 + dt", 1),
+    ("cfl_1d_halved", "return prob.cfl * prob.dx / alpha[0]", "return 0.5 * prob.cfl * prob.dx / alpha[0]", 1),
+    ("roe_enthalpy_unweighted", "H = (sL * HL + sR * HR) / (sL + sR)", "H = 0.5 * (HL + HR)", 1),
+    ("mixed_first_sign", "mixed = (-at(AT, 0) + 7.0 * at(AT, 1)", "mixed = (at(AT, 0) + 7.0 * at(AT, 1)", 1),
+    ("eps_in_tau", "tau = 0.25 * ((b0 - b1).abs() + (b0 - b2).abs()) ** 2",
+     "tau = 0.25 * ((b0 - b1).abs() + (b0 - b2).abs()) ** 2 + eps", 1),
 ]
 
 COPY = ["oracle", "tests", "hweno_inputs", "paper_2207_05258_amd", "pytest.ini"]
