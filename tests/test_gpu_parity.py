@@ -434,6 +434,54 @@ def test_multi_step_call_equals_single_steps(case, dtype, kw):
         assert sb.status & h.hweno.ST_SKIPPED and float(sb.ctrl[7]) == pytest.approx(t_end)
 
 
+@pytest.mark.parametrize("n", [4000, 70000], ids=["16-tiles", "275-tiles"])
+def test_1d_step_end_bookkeeping(n):
+    """The control block and the tapes of 1D steps hold what a step defines: t is the
+    running sum of the taped time steps, the step count counts the steps taken, each
+    record's stage-1 speeds are the global speeds of the state the step started from
+    (Section 2.1), a skipped step (t_end reached) keeps the state, multi-step calls
+    equal single steps bitwise, and the first step is the oracle's."""
+    w = hi.euler1d_piecewise(n, 0)
+    announce("1D step end", n)
+    prob = P.gpu_problem(w, torch.float64)
+    A, B = P.to_gpu(w, torch.float64), P.to_gpu(w, torch.float64)
+    probe = h.Stepper(prob)
+    Sp = P.to_gpu(w, torch.float64)
+    probe.step(Sp)
+    t_end = float(probe.t) * 3.5          # one clipped step, then skipped ones
+    steps = 6
+    sa, sb = h.Stepper(prob), h.Stepper(prob)
+    ta = torch.zeros(steps, h.CTRL_LEN, dtype=torch.float64, device="cuda")
+    tb = torch.zeros_like(ta)
+    starts = []
+    for q in range(steps):
+        starts.append(A.clone())
+        sa.step(A, t_end=t_end, tape=ta[q])
+    sb.steps(B, steps, t_end=t_end, tapes=tb)
+    torch.cuda.synchronize()
+    assert torch.equal(A, B)
+    assert torch.equal(sa.ctrl[:10], sb.ctrl[:10])
+    assert torch.equal(ta[:, :10], tb[:, :10])
+    tape = ta.cpu().numpy()
+    t, taken = 0.0, 0
+    for q in range(steps):
+        speeds = h.alpha(starts[q], prob).cpu().numpy()
+        assert np.array_equal(tape[q, 0:2], speeds), (q, tape[q, 0:2], speeds)
+        dtq = tape[q, 6]
+        if dtq > 0:
+            t += dtq
+            taken += 1
+        else:
+            assert torch.equal(starts[q + 1] if q + 1 < steps else A, starts[q]), q
+        assert tape[q, 7] == t and tape[q, 9] == taken, (q, tape[q])
+    assert taken == 4 and t == pytest.approx(t_end, rel=1e-15)
+    assert sa.status & h.hweno.ST_SKIPPED and sb.status & h.hweno.ST_SKIPPED
+    # the first step against the oracle's, with its own speeds and time step
+    S1, dt1, _ = o.rk3_step(torch.as_tensor(w.S, dtype=torch.float64), P.oracle_problem(w))
+    assert abs(dt1 - tape[0, 6]) <= 1e-14 * dt1
+    P.assert_within(P.step_errors(starts[1], S1, w), 1e-12, f"1D step end n={n}")
+
+
 def test_tape_and_replay_reproduce_the_step():
     w = hi.euler2d_rough(45, 38, 12)
     announce("tape/replay")
