@@ -3,10 +3,11 @@
 pin fail.  The mutants are dropped or swapped terms, wrong signs, indices, coefficients and
 transposed operands in each part of the oracle: the Hermite values, the quintic's
 coefficients, the smoothness indicators and nonlinear weights (Section 2.1), the mirrored
-"-" reconstruction, the linear derivative fluxes, the limiter (Section 2.2), the Euler flux,
-its chain-rule products, the Roe average and eigenvectors (Remarks 2.1/2.2), the splitting,
-the mixed flux (eq. mixed), the flux differences (eqs. odeH/ode2H), the ghost cells, the
-speeds, the time step and SSP-RK3.  Each runs in a copy of the repository in a temporary
+"-" reconstruction, the linear derivative fluxes, the limiter (Section 2.2) and its switch,
+the Euler and scalar fluxes, their chain-rule products and speeds, the Roe average and
+eigenvectors (Remarks 2.1/2.2), the splitting, the mixed flux (eq. mixed), the flux
+differences (eqs. odeH/ode2H), the ghost cells and the obstacle, the time step, SSP-RK3 and
+the clipped last step.  Each runs in a copy of the repository in a temporary
 directory; nothing here touches the HIP path.
 
     python tests/oracle_mutants.py            # all mutants, four at a time
@@ -125,6 +126,21 @@ MUTANTS = [
     ("mixed_first_sign", "mixed = (-at(AT, 0) + 7.0 * at(AT, 1)", "mixed = (at(AT, 0) + 7.0 * at(AT, 1)", 1),
     ("eps_in_tau", "tau = 0.25 * ((b0 - b1).abs() + (b0 - b2).abs()) ** 2",
      "tau = 0.25 * ((b0 - b1).abs() + (b0 - b2).abs()) ** 2 + eps", 1),
+    # scalar laws, the limiter's driver, the obstacle, the run loop
+    ("burgers_flux_not_halved", "return 0.5 * U * U", "return U * U", 1),
+    ("burgers_jvp_without_u", "        return U * D\n", "        return D\n", 1),
+    ("linadv_jvp_x_speed_only", "return self.prob.adv_speed[d] * D", "return self.prob.adv_speed[0] * D", 1),
+    ("linadv_speed_signed", "abs(self.prob.adv_speed[d])", "self.prob.adv_speed[d]", 1),
+    ("char_limiter_left_is_right", "Li = torch.linalg.inv(R)", "Li = R", 1),
+    ("limiter_y_with_dx", "along(W, 1, prob.bc_y, prob.dy)", "along(W, 1, prob.bc_y, prob.dx)", 1),
+    ("limiter_switch_ignored", "    if not prob.limiter_on:\n        return S\n", "", 1),
+    ("obstacle_top_mirror_off_by_one", "(2 * j_s - 1 - jj)", "(2 * j_s - jj)", 1),
+    ("obstacle_solid_columns", "m[:j_s, i_s:] = True", "m[:j_s, i_s + 1:] = True", 1),
+    ("wall_tangential_derivative_flipped", "return pu, [-q for q in pu], pu",
+     "return pu, [-q for q in pu], [-q for q in pu]", 1),
+    ("solid_cells_not_kept", "return torch.where(solid, S, X) if prob.obstacle is not None else X",
+     "return X", 1),
+    ("last_step_not_clipped", "dt = min(dt, t_end - t)", "dt = dt", 1),
 ]
 
 COPY = ["oracle", "tests", "hweno_inputs", "paper_2207_05258_amd", "pytest.ini"]

@@ -222,6 +222,38 @@ def test_2d_reduces_to_1d_for_y_independent_data():
     assert float(L2[8:].abs().max()) < 1e-12
 
 
+@pytest.mark.parametrize("d", [0, 1], ids=["x-only", "y-only"])
+def test_2d_linear_advection_reduces_to_1d_along_each_direction(d):
+    """u_t + a_x u_x + a_y u_y = 0 with data that vary along direction d only: the 2D
+    operator (eqs. odeH, ode2H) and step equal the 1D ones along d with that direction's
+    speed, on (u, derivative along d); the derivative across d stays zero."""
+    n, other, a = 28, 5, (0.7, -1.3)
+    h = (0.05, 0.08)
+    g = torch.Generator().manual_seed(11)
+    u, v = torch.rand(2, n, dtype=torch.float64, generator=g) * 2.0 - 1.0
+    p1 = o.Problem(dim=1, physics="linadv", dx=h[d], adv_speed=(a[d], 0.0))
+    p2 = o.Problem(dim=2, physics="linadv", dx=h[0], dy=h[1], adv_speed=a)
+    S1 = torch.stack([u, v]).view(2, 1, n)
+    shape = (other, n) if d == 0 else (n, other)
+
+    def spread(x):
+        return (x.view(1, n) if d == 0 else x.view(n, 1)).expand(shape)
+    zero = torch.zeros(shape, dtype=torch.float64)
+    S2 = torch.stack([spread(u), spread(v), zero] if d == 0 else [spread(u), zero, spread(v)])
+
+    def back(X2, f):   # the 1D profile of field f of a 2D result
+        return X2[f, 0, :] if d == 0 else X2[f, :, 0]
+    L1, L2 = o.rhs(S1, p1), o.rhs(S2, p2)
+    across = 2 if d == 0 else 1
+    along = 1 + d
+    scale = float(L1.abs().max())
+    for X2, X1 in ((L2, L1),) + ((o.rk3_step(S2, p2, dt=0.01)[0], o.rk3_step(S1, p1, dt=0.01)[0]),):
+        assert torch.allclose(X2[0], spread(X1[0, 0]), rtol=0, atol=1e-13 * scale)
+        assert torch.allclose(X2[along], spread(X1[1, 0]), rtol=0, atol=1e-13 * scale)
+        assert float(X2[across].abs().max()) <= 1e-13 * scale
+        assert torch.allclose(back(X2, 0), X1[0, 0], rtol=0, atol=1e-13 * scale)
+
+
 def test_characteristic_equals_componentwise_with_linear_weights():
     """With omega forced to gamma the reconstruction is linear, so projection commutes."""
     w = hi.euler2d_rough(10, 8, 11, bc=hi.PERIODIC)
