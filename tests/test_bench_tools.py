@@ -83,3 +83,17 @@ def test_kernel_sha_of_the_built_library_is_stable():
     assert bench.kernel_sha(bench.STAGE_2D_EULER) == a
     assert bench.kernel_sha(bench.STAGE_2D_EULER[0]) not in (a, "unknown")
     assert bench.kernel_sha("_ZN5hweno7k_stageI") not in (a, "unknown")
+
+
+@pytest.mark.parametrize("argv,env", [(["--gpus", "2"], {}), (["--gpus", "1"], {"WORLD_SIZE": "4"})])
+def test_bench_refuses_more_than_one_gpu_with_a_message(argv, env):
+    """The path runs on one GPU: asked for more (by flag or by a launcher's WORLD_SIZE),
+    bench.py exits with status 2 and says so before touching a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py")] + argv, cwd=root,
+                       env=dict(os.environ, **env), capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2, (r.returncode, r.stdout, r.stderr)
+    assert "one GPU" in (r.stdout + r.stderr)
+    assert r.stdout.strip() == "" or not r.stdout.strip().startswith("{")
