@@ -369,6 +369,39 @@ def test_transpose_symmetry_on_the_gpu(bc):
     assert float((ST - _transpose_euler(S)).abs().max()) <= 1e-12 * float(S.abs().max())
 
 
+@pytest.mark.parametrize("d", [0, 1], ids=["x-only", "y-only"])
+def test_2d_linear_advection_along_one_direction_equals_the_1d_kernels(d):
+    """u_t + a_x u_x + a_y u_y = 0 with data that vary along direction d only: the 2D
+    kernels' right-hand side and step equal the 1D kernels' along d with that direction's
+    speed, on (u, derivative along d), and the derivative across d stays zero."""
+    n, other, a, hh = 300, 7, (0.7, -1.3), (0.05, 0.08)
+    announce("2D linear advection along one direction", d)
+    g = torch.Generator().manual_seed(5)
+    u, v = (torch.rand(2, n, dtype=torch.float64, generator=g) * 2.0 - 1.0).cuda()
+    ny, nx = (other, n) if d == 0 else (n, other)
+    p1 = h.Problem(dim=1, nx=n, physics="linadv", dx=hh[d], adv_speed=(a[d], 0.0))
+    p2 = h.Problem(dim=2, nx=nx, ny=ny, physics="linadv", dx=hh[0], dy=hh[1], adv_speed=a)
+
+    def spread(x):
+        return (x.view(1, n) if d == 0 else x.view(n, 1)).expand(ny, nx)
+    zero = torch.zeros(ny, nx, dtype=torch.float64, device="cuda")
+    S1 = torch.stack([u, v]).view(2, 1, n).contiguous()
+    S2 = torch.stack([spread(u), spread(v), zero] if d == 0 else
+                     [spread(u), zero, spread(v)]).contiguous()
+    along, across = 1 + d, 2 - d
+    L1, L2 = h.rhs(S1, p1), h.rhs(S2, p2)
+    st1, st2 = h.Stepper(p1), h.Stepper(p2)
+    T1, T2 = S1.clone(), S2.clone()
+    st1.step(T1, dt=0.01)
+    st2.step(T2, dt=0.01)
+    torch.cuda.synchronize()
+    for X1, X2 in ((L1, L2), (T1, T2)):
+        scale = float(X1.abs().max())
+        assert float((X2[0] - spread(X1[0, 0])).abs().max()) <= 1e-13 * scale
+        assert float((X2[along] - spread(X1[1, 0])).abs().max()) <= 1e-13 * scale
+        assert float(X2[across].abs().max()) <= 1e-13 * scale
+
+
 def test_graph_replay_after_a_state_reset_repeats_itself():
     """Resetting the state and the control block between replays of one captured graph
     gives the same result every time (nothing is cached across replays)."""
