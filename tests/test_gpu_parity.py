@@ -402,6 +402,39 @@ def test_2d_linear_advection_along_one_direction_equals_the_1d_kernels(d):
         assert float(X2[across].abs().max()) <= 1e-13 * scale
 
 
+def test_2d_euler_with_x_only_data_equals_the_1d_kernels():
+    """2D Euler data that do not depend on y and have no y-momentum: the 2D kernels'
+    right-hand side and step (characteristic reconstruction, limiter) equal the 1D
+    kernels' on (rho, m_x, E) and their x-derivatives, to rounding; the y-momentum and
+    every y-derivative stay zero."""
+    n, ny = 300, 6
+    announce("2D Euler with x-only data")
+    w1 = hi.euler1d_piecewise(n, 9)
+    g = torch.Generator().manual_seed(3)
+    S1c = torch.as_tensor(w1.S, dtype=torch.float64).clone()
+    S1c[3:] = 0.3 * torch.randn(3, 1, n, dtype=torch.float64, generator=g)
+    S1 = S1c.cuda().contiguous()
+    z = torch.zeros_like(S1[0])
+    U = torch.stack([S1[0], S1[1], z, S1[2]]).expand(4, ny, n)
+    V = torch.stack([S1[3], S1[4], z, S1[5]]).expand(4, ny, n)
+    S2 = torch.cat([U, V, torch.zeros_like(U)]).contiguous()
+    p1 = h.Problem(dim=1, nx=n, physics="euler", dx=w1.dx)
+    p2 = h.Problem(dim=2, nx=n, ny=ny, physics="euler", dx=w1.dx, dy=0.3)
+    L1, L2 = h.rhs(S1, p1), h.rhs(S2, p2)
+    st1, st2 = h.Stepper(p1), h.Stepper(p2)
+    T1, T2 = S1.clone(), S2.clone()
+    st1.step(T1, dt=2e-4)
+    st2.step(T2, dt=2e-4)
+    torch.cuda.synchronize()
+    for X1, X2, what in ((L1, L2, "rhs"), (T1, T2, "step")):
+        for f1, f2 in ((0, 0), (1, 1), (2, 3), (3, 4), (4, 5), (5, 7)):
+            scale = max(float(X1[f1 % 3].abs().max()), float(X1[f1].abs().max()))
+            err = float((X2[f2] - X1[f1, 0].expand(ny, n)).abs().max())
+            assert err <= 1e-12 * scale, (what, f1, err, scale)
+        assert float(X2[[2, 6]].abs().max()) <= 1e-13 * float(X1.abs().max()), what
+        assert float(X2[8:].abs().max()) <= 1e-13 * float(X1.abs().max()), what
+
+
 def test_graph_replay_after_a_state_reset_repeats_itself():
     """Resetting the state and the control block between replays of one captured graph
     gives the same result every time (nothing is cached across replays)."""
