@@ -369,18 +369,20 @@ def test_transpose_symmetry_on_the_gpu(bc):
     assert float((ST - _transpose_euler(S)).abs().max()) <= 1e-12 * float(S.abs().max())
 
 
+@pytest.mark.parametrize("physics", ["linadv", "burgers"])
 @pytest.mark.parametrize("d", [0, 1], ids=["x-only", "y-only"])
-def test_2d_linear_advection_along_one_direction_equals_the_1d_kernels(d):
-    """u_t + a_x u_x + a_y u_y = 0 with data that vary along direction d only: the 2D
-    kernels' right-hand side and step equal the 1D kernels' along d with that direction's
-    speed, on (u, derivative along d), and the derivative across d stays zero."""
+def test_2d_scalar_law_along_one_direction_equals_the_1d_kernels(d, physics):
+    """u_t + f(u)_x + g(u)_y = 0 (linear advection with a_x != a_y, or Burgers) with data
+    that vary along direction d only: the 2D kernels' right-hand side and step equal the
+    1D kernels' along d with that direction's flux, on (u, derivative along d), and the
+    derivative across d stays zero."""
     n, other, a, hh = 300, 7, (0.7, -1.3), (0.05, 0.08)
-    announce("2D linear advection along one direction", d)
+    announce("2D scalar law along one direction", physics, d)
     g = torch.Generator().manual_seed(5)
     u, v = (torch.rand(2, n, dtype=torch.float64, generator=g) * 2.0 - 1.0).cuda()
     ny, nx = (other, n) if d == 0 else (n, other)
-    p1 = h.Problem(dim=1, nx=n, physics="linadv", dx=hh[d], adv_speed=(a[d], 0.0))
-    p2 = h.Problem(dim=2, nx=nx, ny=ny, physics="linadv", dx=hh[0], dy=hh[1], adv_speed=a)
+    p1 = h.Problem(dim=1, nx=n, physics=physics, dx=hh[d], adv_speed=(a[d], 0.0))
+    p2 = h.Problem(dim=2, nx=nx, ny=ny, physics=physics, dx=hh[0], dy=hh[1], adv_speed=a)
 
     def spread(x):
         return (x.view(1, n) if d == 0 else x.view(n, 1)).expand(ny, nx)
